@@ -1,0 +1,345 @@
+"""CPU FP64 oracle for the matrix-free ILU(0) smoother (arXiv:2210.15280).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product library.  The heavy loops
+live in plain C (ilu_oracle.c, built with -ffp-contract=off); the surrogate
+least-squares fit uses numpy/scipy library primitives.
+
+Functions and the passage they follow:
+  interior_points, index_of   Sec. 2.1 logical coordinates, lexicographic order
+  assemble, apply              Sec. 2.1 bilinear form and stencil matvec
+  ilu0                         Sec. 3 definition of ILU(0) (IKJ on CSR)
+  ilu0_stencil                 Sec. 3 stencil equations / Alg. 1
+  smooth                       Sec. 2.1 Richardson smoother with C = L D L^T
+  smooth_stencil(_f32)         Alg. 2 (variant V2), FP64 / FP32-mixed
+  sample_set, fit_surrogate    Sec. 4.1 sample sets S_d and LSQ fit
+  eval_surrogate               Sec. 4.1 surrogate polynomials
+  asymptotic_stencil           Sec. 3 Gauss-Seidel iteration of the stencil equations
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from math import comb
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ilu_oracle.c")
+_LIB = os.path.join(_HERE, "libilu_oracle.so")
+
+# Paper listing order of D (Sec. 2.1); the first 7 are D_l, 7 is c, 8+k = -D_l[k].
+DIRS = np.array([(-1, 0, 0), (0, -1, 0), (1, -1, 0), (-1, 1, -1), (0, 1, -1), (0, 0, -1), (1, 0, -1),
+                 (0, 0, 0),
+                 (1, 0, 0), (0, 1, 0), (-1, 1, 0), (1, -1, 1), (0, -1, 1), (0, 0, 1), (-1, 0, 1)])
+DIR_NAMES = ("w", "s", "se", "bnw", "bn", "bc", "be", "c", "e", "n", "nw", "tse", "ts", "tc", "tw")
+NLOW = 7
+CENTRE = 7
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        i64, i32, dbl, p = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+        lib.oracle_num_interior.restype = i64
+        lib.oracle_num_interior.argtypes = [i32]
+        lib.oracle_interior_points.argtypes = [i32, p]
+        lib.oracle_index_of.argtypes = [i32, i64, p, p]
+        lib.oracle_element_stiffness.restype = dbl
+        lib.oracle_element_stiffness.argtypes = [p, dbl, p]
+        lib.oracle_assemble.restype = i64
+        lib.oracle_assemble.argtypes = [p, i32, i32, p, p, p]
+        lib.oracle_apply.argtypes = [i64, p, p, p, p]
+        lib.oracle_ilu0_csr_inplace.restype = i64
+        lib.oracle_ilu0_csr_inplace.argtypes = [i64, p, p, p]
+        lib.oracle_ilu0_csr.restype = i64
+        lib.oracle_ilu0_csr.argtypes = [i64, p, p, p, p, p]
+        lib.oracle_ilu0_stencil.restype = i64
+        lib.oracle_ilu0_stencil.argtypes = [i32, p, p, p, p]
+        lib.oracle_smooth_csr.argtypes = [i64, p, p, p, p, p, p, i32, p]
+        lib.oracle_smooth_stencil.argtypes = [i64, p, p, p, p, p, p, i32, p]
+        lib.oracle_smooth_stencil_f32.argtypes = [i64, p, p, p, p, p, p, i32, p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def num_interior(level: int) -> int:
+    return comb((1 << level) - 1, 3)
+
+
+def interior_points(level: int) -> np.ndarray:
+    """(N,3) int32 interior coordinates in lexicographic order (z, then y, then x)."""
+    out = np.zeros((num_interior(level), 3), dtype=np.int32)
+    _L().oracle_interior_points(level, _ptr(out))
+    return out
+
+
+def index_of(level: int, xyz) -> np.ndarray:
+    xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros(len(xyz), dtype=np.int64)
+    _L().oracle_index_of(level, len(xyz), _ptr(xyz), _ptr(out))
+    return out
+
+
+def element_stiffness(P, kappa: float = 1.0):
+    P = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(12))
+    K = np.zeros(16)
+    det = _L().oracle_element_stiffness(_ptr(P), float(kappa), _ptr(K))
+    return K.reshape(4, 4), det
+
+
+class Problem:
+    """Assembled restricted operator of one macro-tetrahedron (stencil form)."""
+
+    def __init__(self, verts, level: int, coeff_kind: int = 0, coeff_params=(1.0, 0, 0, 0)):
+        self.verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64).reshape(12))
+        self.level = int(level)
+        self.n = 1 << level
+        self.N = num_interior(level)
+        self.coeff_kind = int(coeff_kind)
+        self.params = np.ascontiguousarray(np.asarray(tuple(coeff_params) + (0.0,) * (4 - len(coeff_params)),
+                                                      dtype=np.float64))
+        self.A = np.zeros((self.N, 15))
+        self.col = np.zeros((self.N, 15), dtype=np.int64)
+        self.ntets = _L().oracle_assemble(_ptr(self.verts), self.level, self.coeff_kind, _ptr(self.params),
+                                          _ptr(self.A), _ptr(self.col))
+        if self.ntets < 0:
+            raise RuntimeError("assembly failed")
+
+    @classmethod
+    def from_tet(cls, tet):
+        return cls(tet.verts, tet.level, tet.coeff_kind, tet.coeff_params)
+
+    def apply(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros(self.N)
+        _L().oracle_apply(self.N, _ptr(self.A), _ptr(self.col), _ptr(x), _ptr(y))
+        return y
+
+    def csr(self):
+        """Restricted matrix as a scipy CSR matrix (structural pattern kept)."""
+        import scipy.sparse as sp
+        m = self.col >= 0
+        rows = np.repeat(np.arange(self.N), 15).reshape(self.N, 15)[m]
+        A = sp.csr_matrix((self.A[m], (rows, self.col[m])), shape=(self.N, self.N))
+        A.sort_indices()
+        return A
+
+    # -------------------------------------------------------------- ILU(0)
+    def ilu0(self):
+        """ILU(0) by the definition: returns (L (N,7), U (N,7 upper), D (N,))."""
+        L = np.zeros((self.N, 7)); U = np.zeros((self.N, 7)); D = np.zeros(self.N)
+        rc = _L().oracle_ilu0_csr(self.N, _ptr(self.A), _ptr(self.col), _ptr(L), _ptr(U), _ptr(D))
+        if rc != 0:
+            raise ArithmeticError("ILU(0) zero pivot (code %d)" % rc)
+        return L, U, D
+
+    def ilu0_stencil(self):
+        """ILU(0) from the stencil equations (Alg. 1 order): (L (N,7), D (N,), breakdown)."""
+        L = np.zeros((self.N, 7)); D = np.zeros(self.N)
+        bad = _L().oracle_ilu0_stencil(self.level, _ptr(self.A), _ptr(self.col), _ptr(L), _ptr(D))
+        return L, D, int(bad)
+
+    # ------------------------------------------------------ smoothing steps
+    def smooth(self, L, D, b, x0=None, nsweeps=1):
+        """x <- x + (L D L^T)^{-1}(b - A x), nsweeps times (matrix form).  Returns (x, relres)."""
+        x = np.zeros(self.N) if x0 is None else np.array(x0, dtype=np.float64)
+        rel = np.zeros(nsweeps + 1)
+        _L().oracle_smooth_csr(self.N, _ptr(self.A), _ptr(self.col), _ptr(np.ascontiguousarray(L)),
+                               _ptr(np.ascontiguousarray(D)), _ptr(np.ascontiguousarray(b, dtype=np.float64)),
+                               _ptr(x), int(nsweeps), _ptr(rel))
+        return x, rel
+
+    def smooth_stencil(self, Lw, Dinv, b, x0=None, nsweeps=1):
+        """Alg. 2 (V2) with per-point weights Lw (N,7) and Dinv (N,).  Returns (x, relres)."""
+        x = np.zeros(self.N) if x0 is None else np.array(x0, dtype=np.float64)
+        rel = np.zeros(nsweeps + 1)
+        _L().oracle_smooth_stencil(self.N, _ptr(self.A), _ptr(self.col),
+                                   _ptr(np.ascontiguousarray(Lw, dtype=np.float64)),
+                                   _ptr(np.ascontiguousarray(Dinv, dtype=np.float64)),
+                                   _ptr(np.ascontiguousarray(b, dtype=np.float64)), _ptr(x), int(nsweeps),
+                                   _ptr(rel))
+        return x, rel
+
+    def smooth_stencil_f32(self, Lw, Dinv, b, x0=None, nsweeps=1):
+        """Alg. 2 with FP64 residual, FP32 weights and substitutions, FP64 update."""
+        x = np.zeros(self.N) if x0 is None else np.array(x0, dtype=np.float64)
+        rel = np.zeros(nsweeps + 1)
+        _L().oracle_smooth_stencil_f32(self.N, _ptr(self.A), _ptr(self.col),
+                                       _ptr(np.ascontiguousarray(Lw, dtype=np.float32)),
+                                       _ptr(np.ascontiguousarray(Dinv, dtype=np.float32)),
+                                       _ptr(np.ascontiguousarray(b, dtype=np.float64)), _ptr(x), int(nsweeps),
+                                       _ptr(rel))
+        return x, rel
+
+
+def ilu0_csr_inplace(rowptr, colind, val):
+    """Generic IKJ ILU(0) on any CSR matrix with sorted columns (in place)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colind = np.ascontiguousarray(colind, dtype=np.int64)
+    val = np.ascontiguousarray(val, dtype=np.float64).copy()
+    rc = _L().oracle_ilu0_csr_inplace(len(rowptr) - 1, _ptr(rowptr), _ptr(colind), _ptr(val))
+    if rc != 0:
+        raise ArithmeticError("zero pivot")
+    return val
+
+
+# ---------------------------------------------------------------- surrogates
+
+def sample_shift(d) -> np.ndarray:
+    """Offset of S_d: 1 - min(d, 0) componentwise (Sec. 4.1, reading of the
+    garbled shift; puts the first sample where p + d is interior)."""
+    d = np.asarray(d)
+    return 1 - np.minimum(d, 0)
+
+
+def sample_side(level: int, d, stride: int) -> int:
+    """Side M of the lattice simplex {k >= 0, sum k <= M} that S_d maps to."""
+    n = 1 << level
+    d = np.asarray(d)
+    room = n - 1 - max(0, int(d.sum())) - int(sample_shift(d).sum())
+    return room // stride if room >= 0 else -1
+
+
+def effective_stride(level: int, degree, stride: int) -> int:
+    """Largest s in {stride, stride/2, ..., 1} for which every S_d is unisolvent
+    for P_{dx,dy,dz} (a lattice simplex of side M is unisolvent iff
+    M >= dx + dy + dz); 0 if none is."""
+    dg = (degree,) * 3 if np.isscalar(degree) else tuple(degree)
+    need = sum(dg)
+    s = stride
+    while s >= 1:
+        if all(sample_side(level, DIRS[t], s) >= need for t in list(range(NLOW)) + [CENTRE]):
+            return s
+        s //= 2
+    return 0
+
+
+def sample_set(level: int, slot: int, stride: int) -> np.ndarray:
+    """Interior indices of S_d: p interior, p = shift_d (mod stride), p + d interior."""
+    pts = interior_points(level).astype(np.int64)
+    d = DIRS[slot]
+    sh = sample_shift(d)
+    m = np.all((pts - sh) % stride == 0, axis=1)
+    q = pts + d
+    n = 1 << level
+    m &= np.all(q >= 1, axis=1) & (q.sum(axis=1) <= n - 1)
+    return np.nonzero(m)[0]
+
+
+def legendre_tensor_matrix(Xhat: np.ndarray, degree) -> np.ndarray:
+    """Columns P_i(2x-1) P_j(2y-1) P_k(2z-1), column index (k (dy+1) + j)(dx+1) + i."""
+    from numpy.polynomial import legendre as lg
+    dx, dy, dz = (degree,) * 3 if np.isscalar(degree) else degree
+    px = lg.legvander(2 * Xhat[:, 0] - 1, dx)
+    py = lg.legvander(2 * Xhat[:, 1] - 1, dy)
+    pz = lg.legvander(2 * Xhat[:, 2] - 1, dz)
+    return (pz[:, :, None, None] * py[:, None, :, None] * px[:, None, None, :]).reshape(len(Xhat), -1)
+
+
+def monomial_tensor_matrix(Xhat: np.ndarray, degree) -> np.ndarray:
+    """Columns x^i y^j z^k (the paper's basis), same column order."""
+    dx, dy, dz = (degree,) * 3 if np.isscalar(degree) else degree
+    px = np.vander(Xhat[:, 0], dx + 1, increasing=True)
+    py = np.vander(Xhat[:, 1], dy + 1, increasing=True)
+    pz = np.vander(Xhat[:, 2], dz + 1, increasing=True)
+    return (pz[:, :, None, None] * py[:, None, :, None] * px[:, None, None, :]).reshape(len(Xhat), -1)
+
+
+def lsq(V: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """Least squares by column-pivoted Householder QR (LAPACK geqp3)."""
+    import scipy.linalg as sla
+    Q, R, piv = sla.qr(V, mode="economic", pivoting=True)
+    c = np.zeros(V.shape[1])
+    c[piv] = sla.solve_triangular(R, Q.T @ y)
+    return c
+
+
+def fit_surrogate(level: int, L: np.ndarray, D: np.ndarray, degree, stride: int, basis: str = "legendre"):
+    """One polynomial per d in D_l (fit to L^p_d) and one for c (fit to 1/D^p),
+    each on its sample set S_d with coordinates X^ = (x,y,z)/2^L (Sec. 4.1 and
+    the sampling step of Alg. 1).  Returns coeffs (8, K): rows 0..6 = D_l, 7 = c."""
+    pts = interior_points(level).astype(np.float64) / (1 << level)
+    mat = legendre_tensor_matrix if basis == "legendre" else monomial_tensor_matrix
+    out = []
+    for t in list(range(NLOW)) + [CENTRE]:
+        idx = sample_set(level, t, stride)
+        y = L[idx, t] if t < NLOW else 1.0 / D[idx]
+        out.append(lsq(mat(pts[idx], degree), y))
+    return np.array(out)
+
+
+def eval_surrogate(level: int, coeffs: np.ndarray, degree, basis: str = "legendre"):
+    """Surrogate weights at every interior point: Lw (N,7) and Dinv (N,).
+    V2 zeroing of weights whose neighbour is not interior happens inside the
+    sweep (it multiplies a boundary value that is never read)."""
+    pts = interior_points(level).astype(np.float64) / (1 << level)
+    mat = legendre_tensor_matrix if basis == "legendre" else monomial_tensor_matrix
+    vals = mat(pts, degree) @ coeffs.T
+    return np.ascontiguousarray(vals[:, :NLOW]), np.ascontiguousarray(vals[:, NLOW])
+
+
+def surrogate_error(level: int, L, D, Lw, Dinv):
+    """Per-direction relative discrete L2 error and max-abs error over the
+    points whose neighbour p + d is interior (for c: all points, on 1/D)."""
+    n = 1 << level
+    pts = interior_points(level).astype(np.int64)
+    rel, mx = [], []
+    for t in range(NLOW):
+        q = pts + DIRS[t]
+        m = np.all(q >= 1, axis=1) & (q.sum(axis=1) <= n - 1)
+        e = Lw[m, t] - L[m, t]
+        rel.append(np.linalg.norm(e) / max(np.linalg.norm(L[m, t]), 1e-300))
+        mx.append(np.abs(e).max() if e.size else 0.0)
+    e = Dinv - 1.0 / D
+    rel.append(np.linalg.norm(e) / np.linalg.norm(1.0 / D))
+    mx.append(np.abs(e).max())
+    return np.array(rel), np.array(mx)
+
+
+# --------------------------------------------------------------- asymptotics
+
+def asymptotic_stencil(Ad, iters: int = 20000, tol: float = 1e-15):
+    """Gauss-Seidel iteration of the stencil equations with a constant stencil
+    A_d (Sec. 3): start from L_c = D_c = 1 and L_d = 0, sweep the equations in
+    the order bc, s, bnw, be, w, bn, se, c, with every neighbour value equal
+    to the current iterate.  Returns (L (7,), D)."""
+    Ad = np.asarray(Ad, dtype=np.float64)
+    L = np.zeros(7)
+    D = 1.0
+    lower = {tuple(DIRS[t]): t for t in range(NLOW)}
+    order = (5, 1, 3, 6, 0, 4, 2)
+    for _ in range(iters):
+        Lold, Dold = L.copy(), D
+        for d in order:
+            acc = Ad[d]
+            for dt in range(NLOW):
+                if dt == d:
+                    continue
+                e = lower.get(tuple(DIRS[dt] - DIRS[d]))
+                if e is not None:
+                    acc -= L[dt] * D * L[e]
+            L[d] = acc / D
+        D = Ad[CENTRE] - D * np.sum(L * L)
+        if np.max(np.abs(L - Lold)) < tol and abs(D - Dold) < tol * abs(D):
+            break
+    return L, D

@@ -1,0 +1,369 @@
+"""Pins for the CPU oracle: every check compares the oracle with something
+other than itself -- a closed form, an invariant of the P1 bilinear form, an
+independent library routine (dense Cholesky, QR), a brute-force count, or a
+value printed in the paper.  No GPU needed."""
+from math import comb
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+import workloads as W
+
+# --------------------------------------------------------------------------- lattice
+
+
+@pytest.mark.parametrize("level", [2, 3, 4, 5, 6])
+def test_interior_count_and_numbering(level):
+    # G-interior = {x,y,z >= 1, x+y+z < 2^L} (Sec. 2.1); brute-force enumeration
+    n = 1 << level
+    brute = [(x, y, z) for z in range(n + 1) for y in range(n + 1) for x in range(n + 1)
+             if x >= 1 and y >= 1 and z >= 1 and x + y + z < n]
+    assert O.num_interior(level) == len(brute) == comb(n - 1, 3)
+    pts = O.interior_points(level)
+    # lexicographic: z slowest, then y, then x (Sec. 2.1 ordering)
+    assert [tuple(p) for p in pts] == sorted(brute, key=lambda p: (p[2], p[1], p[0]))
+    assert np.array_equal(O.index_of(level, pts), np.arange(len(pts)))
+    assert np.all(O.index_of(level, [[0, 1, 1], [1, 1, n - 2], [1, 0, 1]]) == [-1, -1, -1])
+
+
+def test_interior_counts_of_the_workloads():
+    assert O.num_interior(4) == 455
+    assert O.num_interior(7) == 333_375
+    assert O.num_interior(8) == 2_731_135
+    assert O.num_interior(9) == 22_108_415
+    # hyperplanes t = x + 2y + 3z over the interior: 3n - 11 of them
+    for level in (3, 4, 5):
+        pts = O.interior_points(level)
+        t = pts[:, 0] + 2 * pts[:, 1] + 3 * pts[:, 2]
+        assert len(np.unique(t)) == 3 * (1 << level) - 11
+
+
+# ------------------------------------------------------------------------ micro-mesh
+
+
+@pytest.mark.parametrize("level", [2, 3, 4])
+def test_micro_mesh_has_8_to_the_L_tets(level):
+    # uniform 8-subdivision, L times (Sec. 2.1, Bey refinement)
+    assert O.Problem(W.REFERENCE_TET, level).ntets == 8 ** level
+
+
+def test_element_stiffness_against_face_normal_formula():
+    # independent formula: K_ij = (n_i . n_j) / (9 |T|) with n_i the area-weighted
+    # outward normal of the face opposite vertex i (|n_i| = face area)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        P = rng.uniform(-1, 1, size=(4, 3))
+        K, det = O.element_stiffness(P, 2.5)
+        vol = abs(np.linalg.det(P[1:] - P[0])) / 6
+        nrm = []
+        for i in range(4):
+            a, b, c = [P[j] for j in range(4) if j != i]
+            nv = 0.5 * np.cross(b - a, c - a)
+            if np.dot(nv, P[i] - a) > 0:
+                nv = -nv
+            nrm.append(nv)
+        K2 = np.array([[2.5 * np.dot(nrm[i], nrm[j]) / (9 * vol) for j in range(4)] for i in range(4)])
+        np.testing.assert_allclose(K, K2, rtol=1e-12, atol=1e-12 * np.abs(K2).max())
+
+
+# ------------------------------------------------------------------------- assembly
+
+# Closed form, derived by hand for the reference tetrahedron with kappa = 1:
+# in (a,b,c) = (x, x+y, x+y+z) the form is (1/n) int grad(u)^T G grad(v) with
+# G = [[1,1,1],[1,2,2],[1,2,3]] on the Kuhn lattice; e.g. the main diagonal
+# (xyz-direction e) lies in all six Kuhn simplices of one cube and gets
+# -2(G12+G13+G23)/(6n) = -4h/3.  In units of h/3 (h = 2^-L):
+REFERENCE_STENCIL = dict(w=-4, s=-2, se=-1, bnw=1, bn=-1, bc=-4, be=1, c=20,
+                         e=-4, n=-2, nw=-1, tse=1, ts=-1, tc=-4, tw=1)
+
+
+@pytest.mark.parametrize("level", [3, 4, 5])
+def test_reference_tet_closed_form(level):
+    P = O.Problem(W.REFERENCE_TET, level)
+    h = 1.0 / P.n
+    want = np.array([REFERENCE_STENCIL[nm] for nm in O.DIR_NAMES]) * h / 3
+    # every interior point has the full translation-invariant stencil
+    np.testing.assert_allclose(P.A, np.broadcast_to(want, P.A.shape), rtol=0, atol=1e-15)
+
+
+def _jittered(level, kind, params, seed=11):
+    t = W.make_tet(seed, level, kind, params, jitter=0.15)
+    return t, O.Problem.from_tet(t)
+
+
+@pytest.mark.parametrize("coeff", [W.KAPPA_SIN, W.KAPPA_EXP, (W.COEFF_POLY, (1.0, 10.0, 3.0, 0.0))])
+def test_row_sums_vanish_and_symmetry(coeff):
+    # a(phi_i, 1) = 0 for every kappa: the full stencil sums to 0 at every interior point
+    t, P = _jittered(4, *coeff)
+    assert np.abs(P.A.sum(axis=1)).max() < 1e-14 * np.abs(P.A).max()
+    # A^p_d = A^{p+d}_{-d} (symmetric bilinear form)
+    for s in range(7):
+        j = P.col[:, 8 + s]
+        m = j >= 0
+        np.testing.assert_allclose(P.A[m, 8 + s], P.A[j[m], s], rtol=1e-13, atol=1e-16)
+    # diagonal positive
+    assert np.all(P.A[:, 7] > 0)
+
+
+def test_second_moment_identity():
+    # P1 reproduces quadratics in the weak sense on a translation-invariant
+    # lattice: J (sum_d A_d d d^T) J^T = -2 h |det J| I  (kappa = 1, any affine tet)
+    t, P = _jittered(5, W.COEFF_CONST, (1.0,), seed=3)
+    v = np.array(t.verts)
+    J = (v[1:] - v[0]).T
+    h = 1.0 / P.n
+    for p in ([8, 8, 8], [3, 5, 7], [10, 4, 2]):
+        i = O.index_of(5, [p])[0]
+        M = sum(P.A[i, s] * np.outer(O.DIRS[s], O.DIRS[s]) for s in range(15))
+        np.testing.assert_allclose(J @ M @ J.T, -2 * h * abs(np.linalg.det(J)) * np.eye(3), atol=1e-13)
+
+
+def test_stiffness_scales_with_h():
+    # A_d ~ Theta(h) (Remark in Sec. 3): halving h halves the stencil
+    a4 = O.Problem(W.REFERENCE_TET, 4).A[100]
+    a5 = O.Problem(W.REFERENCE_TET, 5).A[100]
+    np.testing.assert_allclose(a5, a4 / 2, rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------- ILU(0)
+
+
+def _factor_matrices(P, L, D):
+    m = P.col[:, :7] >= 0
+    rows = np.repeat(np.arange(P.N), 7).reshape(P.N, 7)[m]
+    Lm = sp.csr_matrix((L[m], (rows, P.col[:, :7][m])), shape=(P.N, P.N)) + sp.identity(P.N)
+    return Lm, sp.diags(D)
+
+
+@pytest.mark.parametrize("level,coeff", [(3, W.KAPPA_SIN), (4, W.KAPPA_SIN), (5, W.KAPPA_EXP)])
+def test_ilu_definition_on_pattern(level, coeff):
+    # (L D L^T)_ij = A_ij for (i,j) in S_A (Sec. 3)
+    t, P = _jittered(level, *coeff)
+    L, U, D = P.ilu0()
+    Lm, Dm = _factor_matrices(P, L, D)
+    C = (Lm @ Dm @ Lm.T).tocsr()
+    A = P.csr()
+    m = P.col >= 0
+    rows = np.repeat(np.arange(P.N), 15).reshape(P.N, 15)[m]
+    cvals = np.asarray(C[rows, P.col[m]]).ravel()
+    np.testing.assert_allclose(cvals, np.asarray(A[rows, P.col[m]]).ravel(), rtol=0,
+                               atol=1e-13 * np.abs(P.A).max())
+    # U = D L^T
+    for s in range(7):
+        j = P.col[:, 8 + s]
+        mm = j >= 0
+        np.testing.assert_allclose(U[mm, s], D[mm] * L[j[mm], s], rtol=1e-13, atol=1e-300)
+
+
+@pytest.mark.parametrize("level,coeff", [(4, W.KAPPA_SIN), (5, (W.COEFF_POLY, (1.0, 10.0, 2.0, 0.0)))])
+def test_stencil_recurrences_equal_definition(level, coeff):
+    # Alg. 1 / eq. (matrix-equations) reproduce the IKJ ILU(0)
+    t, P = _jittered(level, *coeff)
+    L, U, D = P.ilu0()
+    L2, D2, bad = P.ilu0_stencil()
+    assert bad == 0
+    np.testing.assert_allclose(L2, L, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(D2, D, rtol=1e-13)
+
+
+def test_full_pattern_ilu_is_dense_cholesky():
+    # ILU(0) with a full pattern drops nothing, so it is the exact LDL^T = Cholesky
+    t, P = _jittered(3, *W.KAPPA_SIN)
+    A = P.csr().toarray()
+    N = P.N
+    rowptr = np.arange(0, N * N + 1, N)
+    colind = np.tile(np.arange(N), N)
+    LU = O.ilu0_csr_inplace(rowptr, colind, A.ravel()).reshape(N, N)
+    R = np.linalg.cholesky(A)          # A = R R^T
+    d = np.diag(R) ** 2
+    Lx = R / np.diag(R)[None, :]
+    np.testing.assert_allclose(np.tril(LU, -1), np.tril(Lx, -1), atol=1e-13)
+    np.testing.assert_allclose(np.diag(LU), d, rtol=1e-13)
+
+
+def test_ilu_rows_before_first_dropped_fill_are_exact():
+    # rows computed before any fill has been dropped coincide with the exact factor
+    t, P = _jittered(4, *W.KAPPA_SIN)
+    A = P.csr().toarray()
+    R = np.linalg.cholesky(A)
+    Lx = R / np.diag(R)[None, :]
+    pattern = A != 0
+    fill = (np.abs(np.tril(Lx, -1)) > 1e-15) & ~pattern
+    i0 = int(np.nonzero(fill.any(axis=1))[0].min())
+    assert i0 > 0
+    L, U, D = P.ilu0()
+    Lm, _ = _factor_matrices(P, L, D)
+    Ld = Lm.toarray()
+    np.testing.assert_allclose(Ld[:i0], Lx[:i0], atol=1e-14)
+    np.testing.assert_allclose(D[:i0], (np.diag(R) ** 2)[:i0], rtol=1e-13)
+
+
+def test_fill_in_is_12_offsets_per_row():
+    # "our fill-in consists of 12 additional nonzero entries per row" (Sec. 3 remark)
+    t, P = _jittered(5, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    Lm, Dm = _factor_matrices(P, L, D)
+    C = (Lm @ Dm @ Lm.T).tocsr()
+    i = O.index_of(5, [[10, 10, 8]])[0]
+    pts = O.interior_points(5)
+    row = C.getrow(i)
+    offs = {tuple(pts[j] - pts[i]) for j, v in zip(row.indices, row.data) if v != 0}
+    stencil = {tuple(d) for d in O.DIRS}
+    assert stencil <= offs
+    assert len(offs - stencil) == 12
+
+
+def test_interior_ilu_converges_to_asymptotic_stencil():
+    # deep inside, the factors approach the Gauss-Seidel fixed point of the stencil
+    # equations (Sec. 3); D^inf ~ h and L^inf ~ 1 (Remark), A_c = D^inf (1 + sum L^2)
+    prev = None
+    for level in (5, 6):
+        P = O.Problem(W.REFERENCE_TET, level)
+        L, U, D = P.ilu0()
+        c = P.n // 4
+        i = O.index_of(level, [[c, c, c]])[0]
+        Li, Di = O.asymptotic_stencil(P.A[i])
+        tol = 1e-6 if level == 5 else 1e-13
+        np.testing.assert_allclose(L[i], Li, atol=tol)
+        np.testing.assert_allclose(D[i], Di, rtol=tol)
+        np.testing.assert_allclose(P.A[i, 7], Di * (1 + np.sum(Li ** 2)), rtol=1e-13)
+        if prev is not None:
+            np.testing.assert_allclose(Li, prev[0], atol=1e-12)
+            np.testing.assert_allclose(Di, prev[1] / 2, rtol=1e-12)
+        prev = (Li, Di)
+
+
+def test_breakdown_is_reported():
+    # a coefficient that is negative on part of the tet destroys positivity of pivots
+    t = W.make_tet(1, 4, W.COEFF_SINPROD, (0.0, 1.0, 1.0, 0.0))
+    P = O.Problem.from_tet(t)
+    L, D, bad = P.ilu0_stencil()
+    assert bad > 0
+
+
+# ---------------------------------------------------------------------- smoothing
+
+
+@pytest.mark.parametrize("level", [3, 4])
+def test_smoothing_step_solves_with_ldlt(level):
+    # x1 - x0 = (L D L^T)^{-1} (b - A x0): verified by products only
+    t, P = _jittered(level, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    rng = np.random.default_rng(1)
+    b = rng.uniform(-1, 1, P.N)
+    x0 = rng.uniform(-1, 1, P.N)
+    x1, _ = P.smooth(L, D, b, x0, nsweeps=1)
+    Lm, Dm = _factor_matrices(P, L, D)
+    lhs = Lm @ (Dm @ (Lm.T @ (x1 - x0)))
+    rhs = b - P.apply(x0)
+    assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(rhs)
+
+
+def test_first_step_from_zero_is_preconditioned_rhs():
+    t, P = _jittered(4, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    b = t.rhs()
+    x1, rel = P.smooth(L, D, b, nsweeps=1)
+    Lm, Dm = _factor_matrices(P, L, D)
+    assert np.linalg.norm(Lm @ (Dm @ (Lm.T @ x1)) - b) <= 1e-13 * np.linalg.norm(b)
+    assert rel[0] == pytest.approx(1.0)
+
+
+@pytest.mark.parametrize("level,coeff", [(4, W.KAPPA_SIN), (5, W.KAPPA_EXP)])
+def test_stencil_sweep_equals_matrix_sweep(level, coeff):
+    # Alg. 2 (stencil form, V2) with the exact factors = the definition
+    t, P = _jittered(level, *coeff)
+    L, U, D = P.ilu0()
+    b = t.rhs()
+    x, r = P.smooth(L, D, b, nsweeps=5)
+    x2, r2 = P.smooth_stencil(L, 1.0 / D, b, nsweeps=5)
+    np.testing.assert_allclose(x2, x, rtol=0, atol=1e-13 * np.abs(x).max())
+    np.testing.assert_allclose(r2, r, rtol=1e-10)
+    assert r[-1] < r[0] * 0.05
+
+
+def test_mixed_precision_sweep_tracks_fp64():
+    t, P = _jittered(4, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    b = t.rhs()
+    x, r = P.smooth_stencil(L, 1.0 / D, b, nsweeps=30)
+    x32, r32 = P.smooth_stencil_f32(L.astype(np.float32), (1.0 / D).astype(np.float32), b, nsweeps=30)
+    # the FP64 residual keeps driving the error down past FP32 resolution
+    assert r32[-1] < 1e-9
+    np.testing.assert_allclose(r32[:5], r[:5], rtol=1e-4)
+
+
+# ----------------------------------------------------------------------- surrogates
+
+
+def test_sample_sets_match_definition():
+    level, s = 5, 4
+    pts = O.interior_points(level)
+    n = 1 << level
+    for t in list(range(7)) + [7]:
+        d = O.DIRS[t]
+        idx = set(O.sample_set(level, t, s).tolist())
+        shift = 1 - np.minimum(d, 0)
+        for i, p in enumerate(pts):
+            q = p + d
+            ok = all((p - shift) % s == 0) and all(q >= 1) and q.sum() <= n - 1
+            assert (i in idx) == ok
+    # the c set is the plain coarse grid 1 + s Z^3 (no shift)
+    assert all(((pts[sorted(O.sample_set(level, 7, 2))] - 1) % 2 == 0).ravel())
+
+
+@pytest.mark.parametrize("level,stride,deg", [(5, 4, 4), (5, 2, 4), (6, 4, 4), (5, 4, 2)])
+def test_unisolvence_rule_matches_rank(level, stride, deg):
+    pts = O.interior_points(level).astype(float) / (1 << level)
+    for t in list(range(7)) + [7]:
+        idx = O.sample_set(level, t, stride)
+        V = O.legendre_tensor_matrix(pts[idx], deg)
+        full = np.linalg.matrix_rank(V) == V.shape[1]
+        assert full == (O.sample_side(level, O.DIRS[t], stride) >= 3 * deg)
+    # L5, stride 4, degree 4 is rank deficient; the rule falls back to stride 2
+    assert O.effective_stride(5, 4, 4) == 2
+    assert O.effective_stride(7, 4, 4) == 4
+
+
+def test_polynomial_samples_are_recovered_exactly():
+    level, deg, s = 6, 3, 2
+    pts = O.interior_points(level).astype(float) / (1 << level)
+    rng = np.random.default_rng(3)
+    coef = rng.normal(size=(8, (deg + 1) ** 3))
+    Ltrue = O.monomial_tensor_matrix(pts, deg) @ coef.T
+    L = np.ascontiguousarray(Ltrue[:, :7])
+    D = 1.0 / Ltrue[:, 7]
+    for basis in ("legendre", "monomial"):
+        c = O.fit_surrogate(level, L, D, deg, s, basis=basis)
+        Lw, Dinv = O.eval_surrogate(level, c, deg, basis=basis)
+        np.testing.assert_allclose(Lw, L, atol=1e-9 * np.abs(L).max())
+        np.testing.assert_allclose(Dinv, 1.0 / D, atol=1e-9 * np.abs(1 / D).max())
+
+
+def test_degree_zero_fit_is_sample_mean():
+    t, P = _jittered(5, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    c = O.fit_surrogate(5, L, D, 0, 2)
+    for slot in range(7):
+        idx = O.sample_set(5, slot, 2)
+        assert c[slot, 0] == pytest.approx(L[idx, slot].mean(), rel=1e-12)
+    assert c[7, 0] == pytest.approx((1.0 / D[O.sample_set(5, 7, 2)]).mean(), rel=1e-12)
+
+
+def test_fit_is_basis_independent_and_error_falls_with_degree():
+    t, P = _jittered(6, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    errs = []
+    for deg in (0, 1, 2, 3):
+        cl = O.fit_surrogate(6, L, D, deg, 4, basis="legendre")
+        cm = O.fit_surrogate(6, L, D, deg, 4, basis="monomial")
+        Ll, Dl = O.eval_surrogate(6, cl, deg, basis="legendre")
+        Lm, Dm = O.eval_surrogate(6, cm, deg, basis="monomial")
+        np.testing.assert_allclose(Ll, Lm, atol=1e-9)
+        np.testing.assert_allclose(Dl, Dm, rtol=1e-9)
+        rel, mx = O.surrogate_error(6, L, D, Ll, Dl)
+        errs.append(rel.mean())
+    # higher degree, smaller overall error (Sec. 4.2, discrete L2 error study)
+    assert errs[-1] < errs[0]
