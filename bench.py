@@ -1,0 +1,189 @@
+"""Benchmark: smoothed DOF-updates/s of the ILU(0) smoothing step on one MI355X.
+
+One step = one smoothing sweep x <- x + C^{-1}(b - A x) over the whole
+workload: FP64 residual, forward substitution, backward substitution with the
+update (every part of the hot path).  The timed region is one ilu_smooth call
+of K sweeps with x and b already resident in HBM (it includes the call's
+layout conversion of x and b).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TF = 78.6        # vector FP64
+FP32_PEAK_TF = 157.3       # vector FP32
+
+# Algorithmic bytes per interior DOF and kernel (each array touched once per
+# kernel; stencil weights: 8 unique FP64 values per point, the other 7 are the
+# neighbours' by symmetry).  w: FP64 (8 B) or FP32 (4 B).
+def kernel_bytes(variant: str):
+    wb = 4 if variant == "surr_f32" else 8
+    res = 8 + 8 + 64 + wb                    # x, b, A (8 weights), r
+    if variant == "stored_f64":
+        fwd = 8 + 56 + 8                      # r, L (7), w
+        bwd = 8 + 8 + 56 + 8 + 8 + 8          # w in, 1/D, L^T (7), w out, x in, x out
+    else:
+        fwd = wb + wb                         # r, w
+        bwd = wb + wb + 8 + 8                 # w in, w out, x in, x out
+    return {"residual": res, "forward": fwd, "backward": bwd}
+
+
+def kernel_flops(variant: str, dg: int):
+    res = 30                                  # 15 multiply-adds
+    if variant == "stored_f64":
+        return {"residual": res, "forward": 14, "backward": 16}
+    return {"residual": res, "forward": 14 + 14 * dg, "backward": 16 + 16 * dg}
+
+
+VARIANTS = {"stored_f64": 0, "surr_f64": 1, "surr_f32": 2}
+
+
+def run_variant(pkg, torch, wl, variant, steps, warmup):
+    kw = {} if variant == "stored_f64" else dict(degree=wl.degree, stride=wl.stride)
+    t0 = time.perf_counter()
+    sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    import numpy as np
+    b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
+    x = torch.zeros_like(b)
+    if warmup:
+        sm.smooth(x, b, warmup)
+    x.zero_()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sm.smooth(x, b, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    loop_ms = sm.timing()[0]
+    # relative residual reached, then per-kernel timing in a separate run
+    rel, _ = sm.smooth(x, b, 0, want_relres=True)
+    sm.set_kernel_timing(True)
+    x2 = torch.zeros_like(b)
+    sm.smooth(x2, b, steps)
+    torch.cuda.synchronize()
+    _, f_ms, b_ms, r_ms = sm.timing()
+    n = sm.n_total
+    out = dict(variant=variant, n_dof=n, setup_s=setup_s, ms_per_step=ms / steps,
+               loop_ms_per_step=loop_ms / steps, value=n * steps / (ms * 1e-3), relres_after=rel,
+               kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms))
+    sm.close()
+    return out
+
+
+def roofline(res, variant, dg):
+    bpd = kernel_bytes(variant)
+    fpd = kernel_flops(variant, dg)
+    km = res["kernel_ms"]
+    dom = max(km, key=km.get)
+    n = res["n_dof"]
+    t = km[dom] * 1e-3
+    gbs = bpd[dom] * n / t / 1e9
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+           "bytes_per_dof": bpd[dom], "flops_per_dof": fpd[dom],
+           "kernel_ms_per_launch": round(km[dom], 5)}
+    return out
+
+
+def cpu_baseline(wl, variant, budget_s=12.0):
+    """The oracle (plain C, one thread) on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle as O
+    t = wl.tets[0]
+    P = O.Problem.from_tet(t)
+    L, U, D = P.ilu0()
+    b = t.rhs()
+    if variant == "stored_f64":
+        run = lambda k: P.smooth(L, D, b, nsweeps=k)
+        kind = "matrix-form ILU(0) sweep, FP64"
+    else:
+        s = O.effective_stride(t.level, wl.degree, wl.stride)
+        c = O.fit_surrogate(t.level, L, D, wl.degree, s)
+        Lw, Dinv = O.eval_surrogate(t.level, c, wl.degree)
+        if variant == "surr_f32":
+            Lw32, Di32 = Lw.astype(np.float32), Dinv.astype(np.float32)
+            run = lambda k: P.smooth_stencil_f32(Lw32, Di32, b, nsweeps=k)
+            kind = "Alg. 2 stencil sweep, FP32 weights/substitutions, FP64 residual"
+        else:
+            run = lambda k: P.smooth_stencil(Lw, Dinv, b, nsweeps=k)
+            kind = "Alg. 2 stencil sweep, FP64"
+    t0 = time.perf_counter()
+    run(1)
+    one = max(time.perf_counter() - t0, 1e-4)
+    k = max(1, min(1000, int(budget_s / one)))
+    t0 = time.perf_counter()
+    run(k)
+    el = time.perf_counter() - t0
+    return {"value": P.N * k / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%s: tet 0 of the workload (%d DOFs), %d sweeps, %s, %.1f s" % (wl.name, P.N, k, kind, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="jit_L7_sin")
+    ap.add_argument("--variants", default="surr_f32,stored_f64,surr_f64")
+    ap.add_argument("--no-cpu", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(independent tetrahedra would shard across GPUs with no exchange).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2210_15280_amd as pkg
+    import workloads as W
+    pkg.lib()
+    wl = W.workload(a.workload)
+    variants = a.variants.split(",")
+    results = {}
+    for v in variants:
+        results[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup)
+        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, kernels %s" % (
+            v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],
+            json.dumps(results[v]["kernel_ms"])), file=sys.stderr, flush=True)
+    head = variants[0]
+    hr = results[head]
+    line = {
+        "metric": "smoothed DOF-updates/s (ILU(0) sweep) on 1 MI355X; FP32 surrogate vs FP64 stored",
+        "value": hr["value"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": hr["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"surr_f32": "f32 sweeps + f64 residual/update", "surr_f64": "f64",
+                  "stored_f64": "f64"}[head],
+        "data": "synthetic (seeded jittered macro-tetrahedra, seeded RHS)",
+        "config": {"workload": wl.name, "variant": head, "n_tets": len(wl.tets),
+                   "levels": sorted({t.level for t in wl.tets}), "n_dof": hr["n_dof"],
+                   "surrogate_degree": wl.degree, "sample_stride": wl.stride, "parallelism": "single GPU"},
+        "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "loop_ms_per_step", "relres_after", "setup_s",
+                                            "kernel_ms")} for v, r in results.items()},
+        "roofline": roofline(hr, head, wl.degree),
+    }
+    if "stored_f64" in results and head != "stored_f64":
+        line["speedup_vs_stored_f64"] = hr["value"] / results["stored_f64"]["value"]
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, head)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

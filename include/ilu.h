@@ -1,0 +1,167 @@
+/*
+ * ilu.h -- C-ABI of libilu: matrix-free ILU(0) smoothing on uniformly refined
+ * macro-tetrahedra (Drzisga, Wagner, Wohlmuth, "A matrix-free ILU realization
+ * based on surrogates", arXiv:2210.15280), for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. 2.1 and Sec. 3): for each macro-tetrahedron t with vertices
+ * v1..v4 (their order fixes the DOF ordering), refinement level L >= 2
+ * (n = 2^L intervals per edge) and a scalar coefficient kappa, let A be the
+ * P1 stiffness matrix of a(u,v) = int grad(u) . kappa grad(v) restricted to
+ * the N = C(n-1,3) interior lattice points (homogeneous Dirichlet values on
+ * the macro boundary), and L D L^T its ILU(0) in lexicographic order.  A
+ * smoothing step is the Richardson step
+ *     x <- x + C^{-1} (b - A x),   C = L D L^T,
+ * where C is either the exact ILU(0) (stored factors) or its surrogate: one
+ * polynomial per lower stencil direction for L and one for 1/D, fitted by
+ * least squares on the sample sets S_d (Sec. 4.1), evaluated on the fly
+ * (Alg. 2, boundary variant V2).
+ *
+ * Vectors at this interface: FP64 device arrays, interior points of each
+ * tetrahedron in lexicographic order (z slowest, then y, then x; x,y,z >= 1,
+ * x+y+z <= n-1), tetrahedra concatenated in the order given to
+ * ilu_setup_surrogate; ilu_layout reports each tetrahedron's offset.
+ *
+ * Conventions: every call returns ILU_OK (0) or a negative error code; no
+ * exception crosses the interface and nothing is printed.  Device pointers
+ * are caller-owned; the handle owns every buffer it allocates.  `hip_stream`
+ * is a hipStream_t (NULL = default stream).  Calls on one handle must not
+ * overlap (they share the handle's work buffers).
+ */
+#ifndef ILU_H
+#define ILU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define ILU_OK 0
+#define ILU_EINVAL (-1)     /* bad argument (null pointer, level, degree, ...) */
+#define ILU_ENOMEM (-2)     /* device allocation failed */
+#define ILU_EHIP (-3)       /* a HIP runtime call failed */
+#define ILU_EBREAKDOWN (-4) /* ILU(0) pivot D^p <= 0 (A is not an M-matrix) */
+#define ILU_ERANK (-5)      /* a least-squares problem is rank deficient */
+#define ILU_EGEOM (-6)      /* det J <= 0 (degenerate or inverted tetrahedron) */
+#define ILU_ENOTCONV (-7)   /* rel_tol requested but not reached in nsweeps */
+
+/* coefficient kinds (kappa as a function of the physical point X) */
+#define ILU_COEFF_CONST 0     /* p0 */
+#define ILU_COEFF_SINPROD 1   /* p0 + p1 sin(2 pi p2 X) sin(2 pi p2 Y) sin(2 pi p2 Z) */
+#define ILU_COEFF_EXPSINCOS 2 /* exp(p0 sin(2 pi p2 X) cos(2 pi p2 Y)) */
+#define ILU_COEFF_POLY 3      /* p0 + p1 (X^i + Y^i + Z^i), i = (int)p2 */
+
+/* smoother variants */
+#define ILU_STORED_F64 0 /* exact ILU(0) factors stored in HBM, FP64 sweeps */
+#define ILU_SURR_F64 1   /* surrogate weights evaluated on the fly, FP64 sweeps */
+#define ILU_SURR_F32 2   /* surrogate weights and both sweeps in FP32; residual and
+                            update in FP64 (iterative refinement) */
+
+/* sweep schedules */
+#define ILU_SCHED_AUTO 0      /* persistent dataflow kernel */
+#define ILU_SCHED_PLANE 1     /* one launch per hyperplane (reference schedule) */
+#define ILU_SCHED_DATAFLOW 2  /* persistent kernel, per-block progress counters */
+
+typedef struct ilu_tet_desc {
+    double vertex[4][3];   /* v1..v4; d_i = v_{i+1} - v1 must have det > 0 */
+    int32_t level;         /* L in [2, 10] */
+    int32_t coeff_kind;    /* ILU_COEFF_* */
+    double coeff_param[4];
+} ilu_tet_desc;
+
+typedef struct ilu_opts {
+    int32_t variant;        /* ILU_STORED_F64 / ILU_SURR_F64 / ILU_SURR_F32 */
+    int32_t degree[3];      /* surrogate degrees (dg_x, dg_y, dg_z), each in [0, 6] */
+    int32_t sample_stride;  /* stride of S_d (power of two); halved until every
+                               sample set is unisolvent; 0 = 4 */
+    int32_t schedule;       /* ILU_SCHED_* */
+    int32_t reserved[4];    /* must be 0 */
+} ilu_opts;
+
+typedef struct ilu_handle_s *ilu_handle_t;
+
+/* Build the smoother for `ntets` tetrahedra: assemble A (Sec. 2.1), factor it
+ * with the stencil recurrences of Sec. 3 on the GPU, and for surrogate
+ * variants sample the factors on S_d and solve the FP64 least-squares
+ * problems (Sec. 4.1, Alg. 1).  Synchronous on `hip_stream`, so breakdown
+ * (ILU_EBREAKDOWN), rank (ILU_ERANK) and geometry (ILU_EGEOM) errors are
+ * reported here.  On success *out owns all device memory of the smoother. */
+int ilu_setup_surrogate(const ilu_tet_desc *tets, int32_t ntets, const ilu_opts *opts, void *hip_stream,
+                        ilu_handle_t *out);
+
+/* Apply `nsweeps` smoothing steps x <- x + C^{-1}(b - A x) (Alg. 2) to every
+ * tetrahedron.  x (in/out) and b (in) are FP64 device arrays in the layout
+ * above.  If rel_tol > 0 the loop stops early once ||b - A x||_2 / ||b||_2 <=
+ * rel_tol over all tetrahedra (checked after every sweep; this synchronises)
+ * and returns ILU_ENOTCONV if it is not reached.  relres_out (host, may be
+ * NULL) receives the final relative residual, which is only computed when
+ * rel_tol > 0 or relres_out != NULL.  Otherwise stream-ordered. */
+int ilu_smooth(ilu_handle_t h, double *x, const double *b, int32_t nsweeps, double rel_tol, double *relres_out,
+               void *hip_stream);
+
+/* y = A x on the interior points (Sec. 2.1 stencil matvec), FP64 device
+ * arrays in the layout above.  Stream-ordered. */
+int stencil_apply(ilu_handle_t h, const double *x, double *y, void *hip_stream);
+
+/* Offset and interior-point count of tetrahedron `tet` in the vectors. */
+int ilu_layout(ilu_handle_t h, int32_t tet, int64_t *offset, int64_t *count_interior);
+
+/* Release every resource of the handle (NULL is accepted). */
+int ilu_destroy(ilu_handle_t h);
+
+/* Static message for an error code. */
+const char *ilu_strerror(int code);
+
+/* ---- inspection (tests and diagnostics; all synchronous on hip_stream) ---- */
+
+/* Assembled stencil of tetrahedron `tet` in lexicographic order: A_out is a
+ * device FP64 array [N][15], directions in the order
+ * w,s,se,bnw,bn,bc,be,c,e,n,nw,tse,ts,tc,tw (Sec. 2.1); entries whose
+ * neighbour lies on the macro boundary are 0. */
+int ilu_get_stencil(ilu_handle_t h, int32_t tet, double *A_out, void *hip_stream);
+
+/* Exact ILU(0) factors of tetrahedron `tet` (only for ILU_STORED_F64):
+ * L_out device FP64 [N][7] (directions w,s,se,bnw,bn,bc,be; 0 where the
+ * neighbour is on the boundary), D_out device FP64 [N]. */
+int ilu_get_factors(ilu_handle_t h, int32_t tet, double *L_out, double *D_out, void *hip_stream);
+
+/* Surrogate coefficients of tetrahedron `tet` (surrogate variants), host FP64
+ * array [8][K], K = (dg_x+1)(dg_y+1)(dg_z+1).  Row r < 7 fits L_d for the
+ * lower direction r (order above), row 7 fits 1/D.  Basis: shifted Legendre
+ * P_i(2x-1) P_j(2y-1) P_k(2z-1) of X^ = (x,y,z)/2^L, column (k(dg_y+1)+j)(dg_x+1)+i.
+ * ilu_set_surrogate replaces them (and rebuilds the evaluation tables). */
+int ilu_get_surrogate(ilu_handle_t h, int32_t tet, double *coeffs_out);
+int ilu_set_surrogate(ilu_handle_t h, int32_t tet, const double *coeffs, void *hip_stream);
+
+/* Surrogate weights as the sweeps evaluate them, lexicographic order:
+ * L_out device FP64 [N][7], Dinv_out device FP64 [N] (FP32 variants are
+ * widened). */
+int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double *L_out, double *Dinv_out, void *hip_stream);
+
+/* Effective sample stride chosen for tetrahedron `tet` (surrogate variants). */
+int ilu_sample_stride(ilu_handle_t h, int32_t tet, int32_t *stride_out);
+
+/* Device times (ms) of the last ilu_smooth call, from HIP events on its
+ * stream: the whole sweep loop, and per sweep the forward substitution, the
+ * backward substitution and the residual (averaged over all sweeps when
+ * kernel timing is on, else taken from the first sweep).  The forward and
+ * backward figures include the small counter-reset kernel of the dataflow
+ * schedule. */
+int ilu_last_timing(ilu_handle_t h, double *sweep_ms, double *fwd_kernel_ms, double *bwd_kernel_ms,
+                    double *res_kernel_ms);
+
+/* Record events around every kernel of every sweep (diagnostics; adds a
+ * little launch overhead).  Off by default. */
+int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable);
+
+/* Host-only self check (no device needed): builds the stream layout for the
+ * given tetrahedra and replays every index the kernels form, counting
+ * out-of-range or misdirected accesses in *violations (0 = consistent). */
+int ilu_check_layout(const ilu_tet_desc *tets, int32_t ntets, const ilu_opts *opts, int64_t *violations);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ILU_H */

@@ -1,0 +1,892 @@
+// C-ABI entry points of libilu (see include/ilu.h) and the host-side layout
+// and orchestration.  Every arithmetic step of the method runs in the HIP
+// kernels; the host only builds index tables, allocates, launches and checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <queue>
+#include <vector>
+
+#include "../../include/ilu.h"
+#include "ctx.h"
+#include "setup_kernels.h"
+#include "sweep_kernels.h"
+
+using namespace ilu;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n, hipStream_t st, bool zero = true) {
+        release();
+        bytes = n ? n : 8;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        if (zero) e = hipMemsetAsync(p, 0, bytes, st);
+        return e;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+int64_t choose3_h(int64_t k) { return k < 3 ? 0 : k * (k - 1) * (k - 2) / 6; }
+
+}  // namespace
+
+struct ilu_handle_s {
+    int ntets = 0;
+    int variant = 0;
+    int schedule = 0;
+    int deg[3] = {0, 0, 0};
+    int NC = 0, K = 0;
+    int64_t S = 0;
+    int64_t nlex = 0;
+    int tmin = 0, tmax = 0;
+    std::vector<TetDev> tets;
+    std::vector<BlockDev> blocks;
+    std::vector<LaneDev> lanes;
+    std::vector<double> coef_h;  // ntets * 8 * K
+    DevBuf tets_d, blocks_d, lanes_d;
+    DevBuf A8, Lf, Df, Lb, tab64, tab32, coef_d;
+    DevBuf xs, bs, r, w;
+    DevBuf partial, norms, flags;
+    DevBuf order_fwd, order_bwd, progress, ticket;
+    int64_t npartial = 0;
+    int flow_grid = 0;
+    hipEvent_t ev[8] = {};
+    bool have_timing = false;
+    bool kernel_timing = false;          // events around every kernel of every sweep
+    std::vector<hipEvent_t> kev;         // 4 per sweep: res begin/end = fwd begin, fwd end = bwd begin, bwd end
+    int kev_sweeps = 0;
+
+    Ctx ctx() const {
+        Ctx c;
+        c.tets = tets_d.as<TetDev>();
+        c.blocks = blocks_d.as<BlockDev>();
+        c.lanes = lanes_d.as<LaneDev>();
+        c.nblocks = (int)blocks.size();
+        c.S = S;
+        int maxlen = 1;
+        for (const auto& b : blocks) maxlen = std::max(maxlen, b.te - b.tb + 1);
+        c.res_chunks = (maxlen + RES_T - 1) / RES_T;
+        c.A8 = A8.as<double>();
+        c.Lf = Lf.as<double>();
+        c.Lb = Lb.as<double>();
+        c.tab64 = tab64.as<double>();
+        c.tab32 = tab32.as<float>();
+        c.NC = NC;
+        c.r = r.p;
+        c.w = w.p;
+        return c;
+    }
+    Flow flow() const {
+        Flow f;
+        f.order_fwd = order_fwd.as<int32_t>();
+        f.order_bwd = order_bwd.as<int32_t>();
+        f.progress = progress.as<int32_t>();
+        f.ticket = ticket.as<int32_t>();
+        f.flags = flags.as<int32_t>();
+        f.grid = flow_grid;
+        return f;
+    }
+    ~ilu_handle_s() {
+        for (auto& e : ev)
+            if (e) hipEventDestroy(e);
+        for (auto& e : kev)
+            if (e) hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return ILU_EHIP;    \
+    } while (0)
+
+// Sample sets S_d as lattice simplices of side M (see the sampling kernel).
+int sample_side(int n, int fit, int stride) {
+    static const int d[8][3] = {{-1, 0, 0}, {0, -1, 0}, {1, -1, 0}, {-1, 1, -1},
+                                {0, 1, -1}, {0, 0, -1}, {1, 0, -1}, {0, 0, 0}};
+    int sumd = d[fit][0] + d[fit][1] + d[fit][2];
+    int shift = 0;
+    for (int k = 0; k < 3; ++k) shift += 1 - std::min(d[fit][k], 0);
+    int room = n - 1 - std::max(0, sumd) - shift;
+    return room >= 0 ? room / stride : -1;
+}
+
+int build_layout(ilu_handle_t h) {
+    int nmax = 0;
+    for (auto& T : h->tets) nmax = std::max(nmax, T.n);
+    const int64_t Z = (int64_t)LANES * (3 * nmax + 8);
+    int64_t S = Z;
+    std::vector<std::vector<int>> bmap(h->ntets);
+    std::vector<int> nbs(h->ntets);
+    int64_t lexoff = 0;
+    for (int ti = 0; ti < h->ntets; ++ti) {
+        TetDev& T = h->tets[ti];
+        const int n = T.n;
+        const int nb = std::max(1, (n - 3 + 7) / 8);
+        nbs[ti] = nb;
+        bmap[ti].assign((size_t)nb * nb, -1);
+        T.blk0 = (int)h->blocks.size();
+        T.lex_off = lexoff;
+        T.N = choose3_h(n - 1);
+        lexoff += T.N;
+        for (int bw = 0; bw < nb; ++bw)
+            for (int bv = 0; bv < nb; ++bv) {
+                const int V0 = 2 + 8 * bv, W0 = 1 + 8 * bw;
+                int tb = 1 << 30, te = -1;
+                for (int l = 0; l < LANES; ++l) {
+                    const int v = V0 + (l & 7), w = W0 + (l >> 3);
+                    if (v > n - 2 || w > v - 1) continue;
+                    tb = std::min(tb, 2 * v + w + 1);
+                    te = std::max(te, n - 1 + v + w);
+                }
+                if (te < 0) continue;
+                BlockDev B{};
+                B.tet = ti;
+                B.V0 = V0;
+                B.W0 = W0;
+                B.tb = tb;
+                B.te = te;
+                B.tlo = tb - PAD;
+                B.len = te - tb + 1 + 2 * PAD;
+                B.base = S;
+                S += (int64_t)B.len * LANES;
+                bmap[ti][(size_t)bv * nb + bw] = (int)h->blocks.size();
+                h->blocks.push_back(B);
+            }
+        T.nblk = (int)h->blocks.size() - T.blk0;
+    }
+    h->S = S;
+    h->nlex = lexoff;
+    auto block_at = [&](int ti, int bv, int bw) -> int {
+        const int nb = nbs[ti];
+        if (bv < 0 || bw < 0 || bv >= nb || bw >= nb) return -1;
+        return bmap[ti][(size_t)bv * nb + bw];
+    };
+    auto rp_of = [&](int ti, int v, int w) -> int64_t {
+        const int n = h->tets[ti].n;
+        if (v < 2 || v > n - 2 || w < 1 || w > v - 1) return 0;  // zero region
+        const int b = block_at(ti, (v - 2) / 8, (w - 1) / 8);
+        const BlockDev& B = h->blocks[b];
+        const int l = (w - B.W0) * 8 + (v - B.V0);
+        return B.base - (int64_t)B.tlo * LANES + l;
+    };
+    h->lanes.resize(h->blocks.size() * LANES);
+    h->tmin = 1 << 30;
+    h->tmax = 0;
+    for (size_t bi = 0; bi < h->blocks.size(); ++bi) {
+        BlockDev& B = h->blocks[bi];
+        const int ti = B.tet, n = h->tets[ti].n;
+        const int bv = (B.V0 - 2) / 8, bw = (B.W0 - 1) / 8;
+        B.pred[0] = block_at(ti, bv - 1, bw);
+        B.pred[1] = block_at(ti, bv, bw - 1);
+        B.pred[2] = block_at(ti, bv - 1, bw - 1);
+        B.succ[0] = block_at(ti, bv + 1, bw);
+        B.succ[1] = block_at(ti, bv, bw + 1);
+        B.succ[2] = block_at(ti, bv + 1, bw + 1);
+        h->tmin = std::min(h->tmin, B.tb);
+        h->tmax = std::max(h->tmax, B.te);
+        for (int l = 0; l < LANES; ++l) {
+            LaneDev& L = h->lanes[bi * LANES + l];
+            const int v = B.V0 + (l & 7), w = B.W0 + (l >> 3);
+            const bool valid = v <= n - 2 && w <= v - 1;
+            L.v = valid ? v : 0;
+            L.w = w;
+            L.rp[R_SELF] = valid ? B.base - (int64_t)B.tlo * LANES + l : 0;
+            L.rp[R_VM] = rp_of(ti, v - 1, w);
+            L.rp[R_WM] = rp_of(ti, v, w - 1);
+            L.rp[R_VMWM] = rp_of(ti, v - 1, w - 1);
+            L.rp[R_VP] = rp_of(ti, v + 1, w);
+            L.rp[R_WP] = rp_of(ti, v, w + 1);
+            L.rp[R_VPWP] = rp_of(ti, v + 1, w + 1);
+        }
+    }
+    return ILU_OK;
+}
+
+// Kahn topological order of the block DAG, ready blocks taken by priority.
+std::vector<int32_t> topo_order(const std::vector<BlockDev>& blocks, bool forward) {
+    const int nb = (int)blocks.size();
+    std::vector<int> indeg(nb, 0);
+    std::vector<std::vector<int>> out(nb);
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 3; ++k) {
+            const int p = forward ? blocks[b].pred[k] : blocks[b].succ[k];
+            if (p >= 0) {
+                indeg[b]++;
+                out[p].push_back(b);
+            }
+        }
+    auto key = [&](int b) -> int64_t {
+        const BlockDev& B = blocks[b];
+        return forward ? ((int64_t)B.tb << 20) + (B.V0 + B.W0) : ((int64_t)(-B.te) << 20) - (B.V0 + B.W0);
+    };
+    auto cmp = [&](int a, int b) { return key(a) > key(b) || (key(a) == key(b) && a > b); };
+    std::priority_queue<int, std::vector<int>, decltype(cmp)> pq(cmp);
+    for (int b = 0; b < nb; ++b)
+        if (!indeg[b]) pq.push(b);
+    std::vector<int32_t> order;
+    order.reserve(nb);
+    while (!pq.empty()) {
+        const int b = pq.top();
+        pq.pop();
+        order.push_back(b);
+        for (int s : out[b])
+            if (--indeg[s] == 0) pq.push(s);
+    }
+    return order;
+}
+
+template <typename T>
+int upload(DevBuf& buf, const std::vector<T>& v, hipStream_t st) {
+    if (buf.alloc(v.size() * sizeof(T), st, false) != hipSuccess) return ILU_ENOMEM;
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return ILU_OK;
+}
+
+int read_flags(ilu_handle_t h, hipStream_t st, int32_t out[4]) {
+    HIPCHK(hipMemcpyAsync(out, h->flags.p, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+// Least squares for every (tet, fitted direction): TSQR with Householder
+// chunks, then back substitution (all on the device).
+int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st) {
+    const int K = h->K, m = K + 1;
+    const int chunk = 4 * m;
+    const Ctx c = h->ctx();
+    const int np = h->ntets * NFIT;
+    std::vector<int64_t> rows(np);
+    for (int ti = 0; ti < h->ntets; ++ti)
+        for (int f = 0; f < NFIT; ++f) rows[ti * NFIT + f] = h->tets[ti].samp_cnt[f];
+    std::vector<bool> done(np, false);
+    std::vector<int64_t> in_at(np, 0);  // row offset of each problem in the current input
+    DevBuf finalR, in, out, scratch, jobs_d;
+    if (finalR.alloc((size_t)np * m * m * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    bool level0 = true;
+    for (int level = 0; level < 64; ++level) {
+        std::vector<QrJob> jobs;
+        int64_t outrows = 0;
+        int chunks = 0;
+        std::vector<int> jp;
+        for (int p = 0; p < np; ++p) {
+            if (done[p]) continue;
+            QrJob J{};
+            J.tet = p / NFIT;
+            J.fit = p % NFIT;
+            J.in_rows = rows[p];
+            J.in_off = level0 ? h->tets[J.tet].samp_off[J.fit] : in_at[p];
+            J.nchunk = (int)((rows[p] + chunk - 1) / chunk);
+            J.chunk0 = chunks;
+            J.out_off = outrows;
+            chunks += J.nchunk;
+            outrows += (int64_t)J.nchunk * m;
+            jobs.push_back(J);
+            jp.push_back(p);
+        }
+        if (jobs.empty()) break;
+        if (out.alloc((size_t)outrows * m * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
+        const int grid = std::min(chunks, 256);
+        if (scratch.bytes < (size_t)grid * chunk * m * sizeof(double))
+            if (scratch.alloc((size_t)grid * chunk * m * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
+        if (upload(jobs_d, jobs, st)) return ILU_ENOMEM;
+        launch_qr_chunks(c, jobs_d.as<QrJob>(), (int)jobs.size(), level0 ? 1 : 0, m, chunk, samples.as<double>(),
+                         in.as<double>(), out.as<double>(), scratch.as<double>(), grid, chunks, st);
+        HIPCHK(hipGetLastError());
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const int p = jp[j];
+            rows[p] = (int64_t)jobs[j].nchunk * m;
+            in_at[p] = jobs[j].out_off;
+            if (jobs[j].nchunk == 1) {
+                done[p] = true;
+                HIPCHK(hipMemcpyAsync(finalR.as<double>() + (size_t)p * m * m, out.as<double>() + jobs[j].out_off * m,
+                                      (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, st));
+            }
+        }
+        std::swap(in, out);
+        level0 = false;
+    }
+    // solve
+    std::vector<QrJob> sj(np);
+    for (int p = 0; p < np; ++p) {
+        sj[p] = QrJob{};
+        sj[p].tet = p / NFIT;
+        sj[p].fit = p % NFIT;
+        sj[p].out_off = (int64_t)p * m;
+    }
+    if (upload(jobs_d, sj, st)) return ILU_ENOMEM;
+    if (h->coef_d.alloc((size_t)np * K * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    launch_qr_solve(jobs_d.as<QrJob>(), np, m, finalR.as<double>(), h->coef_d.as<double>(), h->flags.as<int>(), st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int build_tables(ilu_handle_t h, hipStream_t st) {
+    const int nslots = (int)h->blocks.size() * LANES;
+    const size_t rec = 2 + 15 * (size_t)h->NC;
+    if (h->tab64.alloc(nslots * rec * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    if (h->variant == ILU_SURR_F32 && h->tab32.alloc(nslots * rec * sizeof(float), st) != hipSuccess)
+        return ILU_ENOMEM;
+    const Ctx c = h->ctx();
+    launch_row_tables(c, nslots, h->coef_d.as<double>(), h->NC, h->tab64.as<double>(),
+                      h->variant == ILU_SURR_F32 ? h->tab32.as<float>() : nullptr, st);
+    HIPCHK(hipGetLastError());
+    return ILU_OK;
+}
+
+// Host-only preparation: validated tetrahedron records, sample layout, block tables.
+int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_handle_t h, int64_t* nsamples) {
+    h->ntets = ntets;
+    h->variant = opts->variant;
+    h->schedule = opts->schedule == ILU_SCHED_PLANE ? ILU_SCHED_PLANE : ILU_SCHED_DATAFLOW;
+    const bool surr = h->variant != ILU_STORED_F64;
+    for (int k = 0; k < 3; ++k) h->deg[k] = surr ? opts->degree[k] : 0;
+    h->NC = h->deg[0] + 1;
+    h->K = (h->deg[0] + 1) * (h->deg[1] + 1) * (h->deg[2] + 1);
+    const int stride0 = opts->sample_stride > 0 ? opts->sample_stride : 4;
+    h->tets.resize(ntets);
+    int64_t soff = 0;
+    for (int i = 0; i < ntets; ++i) {
+        const ilu_tet_desc& D = tets[i];
+        TetDev& T = h->tets[i];
+        std::memset(&T, 0, sizeof(T));
+        T.level = D.level;
+        T.n = 1 << D.level;
+        T.kind = D.coeff_kind;
+        for (int k = 0; k < 4; ++k) T.cp[k] = D.coeff_param[k];
+        for (int r = 0; r < 3; ++r) {
+            T.v0[r] = D.vertex[0][r];
+            for (int c = 0; c < 3; ++c) T.J[3 * r + c] = D.vertex[c + 1][r] - D.vertex[0][r];
+        }
+        const double* J = T.J;
+        const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
+                           J[2] * (J[3] * J[7] - J[4] * J[6]);
+        if (!(det > 0.0) || !std::isfinite(det)) return ILU_EGEOM;
+        for (int k = 0; k < 3; ++k) T.deg[k] = h->deg[k];
+        T.ncoef = h->K;
+        if (surr) {
+            const int need = h->deg[0] + h->deg[1] + h->deg[2];
+            int s = stride0;
+            while (s >= 1) {
+                bool ok = true;
+                for (int f = 0; f < NFIT; ++f) ok = ok && sample_side(T.n, f, s) >= need;
+                if (ok) break;
+                s /= 2;
+            }
+            if (s < 1) return ILU_ERANK;
+            T.stride = s;
+            for (int f = 0; f < NFIT; ++f) {
+                T.samp_M[f] = sample_side(T.n, f, s);
+                T.samp_cnt[f] = choose3_h(T.samp_M[f] + 3);
+                T.samp_off[f] = soff;
+                soff += T.samp_cnt[f];
+            }
+        }
+    }
+    if (int e = build_layout(h)) return e;
+    *nsamples = soff;
+    return ILU_OK;
+}
+
+int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t h) {
+    int64_t soff = 0;
+    if (int e = prepare(tets, ntets, opts, h, &soff)) return e;
+    const bool surr = h->variant != ILU_STORED_F64;
+    if (upload(h->tets_d, h->tets, st) || upload(h->blocks_d, h->blocks, st) || upload(h->lanes_d, h->lanes, st))
+        return ILU_ENOMEM;
+    if (h->flags.alloc(4 * sizeof(int32_t), st) != hipSuccess) return ILU_ENOMEM;
+    const int64_t S = h->S;
+    if (h->A8.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    launch_assemble(h->ctx(), h->A8.as<double>(), nullptr, st);
+    HIPCHK(hipGetLastError());
+    // factorisation on the hyperplane schedule
+    if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    {
+        const Ctx c = h->ctx();
+        for (int t = h->tmin; t <= h->tmax; ++t)
+            launch_factor_plane(c, t, h->Lf.as<double>(), h->Df.as<double>(), h->flags.as<int>(), st);
+        HIPCHK(hipGetLastError());
+    }
+    int32_t fl[4];
+    if (int e = read_flags(h, st, fl)) return e;
+    if (fl[0]) return ILU_EBREAKDOWN;
+    if (!surr) {
+        if (h->Lb.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+        launch_transpose(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->Lb.as<double>(), st);
+        HIPCHK(hipGetLastError());
+    } else {
+        DevBuf samples;
+        if (samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+        launch_gather_samples(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), samples.as<double>(), st);
+        HIPCHK(hipGetLastError());
+        if (int e = solve_lsq(h, samples, st)) return e;
+        if (int e = read_flags(h, st, fl)) return e;
+        if (fl[1]) return ILU_ERANK;
+        h->coef_h.resize((size_t)ntets * NFIT * h->K);
+        HIPCHK(hipMemcpyAsync(h->coef_h.data(), h->coef_d.p, h->coef_h.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        if (int e = build_tables(h, st)) return e;
+        // the exact factors are only needed during setup for the surrogate variants
+        h->Lf.release();
+        h->Df.release();
+    }
+    // sweep buffers
+    const size_t es = h->variant == ILU_SURR_F32 ? sizeof(float) : sizeof(double);
+    if (h->xs.alloc((size_t)S * 8, st) || h->bs.alloc((size_t)S * 8, st) || h->r.alloc((size_t)S * es, st) ||
+        h->w.alloc((size_t)S * es, st))
+        return ILU_ENOMEM;
+    const Ctx c = h->ctx();
+    h->npartial = (int64_t)c.nblocks * c.res_chunks;
+    if (h->partial.alloc((size_t)h->npartial * sizeof(double), st) || h->norms.alloc(4 * sizeof(double), st))
+        return ILU_ENOMEM;
+    if (upload(h->order_fwd, topo_order(h->blocks, true), st) || upload(h->order_bwd, topo_order(h->blocks, false), st))
+        return ILU_ENOMEM;
+    if (h->progress.alloc(std::max<size_t>(1, h->blocks.size()) * sizeof(int32_t), st) ||
+        h->ticket.alloc(2 * sizeof(int32_t), st))
+        return ILU_ENOMEM;
+    h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC));
+    for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+
+// Replays, on the host, every global index the kernels form and checks that
+// it stays inside the streams and addresses the intended point (or a slot that
+// is never written, which holds zero).  Returns the number of violations.
+int64_t check_layout(ilu_handle_t h) {
+    const int64_t S = h->S;
+    std::vector<int32_t> owner(S, -1);  // written slot -> point id (block*64+lane, t) packed
+    std::vector<int32_t> owner_t(S, -1);
+    int64_t bad = 0;
+    auto active = [&](const BlockDev& B, const LaneDev& L, int t, int* x) {
+        if (L.v == 0 || t < B.tb || t > B.te) return false;
+        const int n = h->tets[B.tet].n;
+        *x = t - 2 * L.v - L.w;
+        return *x >= 1 && *x <= n - 1 - L.v;
+    };
+    std::vector<int64_t> seen_lex(h->nlex, -1);
+    for (size_t b = 0; b < h->blocks.size(); ++b) {
+        const BlockDev& B = h->blocks[b];
+        for (int l = 0; l < LANES; ++l) {
+            const LaneDev& L = h->lanes[b * LANES + l];
+            for (int t = B.tb; t <= B.te; ++t) {
+                int x;
+                if (!active(B, L, t, &x)) continue;
+                const int64_t q = L.rp[R_SELF] + (int64_t)LANES * t;
+                if (q < B.base || q >= B.base + (int64_t)B.len * LANES) { ++bad; continue; }
+                if (owner[q] != -1) ++bad;
+                owner[q] = (int32_t)(b * LANES + l);
+                owner_t[q] = t;
+                const TetDev& T = h->tets[B.tet];
+                const int y = L.v - L.w, z = L.w;
+                const int64_t mz = T.n - 1 - z;
+                const int64_t li = T.lex_off + choose3_h(T.n - 1) - choose3_h(T.n - z) + (int64_t)(y - 1) * mz -
+                                   (int64_t)(y - 1) * y / 2 + (x - 1);
+                if (li < T.lex_off || li >= T.lex_off + T.N || seen_lex[li] != -1) ++bad;
+                else seen_lex[li] = q;
+            }
+        }
+    }
+    for (int64_t i = 0; i < h->nlex; ++i) bad += seen_lex[i] < 0;
+    static const int dx[7] = {-1, 0, 1, -1, 0, 0, 1}, dy[7] = {0, -1, -1, 1, 1, 0, 0}, dz[7] = {0, 0, 0, -1, -1, -1, -1};
+    static const int lrow[7] = {R_SELF, R_VM, R_VM, R_WM, R_WM, R_VMWM, R_VMWM};
+    static const int urow[7] = {R_SELF, R_VP, R_VP, R_WP, R_WP, R_VPWP, R_VPWP};
+    // neighbour accesses of the residual, plane and dataflow kernels
+    for (size_t b = 0; b < h->blocks.size(); ++b) {
+        const BlockDev& B = h->blocks[b];
+        const int n = h->tets[B.tet].n;
+        for (int l = 0; l < LANES; ++l) {
+            const LaneDev& L = h->lanes[b * LANES + l];
+            for (int t = B.tb; t <= B.te; ++t) {
+                int x;
+                if (!active(B, L, t, &x)) continue;
+                const int y = L.v - L.w, z = L.w;
+                for (int s = 0; s < 7; ++s)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        const int ex = sg * dx[s], ey = sg * dy[s], ez = sg * dz[s];
+                        const int dt = ex + 2 * ey + 3 * ez;
+                        const int64_t q = L.rp[sg < 0 ? urow[s] : lrow[s]] + (int64_t)LANES * (t + dt);
+                        if (q < 0 || q >= S) { ++bad; continue; }
+                        const int nx = x + ex, ny = y + ey, nz = z + ez;
+                        const bool in = nx >= 1 && ny >= 1 && nz >= 1 && nx + ny + nz <= n - 1;
+                        if (!in) { bad += owner[q] != -1; continue; }
+                        const int o = owner[q];
+                        if (o < 0 || owner_t[q] != t + dt) { ++bad; continue; }
+                        const LaneDev& M = h->lanes[o];
+                        if (M.v != ny + nz || M.w != nz || h->blocks[o / LANES].tet != B.tet) ++bad;
+                    }
+            }
+        }
+        // dataflow halo rows: forward (pred) and backward (succ)
+        for (int dir = 0; dir < 2; ++dir)
+            for (int hl = 0; hl < 17; ++hl) {
+                int64_t rp;
+                int prod;
+                if (dir == 0) {
+                    if (hl < 8) { rp = h->lanes[b * LANES + hl * 8].rp[R_VM]; prod = B.pred[0]; }
+                    else if (hl < 16) { rp = h->lanes[b * LANES + (hl - 8)].rp[R_WM]; prod = B.pred[1]; }
+                    else { rp = h->lanes[b * LANES].rp[R_VMWM]; prod = B.pred[2]; }
+                } else {
+                    if (hl < 8) { rp = h->lanes[b * LANES + hl * 8 + 7].rp[R_VP]; prod = B.succ[0]; }
+                    else if (hl < 16) { rp = h->lanes[b * LANES + 56 + (hl - 8)].rp[R_WP]; prod = B.succ[1]; }
+                    else { rp = h->lanes[b * LANES + 63].rp[R_VPWP]; prod = B.succ[2]; }
+                }
+                if (prod < 0) { bad += rp != 0; continue; }
+                const BlockDev& PB = h->blocks[prod];
+                for (int sl = PB.tb; sl <= PB.te; ++sl) {
+                    const int64_t q = rp + (int64_t)LANES * sl;
+                    if (q < 0 || q >= S) { ++bad; continue; }
+                    if (rp != 0 && (q < PB.base || q >= PB.base + (int64_t)PB.len * LANES)) ++bad;
+                    if (owner[q] >= 0 && owner[q] / LANES != prod) ++bad;
+                }
+            }
+    }
+    // topological orders
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<int32_t> ord = topo_order(h->blocks, dir == 0);
+        if (ord.size() != h->blocks.size()) { ++bad; continue; }
+        std::vector<int> pos(ord.size());
+        for (size_t k = 0; k < ord.size(); ++k) pos[ord[k]] = (int)k;
+        for (size_t b = 0; b < h->blocks.size(); ++b)
+            for (int k = 0; k < 3; ++k) {
+                const int p = dir == 0 ? h->blocks[b].pred[k] : h->blocks[b].succ[k];
+                if (p >= 0 && pos[p] >= pos[b]) ++bad;
+            }
+    }
+    // sample indices: every sample point maps to a distinct slot of its simplex
+    if (h->variant != ILU_STORED_F64) {
+        static const int fd[8][3] = {{-1, 0, 0}, {0, -1, 0}, {1, -1, 0}, {-1, 1, -1},
+                                     {0, 1, -1}, {0, 0, -1}, {1, 0, -1}, {0, 0, 0}};
+        for (const TetDev& T : h->tets)
+            for (int f = 0; f < NFIT; ++f) {
+                std::vector<char> hit(T.samp_cnt[f], 0);
+                const int st = T.stride, M = T.samp_M[f];
+                const int sx = 1 - std::min(fd[f][0], 0), sy = 1 - std::min(fd[f][1], 0), sz = 1 - std::min(fd[f][2], 0);
+                for (int z = 1; z <= T.n - 3; ++z)
+                    for (int y = 1; y <= T.n - 2 - z; ++y)
+                        for (int x = 1; x <= T.n - 1 - y - z; ++x) {
+                            if ((x - sx) % st || (y - sy) % st || (z - sz) % st) continue;
+                            const int qx = x + fd[f][0], qy = y + fd[f][1], qz = z + fd[f][2];
+                            if (!(qx >= 1 && qy >= 1 && qz >= 1 && qx + qy + qz <= T.n - 1)) continue;
+                            const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
+                            const int64_t Mz = M - kz;
+                            const int64_t si = choose3_h(M + 3) - choose3_h(M + 3 - kz) + (int64_t)ky * (Mz + 1) -
+                                               (int64_t)ky * (ky - 1) / 2 + kx;
+                            if (si < 0 || si >= T.samp_cnt[f] || hit[si]) ++bad;
+                            else hit[si] = 1;
+                        }
+                for (char c : hit) bad += !c;
+            }
+    }
+    return bad;
+}
+
+void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
+    if (h->schedule == ILU_SCHED_PLANE) {
+        for (int t = h->tmin; t <= h->tmax; ++t) launch_fwd_plane(c, h->variant, t, st);
+    } else {
+        const Flow f = h->flow();
+        launch_flow_reset(c, f, st);
+        launch_fwd_flow(c, f, h->variant, st);
+    }
+}
+
+void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
+    if (h->schedule == ILU_SCHED_PLANE) {
+        for (int t = h->tmax; t >= h->tmin; --t) launch_bwd_plane(c, h->variant, t, h->xs.as<double>(), st);
+    } else {
+        const Flow f = h->flow();
+        launch_flow_reset(c, f, st);
+        launch_bwd_flow(c, f, h->variant, h->xs.as<double>(), st);
+    }
+}
+
+double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
+    double v = 0.0;
+    *err = hipMemcpyAsync(&v, h->norms.as<double>() + slot, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+           hipStreamSynchronize(st) != hipSuccess;
+    return v;
+}
+
+}  // namespace
+
+namespace {
+int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
+    if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_SURR_F32) return ILU_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (opts->reserved[k]) return ILU_EINVAL;
+    if (opts->variant != ILU_STORED_F64) {
+        for (int k = 0; k < 3; ++k)
+            if (opts->degree[k] < 0 || opts->degree[k] > 6) return ILU_EINVAL;
+        if (opts->sample_stride < 0 || (opts->sample_stride & (opts->sample_stride - 1))) return ILU_EINVAL;
+    }
+    for (int i = 0; i < ntets; ++i) {
+        if (tets[i].level < 2 || tets[i].level > 10) return ILU_EINVAL;
+        if (tets[i].coeff_kind < 0 || tets[i].coeff_kind > 3) return ILU_EINVAL;
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (!std::isfinite(tets[i].vertex[a][b])) return ILU_EINVAL;
+    }
+    return ILU_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* ilu_strerror(int code) {
+    switch (code) {
+    case ILU_OK: return "success";
+    case ILU_EINVAL: return "invalid argument";
+    case ILU_ENOMEM: return "device allocation failed";
+    case ILU_EHIP: return "HIP runtime error";
+    case ILU_EBREAKDOWN: return "ILU(0) breakdown: non-positive pivot";
+    case ILU_ERANK: return "rank-deficient least-squares problem";
+    case ILU_EGEOM: return "degenerate or inverted tetrahedron";
+    case ILU_ENOTCONV: return "relative residual tolerance not reached";
+    default: return "unknown error";
+    }
+}
+
+int ilu_setup_surrogate(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, void* hip_stream,
+                        ilu_handle_t* out) {
+    if (!tets || !opts || !out || ntets <= 0) return ILU_EINVAL;
+    *out = nullptr;
+    if (int e = validate_args(tets, ntets, opts)) return e;
+    ilu_handle_t h = new (std::nothrow) ilu_handle_s();
+    if (!h) return ILU_ENOMEM;
+    const int rc = setup_impl(tets, ntets, opts, (hipStream_t)hip_stream, h);
+    if (rc != ILU_OK) {
+        hipStreamSynchronize((hipStream_t)hip_stream);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return ILU_OK;
+}
+
+int ilu_check_layout(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, int64_t* violations) {
+    if (!tets || !opts || !violations || ntets <= 0) return ILU_EINVAL;
+    if (int e = validate_args(tets, ntets, opts)) return e;
+    ilu_handle_t h = new (std::nothrow) ilu_handle_s();
+    if (!h) return ILU_ENOMEM;
+    int64_t ns = 0;
+    int rc = prepare(tets, ntets, opts, h, &ns);
+    if (rc == ILU_OK) *violations = check_layout(h);
+    delete h;
+    return rc;
+}
+
+int ilu_destroy(ilu_handle_t h) {
+    if (!h) return ILU_OK;
+    hipDeviceSynchronize();
+    delete h;
+    return ILU_OK;
+}
+
+int ilu_layout(ilu_handle_t h, int32_t tet, int64_t* offset, int64_t* count_interior) {
+    if (!h || tet < 0 || tet >= h->ntets) return ILU_EINVAL;
+    if (offset) *offset = h->tets[tet].lex_off;
+    if (count_interior) *count_interior = h->tets[tet].N;
+    return ILU_OK;
+}
+
+int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, double rel_tol, double* relres_out,
+               void* hip_stream) {
+    if (!h || !x || !b || nsweeps < 0 || !(rel_tol >= 0.0)) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Ctx c = h->ctx();
+    const bool f32 = h->variant == ILU_SURR_F32;
+    launch_permute(c, 1, 1, x, h->xs.as<double>(), h->S, 1, -1, st);
+    launch_permute(c, 1, 1, b, h->bs.as<double>(), h->S, 1, -1, st);
+    HIPCHK(hipGetLastError());
+    const bool want_norm = rel_tol > 0.0 || relres_out;
+    double bn = 1.0;
+    int err = 0;
+    if (want_norm) {
+        launch_sumsq(c, h->bs.as<double>(), h->partial.as<double>(), st);
+        launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 0, st);
+        bn = std::sqrt(host_norm(h, 0, st, &err));
+        if (err) return ILU_EHIP;
+        if (bn == 0.0) bn = 1.0;
+    }
+    double rel = -1.0;
+    bool converged = false;
+    if (h->kernel_timing && (int)h->kev.size() < 4 * nsweeps) {
+        const size_t old = h->kev.size();
+        h->kev.resize(4 * (size_t)nsweeps, nullptr);
+        for (size_t i = old; i < h->kev.size(); ++i) HIPCHK(hipEventCreate(&h->kev[i]));
+    }
+    auto mark = [&](int k, int i) -> hipError_t {
+        if (h->kernel_timing) return hipEventRecord(h->kev[4 * (size_t)k + i], st);
+        if (k == 0) return hipEventRecord(h->ev[2 + i], st);
+        return hipSuccess;
+    };
+    int done = 0;
+    HIPCHK(hipEventRecord(h->ev[0], st));
+    for (int k = 0; k < nsweeps; ++k) {
+        HIPCHK(mark(k, 0));
+        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1,
+                        rel_tol > 0.0 ? h->partial.as<double>() : nullptr, st);
+        HIPCHK(mark(k, 1));
+        if (rel_tol > 0.0) {
+            launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 1, st);
+            rel = std::sqrt(host_norm(h, 1, st, &err)) / bn;
+            if (err) return ILU_EHIP;
+            if (rel <= rel_tol) {
+                converged = true;
+                break;
+            }
+            HIPCHK(mark(k, 1));
+        }
+        sweep_fwd(h, c, st);
+        HIPCHK(mark(k, 2));
+        sweep_bwd(h, c, st);
+        HIPCHK(mark(k, 3));
+        ++done;
+    }
+    HIPCHK(hipEventRecord(h->ev[1], st));
+    HIPCHK(hipGetLastError());
+    h->have_timing = done > 0;
+    h->kev_sweeps = h->kernel_timing ? done : (done > 0 ? 1 : 0);
+    if (want_norm && !converged) {
+        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1, h->partial.as<double>(), st);
+        launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 1, st);
+        rel = std::sqrt(host_norm(h, 1, st, &err)) / bn;
+        if (err) return ILU_EHIP;
+        converged = rel <= rel_tol;
+    }
+    if (relres_out) *relres_out = rel;
+    launch_permute(c, 0, 1, h->xs.as<double>(), x, h->S, 1, -1, st);
+    HIPCHK(hipGetLastError());
+    if (h->schedule != ILU_SCHED_PLANE) {
+        int32_t fl[4];
+        if (int e = read_flags(h, st, fl)) return e;
+        if (fl[2]) return ILU_EHIP;  // a dataflow wait exceeded its bound
+    }
+    if (rel_tol > 0.0 && !converged) return ILU_ENOTCONV;
+    return ILU_OK;
+}
+
+int stencil_apply(ilu_handle_t h, const double* x, double* y, void* hip_stream) {
+    if (!h || !x || !y) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Ctx c = h->ctx();
+    launch_permute(c, 1, 1, x, h->xs.as<double>(), h->S, 1, -1, st);
+    // y = A x in FP64 (the residual kernel with subtract = 0), stored in bs
+    launch_residual(c, h->xs.as<double>(), nullptr, h->bs.as<double>(), false, 0, nullptr, st);
+    launch_permute(c, 0, 1, h->bs.as<double>(), y, h->S, 1, -1, st);
+    HIPCHK(hipGetLastError());
+    return ILU_OK;
+}
+
+int ilu_get_stencil(ilu_handle_t h, int32_t tet, double* A_out, void* hip_stream) {
+    if (!h || !A_out || tet < 0 || tet >= h->ntets) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    DevBuf full, a8;
+    if (full.alloc((size_t)15 * h->S * sizeof(double), st) || a8.alloc((size_t)8 * h->S * sizeof(double), st))
+        return ILU_ENOMEM;
+    const Ctx c = h->ctx();
+    launch_assemble(c, a8.as<double>(), full.as<double>(), st);
+    launch_permute(c, 0, 15, full.as<double>(), A_out, h->S, 15, tet, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_get_factors(ilu_handle_t h, int32_t tet, double* L_out, double* D_out, void* hip_stream) {
+    if (!h || tet < 0 || tet >= h->ntets || h->variant != ILU_STORED_F64) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Ctx c = h->ctx();
+    if (L_out) launch_permute(c, 0, 7, h->Lf.as<double>(), L_out, h->S, 7, tet, st);
+    if (D_out) launch_permute(c, 0, 1, h->Df.as<double>(), D_out, h->S, 1, tet, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_get_surrogate(ilu_handle_t h, int32_t tet, double* coeffs_out) {
+    if (!h || !coeffs_out || tet < 0 || tet >= h->ntets || h->variant == ILU_STORED_F64) return ILU_EINVAL;
+    std::memcpy(coeffs_out, h->coef_h.data() + (size_t)tet * NFIT * h->K, (size_t)NFIT * h->K * sizeof(double));
+    return ILU_OK;
+}
+
+int ilu_set_surrogate(ilu_handle_t h, int32_t tet, const double* coeffs, void* hip_stream) {
+    if (!h || !coeffs || tet < 0 || tet >= h->ntets || h->variant == ILU_STORED_F64) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::memcpy(h->coef_h.data() + (size_t)tet * NFIT * h->K, coeffs, (size_t)NFIT * h->K * sizeof(double));
+    HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double), hipMemcpyHostToDevice,
+                          st));
+    if (int e = build_tables(h, st)) return e;
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double* L_out, double* Dinv_out, void* hip_stream) {
+    if (!h || tet < 0 || tet >= h->ntets || h->variant == ILU_STORED_F64) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    launch_export_surrogate(h->ctx(), h->variant == ILU_SURR_F32, tet, L_out, Dinv_out, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_sample_stride(ilu_handle_t h, int32_t tet, int32_t* stride_out) {
+    if (!h || !stride_out || tet < 0 || tet >= h->ntets) return ILU_EINVAL;
+    *stride_out = h->tets[tet].stride;
+    return ILU_OK;
+}
+
+int ilu_last_timing(ilu_handle_t h, double* sweep_ms, double* fwd_kernel_ms, double* bwd_kernel_ms,
+                    double* res_kernel_ms) {
+    if (!h || !h->have_timing) return ILU_EINVAL;
+    float a = 0;
+    HIPCHK(hipEventSynchronize(h->ev[1]));
+    HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+    double f = 0, b = 0, r = 0;
+    const int ns = h->kev_sweeps;
+    for (int k = 0; k < ns; ++k) {
+        hipEvent_t* e = h->kernel_timing ? &h->kev[4 * (size_t)k] : &h->ev[2];
+        float t01 = 0, t12 = 0, t23 = 0;
+        HIPCHK(hipEventElapsedTime(&t01, e[0], e[1]));
+        HIPCHK(hipEventElapsedTime(&t12, e[1], e[2]));
+        HIPCHK(hipEventElapsedTime(&t23, e[2], e[3]));
+        r += t01;
+        f += t12;
+        b += t23;
+    }
+    if (sweep_ms) *sweep_ms = a;
+    if (fwd_kernel_ms) *fwd_kernel_ms = ns ? f / ns : 0.0;
+    if (bwd_kernel_ms) *bwd_kernel_ms = ns ? b / ns : 0.0;
+    if (res_kernel_ms) *res_kernel_ms = ns ? r / ns : 0.0;
+    return ILU_OK;
+}
+
+int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable) {
+    if (!h) return ILU_EINVAL;
+    h->kernel_timing = enable != 0;
+    return ILU_OK;
+}
+
+}  // extern "C"

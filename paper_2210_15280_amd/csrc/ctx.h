@@ -1,0 +1,30 @@
+// Launch context shared by the host code and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ilu_internal.h"
+
+namespace ilu {
+
+constexpr int RES_T = 64;  // hyperplanes per workgroup in the point-parallel kernels
+
+struct Ctx {
+    const TetDev* tets = nullptr;
+    const BlockDev* blocks = nullptr;
+    const LaneDev* lanes = nullptr;
+    int nblocks = 0;
+    int res_chunks = 0;      // ceil(max block window / RES_T)
+    int64_t S = 0;           // stream length (elements)
+    const double* A8 = nullptr;   // [8][S]: centre, then lower weights w..be
+    const double* Lf = nullptr;   // [7][S] stored forward weights
+    const double* Lb = nullptr;   // [8][S] stored backward weights (1/D, L^{p-d}_d)
+    const double* tab64 = nullptr;
+    const float* tab32 = nullptr;
+    int NC = 0;                   // dg_x + 1
+    void* r = nullptr;            // residual stream (FP64, or FP32 for the mixed variant)
+    void* w = nullptr;            // substitution stream (same type as r)
+};
+
+}  // namespace ilu

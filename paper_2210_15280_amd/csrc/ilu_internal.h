@@ -1,0 +1,73 @@
+// Internal definitions shared by the host code and the HIP kernels of libilu.
+//
+// Lattice of one macro-tetrahedron (Sec. 2.1): interior points (x,y,z) with
+// x,y,z >= 1 and x+y+z <= n-1, n = 2^L.  The kernels work in the skewed
+// coordinates
+//     u = x + y + z,   v = y + z,   w = z,
+// in which all seven lower stencil offsets of D_l have non-negative
+// components, and the hyperplane index of the wavefront schedule is
+//     t = x + 2y + 3z = u + v + w.
+// A "row" is a fixed (v, w), i.e. a fixed (y, z); it runs along x (= along u).
+// Rows are tiled into 8 x 8 blocks in (v, w); one wavefront of 64 lanes owns
+// one block, lane = 8 (w - W0) + (v - V0).
+//
+// Stream layout.  Every per-point array (x, b, r, w, stencil and factor
+// arrays) is stored block by block; inside a block the element of lane l at
+// hyperplane t sits at  base + (t - tlo) * 64 + l.  A lane's row pointer is
+// rp = base - tlo * 64 + l, so point (row, t) lives at rp + 64 t.  At a fixed
+// t the 64 lanes of a block are contiguous: every access of the sweep kernels
+// is one coalesced 512 B (FP64) or 256 B (FP32) transaction.  Block windows
+// are padded by PAD zero steps on both sides so that neighbour reads of
+// interior points never leave their block; rows outside the lattice point to
+// the zero region at the start of every stream.
+#pragma once
+
+#include <stdint.h>
+
+namespace ilu {
+
+constexpr int BV = 8;       // block extent in v
+constexpr int BW = 8;       // block extent in w
+constexpr int LANES = 64;   // rows per block = wavefront size
+constexpr int PAD = 2;      // zero steps on each side of a block window
+constexpr int NDIR = 15;
+constexpr int NLOW = 7;
+
+// Lane row-pointer slots: own row and the six neighbour rows in (v, w).
+enum RowSlot { R_SELF = 0, R_VM = 1, R_WM = 2, R_VMWM = 3, R_VP = 4, R_WP = 5, R_VPWP = 6 };
+
+struct TetDev {
+    int32_t level, n, kind, stride;
+    double v0[3];        // base vertex v1
+    double J[9];         // J[3*r + c]: column c = d_{c+1} = v_{c+2} - v1
+    double cp[4];        // coefficient parameters
+    int64_t lex_off;     // offset of this tet in user vectors
+    int64_t N;           // interior points
+    int32_t blk0, nblk;  // block range in the global block table
+    int32_t deg[3];      // surrogate degrees
+    int32_t ncoef;       // (dg_x+1)(dg_y+1)(dg_z+1)
+    int32_t samp_M[8];   // sample simplex side per fitted direction (0..6 lower, 7 = c)
+    int64_t samp_off[8]; // offset of each direction's samples in the sample buffer
+    int64_t samp_cnt[8];
+};
+
+struct BlockDev {
+    int32_t tet, V0, W0;
+    int32_t tb, te;      // first / last hyperplane with an active lane
+    int32_t tlo;         // tb - PAD: time origin of the block's storage
+    int32_t len;         // te - tb + 1 + 2 PAD stored steps
+    int32_t pred[3];     // forward-sweep predecessors: (V-1,W), (V,W-1), (V-1,W-1); -1 if none
+    int32_t succ[3];     // backward-sweep predecessors: (V+1,W), (V,W+1), (V+1,W+1)
+    int32_t pad_;
+    int64_t base;        // stream index of (tlo, lane 0)
+};
+
+struct LaneDev {
+    int64_t rp[7];       // row pointers, RowSlot order; zero-region pointer if the row is outside
+    int32_t v, w;        // row coordinates; v = 0 marks an unused lane
+};
+
+// Fitted directions: 0..6 = lower directions of D_l, 7 = centre (fits 1/D).
+constexpr int NFIT = 8;
+
+}  // namespace ilu

@@ -1,0 +1,31 @@
+// Launchers of the setup kernels.
+#pragma once
+
+#include "ctx.h"
+
+namespace ilu {
+
+struct QrJob {
+    int64_t in_off;   // level 0: offset of the samples; later levels: row offset in the input
+    int64_t in_rows;  // rows of this problem at this level
+    int64_t out_off;  // row offset of this problem's R factors in the output
+    int32_t tet, fit; // problem = (tetrahedron, fitted direction)
+    int32_t chunk0;   // first global chunk id of this problem
+    int32_t nchunk;
+};
+
+void launch_assemble(const Ctx& c, double* A8, double* Afull, hipStream_t st);
+void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags, hipStream_t st);
+void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st);
+void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st);
+void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
+                      const double* samples, const double* in, double* out, double* scratch, int grid, int nchunks,
+                      hipStream_t st);
+void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st);
+void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, double* tab, float* tab32, hipStream_t st);
+// mode 0: stream -> lexicographic, mode 1: lexicographic -> stream
+void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,
+                    int only_tet, hipStream_t st);
+
+
+}  // namespace ilu

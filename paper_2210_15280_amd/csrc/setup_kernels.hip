@@ -1,0 +1,572 @@
+// Setup kernels of libilu: stencil assembly, ILU(0) factorisation by the
+// stencil recurrences, factor transposition, sampling on S_d, FP64 TSQR
+// least squares and the per-row surrogate evaluation tables.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "kernels_common.h"
+#include "setup_kernels.h"
+
+namespace ilu {
+
+// ---------------------------------------------------------------- assembly
+
+__device__ double kappa_at(const TetDev& T, double X, double Y, double Z) {
+    const double two_pi = 6.283185307179586476925286766559;
+    const double* p = T.cp;
+    switch (T.kind) {
+    case 0: return p[0];
+    case 1: return p[0] + p[1] * sin(two_pi * p[2] * X) * sin(two_pi * p[2] * Y) * sin(two_pi * p[2] * Z);
+    case 2: return exp(p[0] * sin(two_pi * p[2] * X) * cos(two_pi * p[2] * Y));
+    default: {
+        int i = (int)p[2];
+        return p[0] + p[1] * (pow(X, (double)i) + pow(Y, (double)i) + pow(Z, (double)i));
+    }
+    }
+}
+
+// Slot in the 15-point stencil (listing order w,s,se,bnw,bn,bc,be,c,e,n,nw,tse,ts,tc,tw)
+// of a lattice offset with components in {-1,0,1}; -1 if it is not a stencil offset.
+__device__ int stencil_slot(int dx, int dy, int dz) {
+    if (dz == -1) {
+        if (dy == 0 && dx == 0) return 5;    // bc
+        if (dy == 0 && dx == 1) return 6;    // be
+        if (dy == 1 && dx == -1) return 3;   // bnw
+        if (dy == 1 && dx == 0) return 4;    // bn
+        return -1;
+    }
+    if (dz == 0) {
+        if (dy == -1 && dx == 0) return 1;   // s
+        if (dy == -1 && dx == 1) return 2;   // se
+        if (dy == 0 && dx == -1) return 0;   // w
+        if (dy == 0 && dx == 0) return 7;    // c
+        if (dy == 0 && dx == 1) return 8;    // e
+        if (dy == 1 && dx == 0) return 9;    // n
+        if (dy == 1 && dx == -1) return 10;  // nw
+        return -1;
+    }
+    if (dy == -1 && dx == 1) return 11;      // tse
+    if (dy == -1 && dx == 0) return 12;      // ts
+    if (dy == 0 && dx == 0) return 13;       // tc
+    if (dy == 0 && dx == -1) return 14;      // tw
+    return -1;
+}
+
+// One thread per (block, lane, hyperplane): gather the 24 micro-tetrahedra
+// around p and sum their P1 element stiffness rows (Sec. 2.1).  The micro-mesh
+// is the Kuhn subdivision in (a,b,c) = (x, x+y, x+y+z): the simplices
+// containing P are q + {0, e_s1, e_s1+e_s2, (1,1,1)} with P one of the four
+// vertices.  Writes the centre and the seven lower weights (entries whose
+// neighbour is on the macro boundary are stored as 0: the restricted matrix
+// drops them), slot order [c, w, s, se, bnw, bn, bc, be].
+__global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                           const LaneDev* __restrict__ lanes, int nblocks, int64_t S, double* __restrict__ A8,
+                           double* __restrict__ Afull /* optional [15][S] */) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const BlockDev B = blocks[b];
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    if (Ln.v == 0) return;
+    const TetDev& T = tets[B.tet];
+    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
+    const double invn = 1.0 / n;
+    static constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
+        const int x = t - 2 * v - w;  // x = u - v, u = t - v - w
+        if (x < 1 || x > n - 1 - v) continue;
+        double Ad[15];
+        for (int s = 0; s < 15; ++s) Ad[s] = 0.0;
+        const int P[3] = {x, x + y, x + y + z};
+        for (int sg = 0; sg < 6; ++sg) {
+            int off[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
+            off[1][perm[sg][0]] = 1;
+            off[2][perm[sg][0]] = 1;
+            off[2][perm[sg][1]] = 1;
+            for (int k = 0; k < 4; ++k) {
+                // vertices (logical xyz) of the simplex whose k-th vertex is p
+                int lx[4], ly[4], lz[4];
+                for (int j = 0; j < 4; ++j) {
+                    const int a = P[0] - off[k][0] + off[j][0];
+                    const int bb = P[1] - off[k][1] + off[j][1];
+                    const int c = P[2] - off[k][2] + off[j][2];
+                    lx[j] = a;
+                    ly[j] = bb - a;
+                    lz[j] = c - bb;
+                }
+                // physical edge matrix E (columns X_j - X_0) = J (l_j - l_0) / n
+                double E[3][3], cen[3];
+                for (int r = 0; r < 3; ++r) {
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const int ex = lx[cc + 1] - lx[0], ey = ly[cc + 1] - ly[0], ez = lz[cc + 1] - lz[0];
+                        E[r][cc] = (T.J[3 * r] * ex + T.J[3 * r + 1] * ey + T.J[3 * r + 2] * ez) * invn;
+                    }
+                    const double mx = 0.25 * (lx[0] + lx[1] + lx[2] + lx[3]);
+                    const double my = 0.25 * (ly[0] + ly[1] + ly[2] + ly[3]);
+                    const double mz = 0.25 * (lz[0] + lz[1] + lz[2] + lz[3]);
+                    cen[r] = T.v0[r] + (T.J[3 * r] * mx + T.J[3 * r + 1] * my + T.J[3 * r + 2] * mz) * invn;
+                }
+                const double c00 = E[1][1] * E[2][2] - E[1][2] * E[2][1];
+                const double c01 = E[1][2] * E[2][0] - E[1][0] * E[2][2];
+                const double c02 = E[1][0] * E[2][1] - E[1][1] * E[2][0];
+                const double det = E[0][0] * c00 + E[0][1] * c01 + E[0][2] * c02;
+                const double id = 1.0 / det;
+                // rows of E^{-1} are the gradients of lambda_1..3
+                double g[4][3];
+                g[1][0] = c00 * id;
+                g[1][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) * id;
+                g[1][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) * id;
+                g[2][0] = c01 * id;
+                g[2][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) * id;
+                g[2][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) * id;
+                g[3][0] = c02 * id;
+                g[3][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) * id;
+                g[3][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) * id;
+                for (int r = 0; r < 3; ++r) g[0][r] = -(g[1][r] + g[2][r] + g[3][r]);
+                const double scale = kappa_at(T, cen[0], cen[1], cen[2]) * fabs(det) / 6.0;
+                for (int j = 0; j < 4; ++j) {
+                    const double kij = scale * (g[k][0] * g[j][0] + g[k][1] * g[j][1] + g[k][2] * g[j][2]);
+                    const int sl = stencil_slot(lx[j] - lx[k], ly[j] - ly[k], lz[j] - lz[k]);
+                    Ad[sl] += kij;
+                }
+            }
+        }
+        const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        A8[idx] = Ad[7];
+        for (int s = 0; s < NLOW; ++s) {
+            const bool in = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
+            A8[(int64_t)(1 + s) * S + idx] = in ? Ad[s] : 0.0;
+        }
+        if (Afull) {
+            for (int s = 0; s < 15; ++s) {
+                const int dx = s < 7 ? low_dx(s) : s == 7 ? 0 : -low_dx(s - 8);
+                const int dy = s < 7 ? low_dy(s) : s == 7 ? 0 : -low_dy(s - 8);
+                const int dz = s < 7 ? low_dz(s) : s == 7 ? 0 : -low_dz(s - 8);
+                const bool in = (s == 7) || interior(n, x + dx, y + dy, z + dz);
+                Afull[(int64_t)s * S + idx] = in ? Ad[s] : 0.0;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ factorisation
+
+// One launch per hyperplane t (every point of a hyperplane only depends on
+// earlier hyperplanes).  For each active point p solves the stencil equations
+// of Sec. 3 (eq. matrix-equations) in the order of Alg. 1 -- bc, s, bnw, be,
+// w, bn, se, then the pivot c -- from the already factored lower neighbours.
+// Neighbours that are not interior contribute L = 0, D = 1 (the guard values
+// of Alg. 1).  Factors are written to Lf[7][S] (lower weights) and Df[S].
+// The first point with D <= 0 is reported through flags[0].
+__global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                               const LaneDev* __restrict__ lanes, int t_glob, int64_t S, const double* __restrict__ A8,
+                               double* __restrict__ Lf, double* __restrict__ Df, int* __restrict__ flags) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const BlockDev& B = blocks[b];
+    const int t = t_glob;
+    if (t < B.tb || t > B.te) return;
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    if (Ln.v == 0) return;
+    const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w;
+    const int x = t - 2 * v - w;
+    if (x < 1 || x > n - 1 - v) return;
+    const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+
+    // neighbour positions, interior flags, pivots
+    int64_t q[NLOW];
+    bool in[NLOW];
+    double Dn[NLOW];
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) {
+        q[s] = Ln.rp[low_row(s)] + (int64_t)LANES * (t + low_dt(s));
+        in[s] = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
+        Dn[s] = in[s] ? Df[q[s]] : 1.0;
+    }
+    auto Lq = [&](int s, int d) -> double { return in[s] ? Lf[(int64_t)d * S + q[s]] : 0.0; };
+    enum { W_ = 0, S_ = 1, SE = 2, BNW = 3, BN = 4, BC = 5, BE = 6 };
+    double a[NLOW];
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) a[s] = A8[(int64_t)(1 + s) * S + idx];
+    const double Lbc = a[BC] / Dn[BC];
+    const double Ls = (a[S_] - Lbc * Dn[BC] * Lq(S_, BN)) / Dn[S_];
+    const double Lbnw = (a[BNW] - Lbc * Dn[BC] * Lq(BNW, SE)) / Dn[BNW];
+    const double Lbe = (a[BE] - Lbc * Dn[BC] * Lq(BE, W_)) / Dn[BE];
+    const double Lw = (a[W_] - Lbc * Dn[BC] * Lq(W_, BE) - Lbnw * Dn[BNW] * Lq(W_, BN) - Ls * Dn[S_] * Lq(W_, SE)) /
+                      Dn[W_];
+    const double Lbn = (a[BN] - Lbc * Dn[BC] * Lq(BN, S_) - Lbe * Dn[BE] * Lq(BN, SE) - Lbnw * Dn[BNW] * Lq(BN, W_)) /
+                       Dn[BN];
+    const double Lse = (a[SE] - Lbc * Dn[BC] * Lq(SE, BNW) - Lbe * Dn[BE] * Lq(SE, BN) - Ls * Dn[S_] * Lq(SE, W_)) /
+                       Dn[SE];
+    const double Dp = A8[idx] - Lbc * Lbc * Dn[BC] - Lbe * Lbe * Dn[BE] - Lbnw * Lbnw * Dn[BNW] -
+                      Lbn * Lbn * Dn[BN] - Lse * Lse * Dn[SE] - Ls * Ls * Dn[S_] - Lw * Lw * Dn[W_];
+    const double Lp[NLOW] = {Lw, Ls, Lse, Lbnw, Lbn, Lbc, Lbe};
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) Lf[(int64_t)s * S + idx] = in[s] ? Lp[s] : 0.0;
+    Df[idx] = Dp;
+    if (!(Dp > 0.0)) atomicOr(&flags[0], 1);
+}
+
+// Backward-sweep weights per point: Lb[0] = 1/D^p, Lb[1+s] = L^{p-d_s}_{d_s}
+// (the transposed factor, read from the upper neighbour; 0 if that neighbour
+// is not interior).
+__global__ void k_transpose_factors(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                    const LaneDev* __restrict__ lanes, int64_t S, const double* __restrict__ Lf,
+                                    const double* __restrict__ Df, double* __restrict__ Lb) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const BlockDev B = blocks[b];
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    if (Ln.v == 0) return;
+    const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w;
+    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
+        const int x = t - 2 * v - w;
+        if (x < 1 || x > n - 1 - v) continue;
+        const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        Lb[idx] = 1.0 / Df[idx];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s) {
+            const bool in = interior(n, x - low_dx(s), y - low_dy(s), z - low_dz(s));
+            const int64_t qq = Ln.rp[up_row(s)] + (int64_t)LANES * (t + up_dt(s));
+            Lb[(int64_t)(1 + s) * S + idx] = in ? Lf[(int64_t)s * S + qq] : 0.0;
+        }
+    }
+}
+
+// ----------------------------------------------------------------- sampling
+
+// Sample sets (Sec. 4.1, reading of the garbled formula): p interior,
+// p = shift_d (mod stride) componentwise with shift_d = 1 - min(d, 0), and
+// p + d interior.  With k = (p - shift)/stride the set is the lattice simplex
+// {k >= 0, k_x + k_y + k_z <= M_d}; sample k is stored at its lexicographic
+// position (k_z slowest).  Values: L^p_d for the lower directions, 1/D^p for c.
+__device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz) {
+    // points with k_z' < k_z: C(M+3,3) - C(M+3-kz,3)
+    const int64_t Mz = M - kz;  // layer side
+    return choose3(M + 3) - choose3(M + 3 - kz) + (int64_t)ky * (Mz + 1) - (int64_t)ky * (ky - 1) / 2 + kx;
+}
+
+__global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                 const LaneDev* __restrict__ lanes, int64_t S, const double* __restrict__ Lf,
+                                 const double* __restrict__ Df, double* __restrict__ samples) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const BlockDev B = blocks[b];
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    if (Ln.v == 0) return;
+    const TetDev& T = tets[B.tet];
+    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w, st = T.stride;
+    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
+        const int x = t - 2 * v - w;
+        if (x < 1 || x > n - 1 - v) continue;
+        const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        for (int f = 0; f < NFIT; ++f) {
+            const int dx = f < NLOW ? low_dx(f) : 0, dy = f < NLOW ? low_dy(f) : 0, dz = f < NLOW ? low_dz(f) : 0;
+            const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
+            if ((x - sx) % st || (y - sy) % st || (z - sz) % st) continue;
+            if (!interior(n, x + dx, y + dy, z + dz)) continue;
+            const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
+            const int64_t si = simplex_index(T.samp_M[f], kx, ky, kz);
+            samples[T.samp_off[f] + si] = f < NLOW ? Lf[(int64_t)f * S + idx] : 1.0 / Df[idx];
+        }
+    }
+}
+
+// ------------------------------------------------------------ least squares
+
+// Householder QR of one chunk of rows, one workgroup per chunk, FP64.
+// The chunk is copied into the workgroup's row-major scratch (rows x m,
+// zero-padded), reduced in place, and its m x m triangular factor R is
+// written as m rows of the output.  Level 0 builds its rows from the samples
+// ([basis values | sample value]); later levels read stacked R factors.
+// Stacking the R factors of the chunks and factoring again yields the R of
+// the whole least-squares matrix (TSQR).
+
+
+__global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ tets, const QrJob* __restrict__ jobs,
+                                                   int njobs, int level0, int m, int chunk_rows,
+                                                   const double* __restrict__ samples, const double* __restrict__ in,
+                                                   double* __restrict__ out, double* __restrict__ scratch_all,
+                                                   int nchunks_total) {
+    extern __shared__ double sh[];  // reduction scratch
+    for (int cid = blockIdx.x; cid < nchunks_total; cid += gridDim.x) {
+        // locate job
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (jobs[mid].chunk0 <= cid) lo = mid; else hi = mid - 1;
+        }
+        const QrJob J = jobs[lo];
+        const int c = cid - J.chunk0;
+        double* A = scratch_all + (int64_t)blockIdx.x * chunk_rows * m;
+        const int64_t r0 = (int64_t)c * chunk_rows;
+        const int nr = (int)min<int64_t>(chunk_rows, J.in_rows - r0);
+        // fill
+        if (level0) {
+            const TetDev& T = tets[J.tet];
+            const int K = m - 1;
+            const int dgx = T.deg[0], dgy = T.deg[1], dgz = T.deg[2];
+            const int M = T.samp_M[J.fit];
+            const int dx = J.fit < NLOW ? low_dx(J.fit) : 0, dy = J.fit < NLOW ? low_dy(J.fit) : 0,
+                      dz = J.fit < NLOW ? low_dz(J.fit) : 0;
+            const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
+            const double invn = 1.0 / T.n;
+            for (int r = threadIdx.x; r < chunk_rows; r += blockDim.x) {
+                double* row = A + (int64_t)r * m;
+                if (r >= nr) {
+                    for (int k = 0; k < m; ++k) row[k] = 0.0;
+                    continue;
+                }
+                // decode the lexicographic simplex index back to k
+                int64_t si = r0 + r;
+                int kz = 0;
+                while (choose3(M + 3) - choose3(M + 3 - (kz + 1)) <= si) ++kz;
+                si -= choose3(M + 3) - choose3(M + 3 - kz);
+                const int Mz = M - kz;
+                int ky = 0;
+                while ((int64_t)(ky + 1) * (Mz + 1) - (int64_t)(ky + 1) * ky / 2 <= si) ++ky;
+                si -= (int64_t)ky * (Mz + 1) - (int64_t)ky * (ky - 1) / 2;
+                const int kx = (int)si;
+                const double X = (sx + T.stride * kx) * invn, Y = (sy + T.stride * ky) * invn,
+                             Z = (sz + T.stride * kz) * invn;
+                double px[9], py[9], pz[9];
+                legendre(2 * X - 1, dgx, px);
+                legendre(2 * Y - 1, dgy, py);
+                legendre(2 * Z - 1, dgz, pz);
+                int col = 0;
+                for (int kk = 0; kk <= dgz; ++kk)
+                    for (int j = 0; j <= dgy; ++j)
+                        for (int i = 0; i <= dgx; ++i) row[col++] = px[i] * py[j] * pz[kk];
+                row[K] = samples[J.in_off + r0 + r];
+            }
+        } else {
+            for (int64_t e = threadIdx.x; e < (int64_t)chunk_rows * m; e += blockDim.x) {
+                const int r = (int)(e / m), k = (int)(e % m);
+                A[e] = r < nr ? in[(J.in_off + r0 + r) * m + k] : 0.0;
+            }
+        }
+        __syncthreads();
+        const int rows = chunk_rows;
+        for (int j = 0; j < m && j < rows; ++j) {
+            // sigma = sum_{i > j} A[i][j]^2
+            double part = 0.0;
+            for (int i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) {
+                const double a = A[(int64_t)i * m + j];
+                part += a * a;
+            }
+            sh[threadIdx.x] = part;
+            __syncthreads();
+            for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+                if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+                __syncthreads();
+            }
+            const double sigma = sh[0];
+            const double alpha = A[(int64_t)j * m + j];
+            __syncthreads();
+            if (sigma == 0.0) continue;  // column already reduced: H = I
+            const double nrm = sqrt(alpha * alpha + sigma);
+            const double beta = alpha > 0.0 ? -nrm : nrm;
+            const double tau = (beta - alpha) / beta;
+            const double scl = 1.0 / (alpha - beta);
+            for (int i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) A[(int64_t)i * m + j] *= scl;
+            __syncthreads();
+            // apply H = I - tau v v^T (v_j = 1) to the trailing columns, one thread per column
+            for (int k = j + 1 + threadIdx.x; k < m; k += blockDim.x) {
+                double dot0 = A[(int64_t)j * m + k], dot1 = 0.0;
+                int i = j + 1;
+                for (; i + 1 < rows; i += 2) {
+                    dot0 += A[(int64_t)i * m + j] * A[(int64_t)i * m + k];
+                    dot1 += A[(int64_t)(i + 1) * m + j] * A[(int64_t)(i + 1) * m + k];
+                }
+                if (i < rows) dot0 += A[(int64_t)i * m + j] * A[(int64_t)i * m + k];
+                const double wk = tau * (dot0 + dot1);
+                A[(int64_t)j * m + k] -= wk;
+                for (int ii = j + 1; ii < rows; ++ii) A[(int64_t)ii * m + k] -= wk * A[(int64_t)ii * m + j];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) A[(int64_t)j * m + j] = beta;
+            __syncthreads();
+        }
+        // write R (upper triangle, zeros below)
+        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+            const int r = (int)(e / m), k = (int)(e % m);
+            out[(J.out_off + (int64_t)c * m + r) * m + k] = (k >= r && r < rows) ? A[(int64_t)r * m + k] : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Back substitution R[:K,:K] c = R[:K,K] for every problem (one thread each),
+// with a rank test on the diagonal of R.
+__global__ void k_qr_solve(const QrJob* __restrict__ jobs, int njobs, int m, const double* __restrict__ Rall,
+                           double* __restrict__ coef, int* __restrict__ flags) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= njobs) return;
+    const QrJob J = jobs[p];
+    const double* R = Rall + J.out_off * m;
+    const int K = m - 1;
+    double dmax = 0.0, dmin = INFINITY;
+    for (int i = 0; i < K; ++i) {
+        const double d = fabs(R[(int64_t)i * m + i]);
+        dmax = fmax(dmax, d);
+        dmin = fmin(dmin, d);
+    }
+    double* c = coef + ((int64_t)J.tet * NFIT + J.fit) * K;
+    if (!(dmin > 1e-15 * dmax)) {
+        atomicOr(&flags[1], 1);
+        for (int i = 0; i < K; ++i) c[i] = 0.0;
+        return;
+    }
+    for (int i = K - 1; i >= 0; --i) {
+        double s = R[(int64_t)i * m + K];
+        for (int j = i + 1; j < K; ++j) s -= R[(int64_t)i * m + j] * c[j];
+        c[i] = s / R[(int64_t)i * m + i];
+    }
+}
+
+// ------------------------------------------------------- evaluation tables
+
+// Per row (y, z) and per sweep, the surrogate restricted to the row as a
+// polynomial in eta = (x - xm) / hw, the row's x-range [1, n-1-y-z] mapped to
+// [-1, 1]:  coefficients of eta^0..eta^dgx (Horner in the sweeps).
+//   forward table  [7][NC]: L_d at (x, y, z)                 (d in D_l)
+//   backward table [8][NC]: 1/D at (x, y, z), then L_d at p - d
+// Row record layout: [xm, 1/hw, fwd 7*NC, bwd 8*NC].
+__global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                             const LaneDev* __restrict__ lanes, int nslots, const double* __restrict__ coef,
+                             int NC, double* __restrict__ tab, float* __restrict__ tab32) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= nslots) return;
+    const LaneDev& Ln = lanes[slot];
+    const int rec = 2 + 15 * NC;
+    double* o = tab + (int64_t)slot * rec;
+    if (Ln.v == 0) {
+        for (int k = 0; k < rec; ++k) o[k] = 0.0;
+        if (tab32)
+            for (int k = 0; k < rec; ++k) tab32[(int64_t)slot * rec + k] = 0.f;
+        return;
+    }
+    const BlockDev& B = blocks[slot / LANES];
+    const TetDev& T = tets[B.tet];
+    const int n = T.n, y = Ln.v - Ln.w, z = Ln.w;
+    const int dgx = T.deg[0], dgy = T.deg[1], dgz = T.deg[2];
+    const int K = (dgx + 1) * (dgy + 1) * (dgz + 1);
+    const double xlo = 1.0, xhi = n - 1 - Ln.v;
+    const double xm = 0.5 * (xlo + xhi);
+    const double hw = xhi > xlo ? 0.5 * (xhi - xlo) : 1.0;
+    o[0] = xm;
+    o[1] = 1.0 / hw;
+    for (int e = 0; e < 15; ++e) {
+        // entry e < 7: forward L_e at own row; e == 7: 1/D; e > 7: L_{e-8} at p - d
+        const int fit = e < 7 ? e : e == 7 ? 7 : e - 8;
+        int sx = 0, sy = 0, sz = 0;
+        if (e > 7) { sx = low_dx(e - 8); sy = low_dy(e - 8); sz = low_dz(e - 8); }
+        const double* a = coef + ((int64_t)B.tet * NFIT + fit) * K;
+        double py[9], pz[9];
+        legendre(2.0 * (y - sy) / n - 1.0, dgy, py);
+        legendre(2.0 * (z - sz) / n - 1.0, dgz, pz);
+        double cx[9];
+        for (int i = 0; i <= dgx; ++i) cx[i] = 0.0;
+        for (int kk = 0; kk <= dgz; ++kk)
+            for (int j = 0; j <= dgy; ++j) {
+                const double wgt = py[j] * pz[kk];
+                for (int i = 0; i <= dgx; ++i) cx[i] += a[(kk * (dgy + 1) + j) * (dgx + 1) + i] * wgt;
+            }
+        // s = 2 (x - sx)/n - 1 = alpha + beta eta
+        const double alpha = 2.0 * (xm - sx) / n - 1.0, beta = 2.0 * hw / n;
+        double Pm1[9], P0[9], P1[9], out[9];
+        for (int i = 0; i < 9; ++i) { Pm1[i] = 0.0; P0[i] = 0.0; out[i] = 0.0; }
+        P0[0] = 1.0;  // P_0
+        for (int i = 0; i <= dgx; ++i) out[i] = 0.0;
+        out[0] += cx[0];
+        if (dgx >= 1) {
+            for (int i = 0; i < 9; ++i) { Pm1[i] = P0[i]; P0[i] = 0.0; }
+            P0[0] = alpha;
+            P0[1] = beta;  // P_1
+            for (int i = 0; i <= 1; ++i) out[i] += cx[1] * P0[i];
+            for (int k = 1; k < dgx; ++k) {
+                // P_{k+1} = ((2k+1) s P_k - k P_{k-1}) / (k+1)
+                for (int i = 0; i < 9; ++i) P1[i] = -k * Pm1[i];
+                for (int i = 0; i <= k; ++i) {
+                    P1[i] += (2 * k + 1) * alpha * P0[i];
+                    P1[i + 1] += (2 * k + 1) * beta * P0[i];
+                }
+                for (int i = 0; i < 9; ++i) { P1[i] /= (k + 1); Pm1[i] = P0[i]; P0[i] = P1[i]; }
+                for (int i = 0; i <= k + 1; ++i) out[i] += cx[k + 1] * P0[i];
+            }
+        }
+        for (int i = 0; i < NC; ++i) o[2 + e * NC + i] = i <= dgx ? out[i] : 0.0;
+    }
+    if (tab32)
+        for (int k = 0; k < rec; ++k) tab32[(int64_t)slot * rec + k] = (float)o[k];
+}
+
+// ------------------------------------------------------------ lex <-> stream
+
+// mode 0: stream -> lex (dst[lex] = src[stream]); mode 1: lex -> stream.
+// Stencil/factor exports use `count` arrays spaced `sstride` / `lstride` apart.
+__global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                          const LaneDev* __restrict__ lanes, int mode, int count, const double* __restrict__ src,
+                          double* __restrict__ dst, int64_t sstride, int lmul, int only_tet) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const BlockDev B = blocks[b];
+    if (only_tet >= 0 && B.tet != only_tet) return;
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    if (Ln.v == 0) return;
+    const TetDev& T = tets[B.tet];
+    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
+    const int64_t lexbase = only_tet >= 0 ? 0 : T.lex_off;
+    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
+        const int x = t - 2 * v - w;
+        if (x < 1 || x > n - 1 - v) continue;
+        const int64_t si = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        const int64_t li = lexbase + lex_index(n, x, y, z);
+        for (int k = 0; k < count; ++k) {
+            if (mode == 0) dst[li * lmul + k] = src[k * sstride + si];
+            else dst[k * sstride + si] = src[li * lmul + k];
+        }
+    }
+}
+
+}  // namespace ilu
+
+namespace ilu {
+
+void launch_assemble(const Ctx& c, double* A8, double* Afull, hipStream_t st) {
+    k_assemble<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S, A8, Afull);
+}
+
+void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags, hipStream_t st) {
+    k_factor_plane<<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, c.A8, Lf, Df, flags);
+}
+
+void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st) {
+    k_transpose_factors<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, Lf, Df, Lb);
+}
+
+void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st) {
+    k_gather_samples<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, Lf, Df, samples);
+}
+
+void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
+                      const double* samples, const double* in, double* out, double* scratch, int grid, int nchunks,
+                      hipStream_t st) {
+    k_qr_chunks<<<grid, 256, 256 * sizeof(double), st>>>(c.tets, jobs, njobs, level0, m, chunk_rows, samples, in, out,
+                                                         scratch, nchunks);
+}
+
+void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st) {
+    k_qr_solve<<<(njobs + 63) / 64, 64, 0, st>>>(jobs, njobs, m, R, coef, flags);
+}
+
+void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, double* tab, float* tab32, hipStream_t st) {
+    k_row_tables<<<(nslots + 127) / 128, 128, 0, st>>>(c.tets, c.blocks, c.lanes, nslots, coef, NC, tab, tab32);
+}
+
+void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,
+                    int only_tet, hipStream_t st) {
+    k_permute<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, mode, count, src, dst, sstride, lmul, only_tet);
+}
+
+
+}  // namespace ilu

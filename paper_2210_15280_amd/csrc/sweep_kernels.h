@@ -1,0 +1,31 @@
+// Launchers of the per-sweep kernels.
+#pragma once
+
+#include "ctx.h"
+
+namespace ilu {
+
+void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
+                     hipStream_t st);
+void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st);
+void launch_reduce(const double* partial, int64_t count, double* out, int slot, hipStream_t st);
+void launch_fwd_plane(const Ctx& c, int variant, int t, hipStream_t st);
+void launch_bwd_plane(const Ctx& c, int variant, int t, double* x, hipStream_t st);
+// surrogate weights of one tetrahedron in lexicographic order: L_out [N][7], Dinv_out [N]
+void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, double* Dinv_out, hipStream_t st);
+
+// persistent dataflow schedule (dataflow_kernels.hip)
+struct Flow {
+    const int32_t* order_fwd = nullptr;  // block ids in a topological order of the forward sweep
+    const int32_t* order_bwd = nullptr;  // ... and of the backward sweep
+    int32_t* progress = nullptr;         // [nblocks] last finished hyperplane + 1 (0 = not started)
+    int32_t* ticket = nullptr;           // [2] work counters
+    int32_t* flags = nullptr;            // [4] error flags (flags[2]: wait limit hit)
+    int grid = 0;                        // resident workgroups
+};
+void launch_flow_reset(const Ctx& c, const Flow& f, hipStream_t st);
+void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st);
+void launch_bwd_flow(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st);
+int flow_max_resident(int variant, int NC);
+
+}  // namespace ilu

@@ -1,0 +1,271 @@
+// Per-sweep kernels of libilu: FP64 residual (stencil matvec), the forward
+// and backward substitutions of Alg. 2 on the hyperplane schedule (one launch
+// per hyperplane t = x + 2y + 3z), and norm reductions.
+#include <hip/hip_runtime.h>
+
+#include "kernels_common.h"
+#include "sweep_kernels.h"
+
+namespace ilu {
+
+// ---------------------------------------------------------------- residual
+
+// r = b - A x on the interior (Sec. 2.1 stencil matvec, FP64).  The centre and
+// lower weights of p are stored at p; the upper weight A^p_{-d} equals the
+// lower weight A^{p-d}_d stored at the upper neighbour (symmetric form).
+// Neighbours on the macro boundary read stored zeros.  With `subtract` = 0 it
+// computes y = A x instead (r holds y, b is ignored).  One workgroup handles
+// 64 lanes x RES_T hyperplanes of one block; per-workgroup partial sums of r^2
+// go to `partial` (deterministic reduction afterwards).
+template <typename RT>
+__global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                                  const LaneDev* __restrict__ lanes, int64_t S,
+                                                  const double* __restrict__ A8, const double* __restrict__ x,
+                                                  const double* __restrict__ b, RT* __restrict__ r, int subtract,
+                                                  double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int sub = threadIdx.x >> 6;
+    const BlockDev& B = blocks[blk];
+    const LaneDev& Ln = lanes[(int64_t)blk * LANES + lane];
+    double acc2 = 0.0;
+    const int t0 = B.tb + (int)blockIdx.y * RES_T;
+    if (Ln.v != 0 && t0 <= B.te) {
+        const int n = tets[B.tet].n, v = Ln.v, w = Ln.w;
+        int64_t rpl[NLOW], rpu[NLOW];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s) {
+            rpl[s] = Ln.rp[low_row(s)] + (int64_t)LANES * low_dt(s);
+            rpu[s] = Ln.rp[up_row(s)] + (int64_t)LANES * up_dt(s);
+        }
+        const int t1 = min(B.te, t0 + RES_T - 1);
+        for (int t = t0 + sub; t <= t1; t += 4) {
+            const int xx = t - 2 * v - w;
+            if (xx < 1 || xx > n - 1 - v) continue;
+            const int64_t off = (int64_t)LANES * t;
+            const int64_t idx = Ln.rp[R_SELF] + off;
+            double acc = A8[idx] * x[idx];
+#pragma unroll
+            for (int s = 0; s < NLOW; ++s) {
+                acc += A8[(int64_t)(1 + s) * S + idx] * x[rpl[s] + off];
+                const int64_t qu = rpu[s] + off;
+                acc += A8[(int64_t)(1 + s) * S + qu] * x[qu];
+            }
+            const double rv = subtract ? b[idx] - acc : acc;
+            r[idx] = (RT)rv;
+            acc2 += rv * rv;
+        }
+    }
+    red[threadIdx.x] = acc2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && partial) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// sum of squares of a stream vector restricted to active points (for ||b||)
+__global__ void __launch_bounds__(256) k_sumsq(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                               const LaneDev* __restrict__ lanes, const double* __restrict__ v_s,
+                                               double* __restrict__ partial) {
+    __shared__ double red[256];
+    const int blk = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const BlockDev& B = blocks[blk];
+    const LaneDev& Ln = lanes[(int64_t)blk * LANES + lane];
+    double acc2 = 0.0;
+    const int t0 = B.tb + (int)blockIdx.y * RES_T;
+    if (Ln.v != 0 && t0 <= B.te) {
+        const int n = tets[B.tet].n;
+        const int t1 = min(B.te, t0 + RES_T - 1);
+        for (int t = t0 + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
+            const int xx = t - 2 * Ln.v - Ln.w;
+            if (xx < 1 || xx > n - 1 - Ln.v) continue;
+            const double a = v_s[Ln.rp[R_SELF] + (int64_t)LANES * t];
+            acc2 += a * a;
+        }
+    }
+    red[threadIdx.x] = acc2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+// out[slot] = sum of partial[0..count) (single workgroup, fixed order)
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partial, int64_t count,
+                                                double* __restrict__ out, int slot) {
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) a += partial[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[slot] = red[0];
+}
+
+// ------------------------------------------------- hyperplane-schedule sweeps
+
+// Surrogate weight of table entry e at eta (Horner; NC = dg_x + 1 coefficients).
+template <typename T>
+__device__ __forceinline__ T horner(const T* __restrict__ c, int NC, T eta) {
+    T acc = c[NC - 1];
+    for (int i = NC - 2; i >= 0; --i) acc = acc * eta + c[i];
+    return acc;
+}
+
+// Forward substitution on hyperplane t (Alg. 2, first loop, after the
+// residual):  w^p = r^p - sum_{d in D_l} L^p_d w^{p+d}.
+template <typename T, bool STORED>
+__global__ void __launch_bounds__(64) k_fwd_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                                  const LaneDev* __restrict__ lanes, int t, int64_t S,
+                                                  const double* __restrict__ Lf, const T* __restrict__ tab, int NC,
+                                                  const T* __restrict__ r, T* __restrict__ w) {
+    const int b = blockIdx.x;
+    const BlockDev& B = blocks[b];
+    if (t < B.tb || t > B.te) return;
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + threadIdx.x];
+    if (Ln.v == 0) return;
+    const int n = tets[B.tet].n, v = Ln.v;
+    const int x = t - 2 * v - Ln.w;
+    if (x < 1 || x > n - 1 - v) return;
+    const int64_t off = (int64_t)LANES * t;
+    const int64_t idx = Ln.rp[R_SELF] + off;
+    T acc = r[idx];
+    if (STORED) {
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s)
+            acc -= (T)Lf[(int64_t)s * S + idx] * w[Ln.rp[low_row(s)] + off + LANES * low_dt(s)];
+    } else {
+        const T* c = tab + ((int64_t)b * LANES + threadIdx.x) * (2 + 15 * NC);
+        const T eta = ((T)x - c[0]) * c[1];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s)
+            acc -= horner(c + 2 + s * NC, NC, eta) * w[Ln.rp[low_row(s)] + off + LANES * low_dt(s)];
+    }
+    w[idx] = acc;
+}
+
+// Backward substitution with the diagonal scaling and the update on
+// hyperplane t (Alg. 2, second loop):
+//   w^p = (D^p)^{-1} w^p - sum_{d in D_l} L^{p-d}_d w^{p-d};  x^p += w^p.
+template <typename T, bool STORED>
+__global__ void __launch_bounds__(64) k_bwd_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                                  const LaneDev* __restrict__ lanes, int t, int64_t S,
+                                                  const double* __restrict__ Lb, const T* __restrict__ tab, int NC,
+                                                  T* __restrict__ w, double* __restrict__ x) {
+    const int b = blockIdx.x;
+    const BlockDev& B = blocks[b];
+    if (t < B.tb || t > B.te) return;
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + threadIdx.x];
+    if (Ln.v == 0) return;
+    const int n = tets[B.tet].n, v = Ln.v;
+    const int xx = t - 2 * v - Ln.w;
+    if (xx < 1 || xx > n - 1 - v) return;
+    const int64_t off = (int64_t)LANES * t;
+    const int64_t idx = Ln.rp[R_SELF] + off;
+    T acc;
+    if (STORED) {
+        acc = w[idx] * (T)Lb[idx];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s)
+            acc -= (T)Lb[(int64_t)(1 + s) * S + idx] * w[Ln.rp[up_row(s)] + off + LANES * up_dt(s)];
+    } else {
+        const T* c = tab + ((int64_t)b * LANES + threadIdx.x) * (2 + 15 * NC);
+        const T eta = ((T)xx - c[0]) * c[1];
+        acc = w[idx] * horner(c + 2 + 7 * NC, NC, eta);
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s)
+            acc -= horner(c + 2 + (8 + s) * NC, NC, eta) * w[Ln.rp[up_row(s)] + off + LANES * up_dt(s)];
+    }
+    w[idx] = acc;
+    x[idx] += (double)acc;
+}
+
+// Surrogate weights exactly as the sweeps evaluate them, exported in
+// lexicographic order (inspection only).
+template <typename T>
+__global__ void k_export_surrogate(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                   const LaneDev* __restrict__ lanes, const T* __restrict__ tab, int NC, int only_tet,
+                                   double* __restrict__ L_out, double* __restrict__ Dinv_out) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const BlockDev B = blocks[b];
+    if (B.tet != only_tet) return;
+    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    if (Ln.v == 0) return;
+    const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w;
+    const T* c = tab + ((int64_t)b * LANES + lane) * (2 + 15 * NC);
+    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
+        const int x = t - 2 * v - w;
+        if (x < 1 || x > n - 1 - v) continue;
+        const int64_t li = lex_index(n, x, y, z);
+        const T eta = ((T)x - c[0]) * c[1];
+        if (L_out)
+            for (int s = 0; s < NLOW; ++s) L_out[li * NLOW + s] = (double)horner(c + 2 + s * NC, NC, eta);
+        if (Dinv_out) Dinv_out[li] = (double)horner(c + 2 + 7 * NC, NC, eta);
+    }
+}
+
+// ------------------------------------------------------------- host launchers
+
+void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, double* Dinv_out, hipStream_t st) {
+    if (f32)
+        k_export_surrogate<float><<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.tab32, c.NC, tet, L_out,
+                                                             Dinv_out);
+    else
+        k_export_surrogate<double><<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.tab64, c.NC, tet, L_out,
+                                                              Dinv_out);
+}
+
+void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
+                     hipStream_t st) {
+    dim3 grid(c.nblocks, c.res_chunks);
+    if (f32)
+        k_residual<float><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, c.A8, x, b, (float*)r, subtract, partial);
+    else
+        k_residual<double><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, c.A8, x, b, (double*)r, subtract,
+                                                  partial);
+}
+
+void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st) {
+    dim3 grid(c.nblocks, c.res_chunks);
+    k_sumsq<<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, v, partial);
+}
+
+void launch_reduce(const double* partial, int64_t count, double* out, int slot, hipStream_t st) {
+    k_reduce<<<1, 256, 0, st>>>(partial, count, out, slot);
+}
+
+void launch_fwd_plane(const Ctx& c, int variant, int t, hipStream_t st) {
+    if (variant == 0)
+        k_fwd_plane<double, true><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, c.Lf, nullptr, 0,
+                                                            (const double*)c.r, (double*)c.w);
+    else if (variant == 1)
+        k_fwd_plane<double, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab64, c.NC,
+                                                             (const double*)c.r, (double*)c.w);
+    else
+        k_fwd_plane<float, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab32, c.NC,
+                                                            (const float*)c.r, (float*)c.w);
+}
+
+void launch_bwd_plane(const Ctx& c, int variant, int t, double* x, hipStream_t st) {
+    if (variant == 0)
+        k_bwd_plane<double, true><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, c.Lb, nullptr, 0,
+                                                            (double*)c.w, x);
+    else if (variant == 1)
+        k_bwd_plane<double, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab64, c.NC,
+                                                             (double*)c.w, x);
+    else
+        k_bwd_plane<float, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab32, c.NC,
+                                                            (float*)c.w, x);
+}
+
+}  // namespace ilu

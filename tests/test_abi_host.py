@@ -1,0 +1,86 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol include/ilu.h declares, and rejects bad arguments before any
+device work (geometry, level, degree, rank of the sampled problems)."""
+import ctypes
+import os
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2210_15280_amd as pkg
+    if not os.path.exists(pkg.library_path()):
+        from paper_2210_15280_amd import build
+        build.build()
+    pkg.lib()
+    return pkg
+
+
+def test_header_symbols_exported(P):
+    names = P.header_symbols()
+    for must in ("ilu_setup_surrogate", "ilu_smooth", "stencil_apply", "ilu_layout", "ilu_destroy",
+                 "ilu_strerror", "ilu_get_stencil", "ilu_get_factors", "ilu_get_surrogate",
+                 "ilu_set_surrogate", "ilu_get_surrogate_values", "ilu_sample_stride", "ilu_last_timing"):
+        assert must in names
+    assert P.exported_symbols() == names
+
+
+def test_strerror(P):
+    L = P.lib()
+    assert L.ilu_strerror(0) == b"success"
+    assert b"breakdown" in L.ilu_strerror(-4)
+    assert L.ilu_strerror(-99) == b"unknown error"
+
+
+def _setup(P, tets, variant=0, degree=(4, 4, 4), stride=4, reserved=0):
+    from paper_2210_15280_amd._lib import ilu_opts, ilu_tet_desc
+    arr = (ilu_tet_desc * len(tets))()
+    for i, t in enumerate(tets):
+        arr[i].vertex[:] = [c for row in t.verts for c in row]
+        arr[i].level = t.level
+        arr[i].coeff_kind = t.coeff_kind
+        arr[i].coeff_param[:] = list(t.coeff_params)
+    o = ilu_opts()
+    o.variant = variant
+    o.degree[:] = list(degree)
+    o.sample_stride = stride
+    o.reserved[0] = reserved
+    h = ctypes.c_void_p()
+    return P.lib().ilu_setup_surrogate(arr, len(tets), ctypes.byref(o), None, ctypes.byref(h))
+
+
+def test_inverted_tet_is_rejected(P):
+    t = W.make_tet(1, 4, W.COEFF_CONST, (1.0,))
+    v = list(t.verts)
+    v[1], v[2] = v[2], v[1]  # swap two vertices: det J < 0
+    bad = W.Tet(tuple(v), 4, 0, (1.0, 0, 0, 0), t.rhs_state)
+    assert _setup(P, [bad]) == -6
+    flat = W.Tet(((0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0)), 4, 0, (1.0, 0, 0, 0), 0)
+    assert _setup(P, [flat]) == -6
+
+
+def test_invalid_arguments(P):
+    t = W.make_tet(1, 4, W.COEFF_CONST, (1.0,))
+    assert _setup(P, [W.Tet(t.verts, 1, 0, (1.0, 0, 0, 0), 0)]) == -1      # level < 2
+    assert _setup(P, [W.Tet(t.verts, 11, 0, (1.0, 0, 0, 0), 0)]) == -1     # level > 10
+    assert _setup(P, [W.Tet(t.verts, 4, 9, (1.0, 0, 0, 0), 0)]) == -1      # coefficient kind
+    assert _setup(P, [t], variant=1, degree=(7, 7, 7)) == -1                 # degree
+    assert _setup(P, [t], variant=1, stride=3) == -1                         # stride not a power of two
+    assert _setup(P, [t], reserved=1) == -1
+    assert _setup(P, [t], variant=5) == -1
+    L = P.lib()
+    assert L.ilu_smooth(None, None, None, 1, 0.0, None, None) == -1
+    assert L.stencil_apply(None, None, None, None) == -1
+    assert L.ilu_destroy(None) == 0
+
+
+def test_rank_deficient_sampling_is_rejected(P):
+    # level 3 has 7 intervals per edge: no stride leaves a sample simplex of side
+    # >= 12 for degree 4, so every LSQ problem is rank deficient
+    t = W.make_tet(1, 3, W.COEFF_CONST, (1.0,))
+    assert _setup(P, [t], variant=1, degree=(4, 4, 4)) == -5
