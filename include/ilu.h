@@ -113,6 +113,10 @@ int ilu_destroy(ilu_handle_t h);
 /* Static message for an error code. */
 const char *ilu_strerror(int code);
 
+/* Detail of the last ILU_EHIP failure on the calling thread (the HIP call
+ * and its error name); empty if none. */
+const char *ilu_last_error(void);
+
 /* ---- inspection (tests and diagnostics; all synchronous on hip_stream) ---- */
 
 /* Assembled stencil of tetrahedron `tet` in lexicographic order: A_out is a

@@ -31,7 +31,9 @@ class ilu_opts(ctypes.Structure):
 class ILUError(RuntimeError):
     def __init__(self, code: int, what: str):
         self.code = code
-        super().__init__("%s: %s (%d)" % (what, lib().ilu_strerror(code).decode(), code))
+        detail = lib().ilu_last_error().decode() if code == -3 else ""
+        super().__init__("%s: %s (%d)%s" % (what, lib().ilu_strerror(code).decode(), code,
+                                            " [" + detail + "]" if detail else ""))
 
 
 _lib = None
@@ -55,6 +57,8 @@ def lib():
         L.ilu_destroy.argtypes = [P]
         L.ilu_strerror.argtypes = [ctypes.c_int]
         L.ilu_strerror.restype = ctypes.c_char_p
+        L.ilu_last_error.argtypes = []
+        L.ilu_last_error.restype = ctypes.c_char_p
         L.ilu_get_stencil.argtypes = [P, I32, P, P]
         L.ilu_get_factors.argtypes = [P, I32, P, P, P]
         L.ilu_get_surrogate.argtypes = [P, I32, P]

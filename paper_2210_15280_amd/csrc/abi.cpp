@@ -6,12 +6,14 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <queue>
+#include <utility>
 #include <vector>
 
-#include "../../include/ilu.h"
+#include "ilu.h"
 #include "ctx.h"
 #include "setup_kernels.h"
 #include "sweep_kernels.h"
@@ -20,9 +22,28 @@ using namespace ilu;
 
 namespace {
 
+// Owning device buffer (move-only: a copy would free the same pointer twice).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf& operator=(DevBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    void swap(DevBuf& o) noexcept {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
     ~DevBuf() { release(); }
     void release() {
         if (p) hipFree(p);
@@ -114,9 +135,17 @@ struct ilu_handle_s {
 
 namespace {
 
-#define HIPCHK(x)                                  \
-    do {                                           \
-        if ((x) != hipSuccess) return ILU_EHIP;    \
+thread_local char g_last_error[256] = "";
+
+int hip_fail(hipError_t e, const char* what, int line) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s failed: %s (abi.cpp:%d)", what, hipGetErrorName(e), line);
+    return ILU_EHIP;
+}
+
+#define HIPCHK(x)                                            \
+    do {                                                     \
+        const hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__); \
     } while (0)
 
 // Sample sets S_d as lattice simplices of side M (see the sampling kernel).
@@ -322,7 +351,7 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st) {
                                       (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, st));
             }
         }
-        std::swap(in, out);
+        in.swap(out);
         level0 = false;
     }
     // solve
@@ -654,6 +683,8 @@ int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts)
 }  // namespace
 
 extern "C" {
+
+const char* ilu_last_error(void) { return g_last_error; }
 
 const char* ilu_strerror(int code) {
     switch (code) {

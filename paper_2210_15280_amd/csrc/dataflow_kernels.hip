@@ -59,21 +59,25 @@ struct Halo {
     int ptb = 0, pte = 0;
 };
 
-// Wait until block `prod` has finished hyperplane `slot` (forward order:
-// slots tb..; backward: te downwards).  Returns false if the wait bound hit.
-__device__ __forceinline__ bool wait_done(const int32_t* progress, int prod, int need_count, int32_t* flags) {
+// Wait until block `prod` has published at least `need` finished hyperplanes.
+// `known` caches the last value observed, so most calls return at once.
+// A wait that exceeds the bound (or a bound hit anywhere else) gives up.
+__device__ __forceinline__ void wait_progress(const int32_t* progress, int prod, int need, int& known,
+                                              int32_t* flags) {
+    if (known >= need) return;
     long spins = 0;
-    while (ld_dev(&progress[prod]) < need_count) {
+    int v = ld_dev(&progress[prod]);
+    while (v < need) {
         __builtin_amdgcn_s_sleep(1);
         ++spins;
-        // a failed wait anywhere makes every later wait give up at once
-        if ((spins & 1023) == 0 && ld_dev(&flags[2])) return false;
+        if ((spins & 1023) == 0 && ld_dev(&flags[2])) break;
         if (spins > SPIN_LIMIT) {
             atomicOr(&flags[2], 1);
-            return false;
+            break;
         }
+        v = ld_dev(&progress[prod]);
     }
-    return true;
+    known = v;
 }
 
 }  // namespace
@@ -138,16 +142,17 @@ __global__ void __launch_bounds__(64) k_fwd_flow(const TetDev* __restrict__ tets
         for (int i = lane; i < RING * GRIDC; i += 64) ring[i] = (T)0;
         __syncthreads();
         const int tb = B.tb, te = B.te;
-        // prologue: halo slots tb-3 .. tb+H-2
+        // prologue: halo slots tb-3 .. tb+H-2 (one wait for the furthest slot)
         T hreg[H];
+        int known = 0, pending = 0;
         if (hl.cell >= 0) {
+            if (hl.prod >= 0) {
+                const int smax = min(tb + H - 2, hl.pte);
+                if (smax >= hl.ptb) wait_progress(progress, hl.prod, smax - hl.ptb + 1, known, flags);
+            }
             for (int s = tb - 3; s <= tb + H - 2; ++s) {
-                T val = (T)0;
-                if (hl.prod >= 0 && s >= hl.ptb && s <= hl.pte) {
-                    wait_done(progress, hl.prod, s - hl.ptb + 1, flags);
-                    val = ld_dev(&w[hl.rp + (int64_t)LANES * s]);
-                }
-                ring[(s & (RING - 1)) * GRIDC + hl.cell] = val;
+                const bool ld = hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
+                ring[(s & (RING - 1)) * GRIDC + hl.cell] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
             }
         }
         // operand prefetch registers for the current batch
@@ -173,15 +178,20 @@ __global__ void __launch_bounds__(64) k_fwd_flow(const TetDev* __restrict__ tets
             }
             // issue halo loads for the next batch: slots T0+H-1 .. T0+2H-2
             if (hl.cell >= 0) {
+                const bool more = T0 + H <= te;
+                if (hl.prod >= 0 && more) {
+                    known = max(known, pending);
+                    const int smax = min(T0 + 2 * H - 2, hl.pte);
+                    if (smax >= hl.ptb) wait_progress(progress, hl.prod, smax - hl.ptb + 1, known, flags);
+                }
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
                     const int s = T0 + H - 1 + q;
-                    hreg[q] = (T)0;
-                    if (hl.prod >= 0 && s >= hl.ptb && s <= hl.pte && T0 + H <= te) {
-                        wait_done(progress, hl.prod, s - hl.ptb + 1, flags);
-                        hreg[q] = ld_dev(&w[hl.rp + (int64_t)LANES * s]);
-                    }
+                    const bool ld = more && hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
+                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
                 }
+                // refresh the producer's progress for the next batch (arrives with the batch)
+                if (hl.prod >= 0 && more) pending = ld_dev(&progress[hl.prod]);
             }
             // prefetch operands of the next batch
             T rnxt[H];
@@ -300,16 +310,17 @@ __global__ void __launch_bounds__(64) k_bwd_flow(const TetDev* __restrict__ tets
         for (int i = lane; i < RING * GRIDC; i += 64) ring[i] = (T)0;
         __syncthreads();
         const int tb = B.tb, te = B.te;
-        // prologue: halo slots te+3 .. te-H+2 (descending)
+        // prologue: halo slots te+3 .. te-H+2 (descending; one wait for the furthest slot)
         T hreg[H];
+        int known = 0, pending = 0;
         if (hl.cell >= 0) {
+            if (hl.prod >= 0) {
+                const int smin = max(te - H + 2, hl.ptb);
+                if (smin <= hl.pte) wait_progress(progress, hl.prod, hl.pte - smin + 1, known, flags);
+            }
             for (int s = te + 3; s >= te - H + 2; --s) {
-                T val = (T)0;
-                if (hl.prod >= 0 && s >= hl.ptb && s <= hl.pte) {
-                    wait_done(progress, hl.prod, hl.pte - s + 1, flags);
-                    val = ld_dev(&w[hl.rp + (int64_t)LANES * s]);
-                }
-                ring[(s & (RING - 1)) * GRIDC + hl.cell] = val;
+                const bool ld = hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
+                ring[(s & (RING - 1)) * GRIDC + hl.cell] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
             }
         }
         T wcur[H];
@@ -335,15 +346,19 @@ __global__ void __launch_bounds__(64) k_bwd_flow(const TetDev* __restrict__ tets
                 for (int q = 0; q < H; ++q) ring[((T0 + 1 - q) & (RING - 1)) * GRIDC + hl.cell] = hreg[q];
             }
             if (hl.cell >= 0) {
+                const bool more = T0 - H >= tb;
+                if (hl.prod >= 0 && more) {
+                    known = max(known, pending);
+                    const int smin = max(T0 - 2 * H + 2, hl.ptb);
+                    if (smin <= hl.pte) wait_progress(progress, hl.prod, hl.pte - smin + 1, known, flags);
+                }
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
                     const int s = T0 - H + 1 - q;
-                    hreg[q] = (T)0;
-                    if (hl.prod >= 0 && s >= hl.ptb && s <= hl.pte && T0 - H >= tb) {
-                        wait_done(progress, hl.prod, hl.pte - s + 1, flags);
-                        hreg[q] = ld_dev(&w[hl.rp + (int64_t)LANES * s]);
-                    }
+                    const bool ld = more && hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
+                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
                 }
+                if (hl.prod >= 0 && more) pending = ld_dev(&progress[hl.prod]);
             }
             T wnxt[H];
             double xnxt[H];
@@ -419,22 +434,23 @@ __global__ void k_flow_reset(int32_t* __restrict__ progress, int n, int32_t* __r
 
 // ------------------------------------------------------------------ launchers
 
-constexpr int H_F64 = 4;
-constexpr int H_F32 = 8;
+constexpr int H_F64 = 4;   // stored factors: 8 operands per step are prefetched
+constexpr int H_S64 = 8;   // FP64 surrogate
+constexpr int H_F32 = 16;  // FP32 surrogate
 
 template <int NC>
 struct FlowK {
     static const void* fwd(int variant) {
-        if (variant == 1) return (const void*)k_fwd_flow<double, false, H_F64, NC>;
+        if (variant == 1) return (const void*)k_fwd_flow<double, false, H_S64, NC>;
         return (const void*)k_fwd_flow<float, false, H_F32, NC>;
     }
     static const void* bwd(int variant) {
-        if (variant == 1) return (const void*)k_bwd_flow<double, false, H_F64, NC>;
+        if (variant == 1) return (const void*)k_bwd_flow<double, false, H_S64, NC>;
         return (const void*)k_bwd_flow<float, false, H_F32, NC>;
     }
     static void run_fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, H_F64, NC><<<f.grid, 64, 0, st>>>(
+            k_fwd_flow<double, false, H_S64, NC><<<f.grid, 64, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.r, (double*)c.w,
                 f.order_fwd, f.progress, f.ticket, f.flags);
         else
@@ -444,7 +460,7 @@ struct FlowK {
     }
     static void run_bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
         if (variant == 1)
-            k_bwd_flow<double, false, H_F64, NC><<<f.grid, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S,
+            k_bwd_flow<double, false, H_S64, NC><<<f.grid, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S,
                                                                         nullptr, c.tab64, (double*)c.w, x,
                                                                         f.order_bwd, f.progress, f.ticket, f.flags);
         else
