@@ -46,8 +46,9 @@ def kernel_flops(variant: str, dg: int):
 VARIANTS = {"stored_f64": 0, "surr_f64": 1, "surr_f32": 2}
 
 
-def run_variant(pkg, torch, wl, variant, steps, warmup):
+def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     kw = {} if variant == "stored_f64" else dict(degree=wl.degree, stride=wl.stride)
+    kw["tile"] = tile
     t0 = time.perf_counter()
     sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
     torch.cuda.synchronize()
@@ -138,6 +139,7 @@ def main():
     ap.add_argument("--workload", default="jit_L7_sin")
     ap.add_argument("--variants", default="surr_f32,stored_f64,surr_f64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile", default="auto", help="block shape BVxBW of the sweep schedule, e.g. 16x32")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -149,9 +151,10 @@ def main():
     pkg.lib()
     wl = W.workload(a.workload)
     variants = a.variants.split(",")
+    tile = (0, 0) if a.tile == "auto" else tuple(int(c) for c in a.tile.split("x"))
     results = {}
     for v in variants:
-        results[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup)
+        results[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
         print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, kernels %s" % (
             v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],
             json.dumps(results[v]["kernel_ms"])), file=sys.stderr, flush=True)

@@ -76,7 +76,10 @@ typedef struct ilu_opts {
     int32_t sample_stride;  /* stride of S_d (power of two); halved until every
                                sample set is unisolvent; 0 = 4 */
     int32_t schedule;       /* ILU_SCHED_* */
-    int32_t reserved[4];    /* must be 0 */
+    int32_t tile[2];        /* rows per block (BV, BW) of the sweep schedule in the
+                               skewed row coordinates (v, w) = (y+z, z): (8,8), (16,16)
+                               or (16,32); (0,0) = chosen from the levels */
+    int32_t reserved[2];    /* must be 0 */
 } ilu_opts;
 
 typedef struct ilu_handle_s *ilu_handle_t;

@@ -25,7 +25,7 @@ class ilu_tet_desc(ctypes.Structure):
 
 class ilu_opts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("degree", ctypes.c_int32 * 3), ("sample_stride", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("schedule", ctypes.c_int32), ("tile", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32 * 2)]
 
 
 class ILUError(RuntimeError):
@@ -109,7 +109,7 @@ class Smoother:
     in lexicographic order, concatenated (see ``offsets``)."""
 
     def __init__(self, tets: Sequence, variant: int = STORED_F64, degree=4, stride: int = 4,
-                 schedule: int = SCHED_AUTO, stream=None):
+                 schedule: int = SCHED_AUTO, tile=(0, 0), stream=None):
         import torch
         self.torch = torch
         self.L = lib()
@@ -127,6 +127,7 @@ class Smoother:
         opts.degree[:] = [int(d) for d in dg]
         opts.sample_stride = int(stride)
         opts.schedule = int(schedule)
+        opts.tile[:] = [int(tile[0]), int(tile[1])]
         self.variant = variant
         self.degree = dg
         self.h = ctypes.c_void_p()

@@ -75,6 +75,7 @@ struct ilu_handle_s {
     int schedule = 0;
     int deg[3] = {0, 0, 0};
     int NC = 0, K = 0;
+    int bv = 8, bw = 8;  // block shape in rows
     int64_t S = 0;
     int64_t nlex = 0;
     int tmin = 0, tmax = 0;
@@ -101,6 +102,10 @@ struct ilu_handle_s {
         c.blocks = blocks_d.as<BlockDev>();
         c.lanes = lanes_d.as<LaneDev>();
         c.nblocks = (int)blocks.size();
+        c.bv = bv;
+        c.bw = bw;
+        c.lpb = bv * bw;
+        c.groups = c.lpb / WAVE;
         c.S = S;
         int maxlen = 1;
         for (const auto& b : blocks) maxlen = std::max(maxlen, b.te - b.tb + 1);
@@ -160,29 +165,31 @@ int sample_side(int n, int fit, int stride) {
 }
 
 int build_layout(ilu_handle_t h) {
+    const int bv = h->bv, bw = h->bw, lpb = bv * bw;
     int nmax = 0;
     for (auto& T : h->tets) nmax = std::max(nmax, T.n);
-    const int64_t Z = (int64_t)LANES * (3 * nmax + 8);
+    const int64_t Z = (int64_t)lpb * (3 * nmax + 8);
     int64_t S = Z;
     std::vector<std::vector<int>> bmap(h->ntets);
-    std::vector<int> nbs(h->ntets);
+    std::vector<int> nbv(h->ntets), nbw(h->ntets);
     int64_t lexoff = 0;
     for (int ti = 0; ti < h->ntets; ++ti) {
         TetDev& T = h->tets[ti];
         const int n = T.n;
-        const int nb = std::max(1, (n - 3 + 7) / 8);
-        nbs[ti] = nb;
-        bmap[ti].assign((size_t)nb * nb, -1);
+        // rows: v in [2, n-2], w in [1, v-1]
+        nbv[ti] = std::max(1, (n - 3 + bv - 1) / bv);
+        nbw[ti] = std::max(1, (n - 3 + bw - 1) / bw);
+        bmap[ti].assign((size_t)nbv[ti] * nbw[ti], -1);
         T.blk0 = (int)h->blocks.size();
         T.lex_off = lexoff;
         T.N = choose3_h(n - 1);
         lexoff += T.N;
-        for (int bw = 0; bw < nb; ++bw)
-            for (int bv = 0; bv < nb; ++bv) {
-                const int V0 = 2 + 8 * bv, W0 = 1 + 8 * bw;
+        for (int kw = 0; kw < nbw[ti]; ++kw)
+            for (int kv = 0; kv < nbv[ti]; ++kv) {
+                const int V0 = 2 + bv * kv, W0 = 1 + bw * kw;
                 int tb = 1 << 30, te = -1;
-                for (int l = 0; l < LANES; ++l) {
-                    const int v = V0 + (l & 7), w = W0 + (l >> 3);
+                for (int l = 0; l < lpb; ++l) {
+                    const int v = V0 + l % bv, w = W0 + l / bv;
                     if (v > n - 2 || w > v - 1) continue;
                     tb = std::min(tb, 2 * v + w + 1);
                     te = std::max(te, n - 1 + v + w);
@@ -197,49 +204,48 @@ int build_layout(ilu_handle_t h) {
                 B.tlo = tb - PAD;
                 B.len = te - tb + 1 + 2 * PAD;
                 B.base = S;
-                S += (int64_t)B.len * LANES;
-                bmap[ti][(size_t)bv * nb + bw] = (int)h->blocks.size();
+                S += (int64_t)B.len * lpb;
+                bmap[ti][(size_t)kv * nbw[ti] + kw] = (int)h->blocks.size();
                 h->blocks.push_back(B);
             }
         T.nblk = (int)h->blocks.size() - T.blk0;
     }
     h->S = S;
     h->nlex = lexoff;
-    auto block_at = [&](int ti, int bv, int bw) -> int {
-        const int nb = nbs[ti];
-        if (bv < 0 || bw < 0 || bv >= nb || bw >= nb) return -1;
-        return bmap[ti][(size_t)bv * nb + bw];
+    auto block_at = [&](int ti, int kv, int kw) -> int {
+        if (kv < 0 || kw < 0 || kv >= nbv[ti] || kw >= nbw[ti]) return -1;
+        return bmap[ti][(size_t)kv * nbw[ti] + kw];
     };
     auto rp_of = [&](int ti, int v, int w) -> int64_t {
         const int n = h->tets[ti].n;
         if (v < 2 || v > n - 2 || w < 1 || w > v - 1) return 0;  // zero region
-        const int b = block_at(ti, (v - 2) / 8, (w - 1) / 8);
+        const int b = block_at(ti, (v - 2) / bv, (w - 1) / bw);
         const BlockDev& B = h->blocks[b];
-        const int l = (w - B.W0) * 8 + (v - B.V0);
-        return B.base - (int64_t)B.tlo * LANES + l;
+        const int l = (w - B.W0) * bv + (v - B.V0);
+        return B.base - (int64_t)B.tlo * lpb + l;
     };
-    h->lanes.resize(h->blocks.size() * LANES);
+    h->lanes.resize(h->blocks.size() * lpb);
     h->tmin = 1 << 30;
     h->tmax = 0;
     for (size_t bi = 0; bi < h->blocks.size(); ++bi) {
         BlockDev& B = h->blocks[bi];
         const int ti = B.tet, n = h->tets[ti].n;
-        const int bv = (B.V0 - 2) / 8, bw = (B.W0 - 1) / 8;
-        B.pred[0] = block_at(ti, bv - 1, bw);
-        B.pred[1] = block_at(ti, bv, bw - 1);
-        B.pred[2] = block_at(ti, bv - 1, bw - 1);
-        B.succ[0] = block_at(ti, bv + 1, bw);
-        B.succ[1] = block_at(ti, bv, bw + 1);
-        B.succ[2] = block_at(ti, bv + 1, bw + 1);
+        const int kv = (B.V0 - 2) / bv, kw = (B.W0 - 1) / bw;
+        B.pred[0] = block_at(ti, kv - 1, kw);
+        B.pred[1] = block_at(ti, kv, kw - 1);
+        B.pred[2] = block_at(ti, kv - 1, kw - 1);
+        B.succ[0] = block_at(ti, kv + 1, kw);
+        B.succ[1] = block_at(ti, kv, kw + 1);
+        B.succ[2] = block_at(ti, kv + 1, kw + 1);
         h->tmin = std::min(h->tmin, B.tb);
         h->tmax = std::max(h->tmax, B.te);
-        for (int l = 0; l < LANES; ++l) {
-            LaneDev& L = h->lanes[bi * LANES + l];
-            const int v = B.V0 + (l & 7), w = B.W0 + (l >> 3);
+        for (int l = 0; l < lpb; ++l) {
+            LaneDev& L = h->lanes[bi * lpb + l];
+            const int v = B.V0 + l % bv, w = B.W0 + l / bv;
             const bool valid = v <= n - 2 && w <= v - 1;
             L.v = valid ? v : 0;
             L.w = w;
-            L.rp[R_SELF] = valid ? B.base - (int64_t)B.tlo * LANES + l : 0;
+            L.rp[R_SELF] = valid ? B.base - (int64_t)B.tlo * lpb + l : 0;
             L.rp[R_VM] = rp_of(ti, v - 1, w);
             L.rp[R_WM] = rp_of(ti, v, w - 1);
             L.rp[R_VMWM] = rp_of(ti, v - 1, w - 1);
@@ -371,7 +377,7 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st) {
 }
 
 int build_tables(ilu_handle_t h, hipStream_t st) {
-    const int nslots = (int)h->blocks.size() * LANES;
+    const int nslots = (int)h->blocks.size() * h->bv * h->bw;
     const size_t rec = 2 + 15 * (size_t)h->NC;
     if (h->tab64.alloc(nslots * rec * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
     if (h->variant == ILU_SURR_F32 && h->tab32.alloc(nslots * rec * sizeof(float), st) != hipSuccess)
@@ -432,6 +438,18 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
             }
         }
     }
+    if (opts->tile[0] && opts->tile[1]) {
+        h->bv = opts->tile[0];
+        h->bw = opts->tile[1];
+    } else {
+        // larger blocks cut the number of cross-workgroup hops on the critical
+        // path of one big tetrahedron; many small ones keep 8 x 8 blocks
+        int lmax = 0;
+        for (const auto& T : h->tets) lmax = std::max(lmax, T.level);
+        h->bv = h->bw = 8;
+        if (ntets == 1 && lmax >= 8) { h->bv = 16; h->bw = 32; }
+        else if (ntets == 1 && lmax == 7) { h->bv = 16; h->bw = 16; }
+    }
     if (int e = build_layout(h)) return e;
     *nsamples = soff;
     return ILU_OK;
@@ -486,7 +504,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         h->w.alloc((size_t)S * es, st))
         return ILU_ENOMEM;
     const Ctx c = h->ctx();
-    h->npartial = (int64_t)c.nblocks * c.res_chunks;
+    h->npartial = (int64_t)c.nblocks * c.groups * c.res_chunks;
     if (h->partial.alloc((size_t)h->npartial * sizeof(double), st) || h->norms.alloc(4 * sizeof(double), st))
         return ILU_ENOMEM;
     if (upload(h->order_fwd, topo_order(h->blocks, true), st) || upload(h->order_bwd, topo_order(h->blocks, false), st))
@@ -494,7 +512,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     if (h->progress.alloc(std::max<size_t>(1, h->blocks.size()) * sizeof(int32_t), st) ||
         h->ticket.alloc(2 * sizeof(int32_t), st))
         return ILU_ENOMEM;
-    h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC));
+    h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->bv, h->bw));
     for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
@@ -506,6 +524,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
 // is never written, which holds zero).  Returns the number of violations.
 int64_t check_layout(ilu_handle_t h) {
     const int64_t S = h->S;
+    const int bv = h->bv, bw = h->bw, LANES = bv * bw;
     std::vector<int32_t> owner(S, -1);  // written slot -> point id (block*64+lane, t) packed
     std::vector<int32_t> owner_t(S, -1);
     int64_t bad = 0;
@@ -570,17 +589,19 @@ int64_t check_layout(ilu_handle_t h) {
         }
         // dataflow halo rows: forward (pred) and backward (succ)
         for (int dir = 0; dir < 2; ++dir)
-            for (int hl = 0; hl < 17; ++hl) {
+            for (int hl = 0; hl < bv + bw + 1; ++hl) {
                 int64_t rp;
                 int prod;
                 if (dir == 0) {
-                    if (hl < 8) { rp = h->lanes[b * LANES + hl * 8].rp[R_VM]; prod = B.pred[0]; }
-                    else if (hl < 16) { rp = h->lanes[b * LANES + (hl - 8)].rp[R_WM]; prod = B.pred[1]; }
+                    if (hl < bw) { rp = h->lanes[b * LANES + hl * bv].rp[R_VM]; prod = B.pred[0]; }
+                    else if (hl < bw + bv) { rp = h->lanes[b * LANES + (hl - bw)].rp[R_WM]; prod = B.pred[1]; }
                     else { rp = h->lanes[b * LANES].rp[R_VMWM]; prod = B.pred[2]; }
                 } else {
-                    if (hl < 8) { rp = h->lanes[b * LANES + hl * 8 + 7].rp[R_VP]; prod = B.succ[0]; }
-                    else if (hl < 16) { rp = h->lanes[b * LANES + 56 + (hl - 8)].rp[R_WP]; prod = B.succ[1]; }
-                    else { rp = h->lanes[b * LANES + 63].rp[R_VPWP]; prod = B.succ[2]; }
+                    if (hl < bw) { rp = h->lanes[b * LANES + hl * bv + bv - 1].rp[R_VP]; prod = B.succ[0]; }
+                    else if (hl < bw + bv) {
+                        rp = h->lanes[b * LANES + (bw - 1) * bv + (hl - bw)].rp[R_WP];
+                        prod = B.succ[1];
+                    } else { rp = h->lanes[b * LANES + LANES - 1].rp[R_VPWP]; prod = B.succ[2]; }
                 }
                 if (prod < 0) { bad += rp != 0; continue; }
                 const BlockDev& PB = h->blocks[prod];
@@ -664,8 +685,9 @@ double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
 namespace {
 int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
     if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_SURR_F32) return ILU_EINVAL;
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 2; ++k)
         if (opts->reserved[k]) return ILU_EINVAL;
+    if ((opts->tile[0] || opts->tile[1]) && !flow_shape_supported(opts->tile[0], opts->tile[1])) return ILU_EINVAL;
     if (opts->variant != ILU_STORED_F64) {
         for (int k = 0; k < 3; ++k)
             if (opts->degree[k] < 0 || opts->degree[k] > 6) return ILU_EINVAL;

@@ -15,6 +15,9 @@ struct Ctx {
     const BlockDev* blocks = nullptr;
     const LaneDev* lanes = nullptr;
     int nblocks = 0;
+    int bv = 8, bw = 8;      // block shape in rows
+    int lpb = 64;            // lanes per block = bv * bw
+    int groups = 1;          // 64-lane groups per block
     int res_chunks = 0;      // ceil(max block window / RES_T)
     int64_t S = 0;           // stream length (elements)
     const double* A8 = nullptr;   // [8][S]: centre, then lower weights w..be

@@ -1,20 +1,25 @@
 // Persistent dataflow sweeps (Alg. 2 on the hyperplane schedule without a
 // global barrier per hyperplane).
 //
-// One workgroup = one wavefront = one 8 x 8 block of rows at a time.  A
+// One workgroup of BV*BW threads owns one BV x BW block of rows at a time.  A
 // workgroup takes blocks from a ticket counter in a topological order of the
 // block dependency graph, so every block it waits for is owned by a resident
 // workgroup that took its ticket earlier: the wait chain always ends.
 //
-// Inside a block the 64 lanes advance hyperplane by hyperplane in lock step.
-// Values of the last few hyperplanes live in an LDS ring of 9 x 9 cells per
-// hyperplane: 8 x 8 own rows plus one halo column and one halo row holding
-// rows of the neighbouring blocks.  Halo values are produced by other
-// workgroups; they are read from the w stream with device-coherent loads once
-// the producer's progress counter shows them finished, H hyperplanes ahead of
-// use, and committed to the ring a batch later.  w is written with
-// device-coherent stores and each block publishes its progress every H
-// hyperplanes after waiting for those stores.
+// Inside a block all lanes advance hyperplane by hyperplane in lock step (one
+// workgroup barrier per hyperplane).  The values of the last three
+// hyperplanes live in a 4-slot LDS grid of (BV+1) x (BW+1) cells: the block's
+// own rows plus one halo column and one halo row holding rows of the
+// neighbouring blocks.  Halo values come from other workgroups: halo threads
+// read them from the w stream with device-coherent loads once the producer's
+// progress counter covers them, one batch of H hyperplanes ahead of use, park
+// them in a staging ring, and copy one hyperplane per step into the grid.
+// w is written with device-coherent stores; each block publishes its progress
+// once per batch after waiting for those stores.
+//
+// The seven products of a point are accumulated oldest hyperplane first
+// (the t-2 / t-3 neighbours, then the three t-1 neighbours), so only three
+// fused multiply-adds sit on the hyperplane-to-hyperplane dependency chain.
 //
 // A wait that exceeds a fixed bound sets flags[2] and gives up, so a logic
 // error can never hang the device.
@@ -27,8 +32,9 @@ namespace ilu {
 
 namespace {
 
-constexpr int GRIDC = 81;           // 9 x 9 cells per hyperplane
 constexpr long SPIN_LIMIT = 1L << 24;
+// accumulation order over D_l: s, bnw, bc, be (older hyperplanes) then w, se, bn
+constexpr int ORD[7] = {1, 3, 5, 6, 0, 2, 4};
 
 template <typename T>
 __device__ __forceinline__ void st_dev(T* p, T v) {
@@ -44,6 +50,14 @@ __device__ __forceinline__ void wait_stores() {
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
+// Workgroup barrier that orders LDS traffic only: a full __syncthreads()
+// would also wait for this wave's outstanding global stores and loads.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int NC, typename T>
 __device__ __forceinline__ T horner(const T* c, T eta) {
     T acc = c[NC - 1];
@@ -51,13 +65,6 @@ __device__ __forceinline__ T horner(const T* c, T eta) {
     for (int i = NC - 2; i >= 0; --i) acc = acc * eta + c[i];
     return acc;
 }
-
-struct Halo {
-    int cell = -1;     // ring cell this lane fills (-1: no halo role)
-    int64_t rp = 0;    // row pointer of the halo row
-    int prod = -1;     // producing block (-1: row outside the lattice, value 0)
-    int ptb = 0, pte = 0;
-};
 
 // Wait until block `prod` has published at least `need` finished hyperplanes.
 // `known` caches the last value observed, so most calls return at once.
@@ -80,174 +87,192 @@ __device__ __forceinline__ void wait_progress(const int32_t* progress, int prod,
     known = v;
 }
 
+struct Halo {
+    int idx = -1;      // halo row index in the staging ring (-1: no halo role)
+    int cell = 0;      // grid cell of the halo row
+    int64_t rp = 0;    // row pointer of the halo row
+    int prod = -1;     // producing block (-1: no block, value 0)
+    int ptb = 0, pte = 0;
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------ forward
 
-template <typename T, bool STORED, int H, int NC>
-__global__ void __launch_bounds__(64) k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                 const LaneDev* __restrict__ lanes, int nblocks, int64_t S,
-                                                 const double* __restrict__ Lf, const T* __restrict__ tab,
-                                                 const T* __restrict__ r, T* __restrict__ w,
-                                                 const int32_t* __restrict__ order, int32_t* __restrict__ progress,
-                                                 int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
-    constexpr int RING = 2 * H >= 8 ? 2 * H : 8;
-    static_assert((RING & (RING - 1)) == 0 && RING >= H + 2, "ring size");
-    __shared__ T ring[RING * GRIDC];
+template <typename T, bool STORED, int H, int NC, int BV, int BW>
+__global__ void __launch_bounds__(BV* BW) k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                                     const LaneDev* __restrict__ lanes, int nblocks, int64_t S,
+                                                     const double* __restrict__ Lf, const T* __restrict__ tab,
+                                                     const T* __restrict__ r, T* __restrict__ w,
+                                                     const int32_t* __restrict__ order, int32_t* __restrict__ progress,
+                                                     int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+    constexpr int NT = BV * BW;
+    constexpr int GW = BV + 1;
+    constexpr int GC = (BV + 1) * (BW + 1);
+    constexpr int NH = BV + BW + 1;
+    static_assert((H & (H - 1)) == 0, "H must be a power of two");
+    __shared__ T grid[4 * GC];
+    __shared__ T stage[H * NH];
     __shared__ int s_ticket;
-    const int lane = threadIdx.x;
-    const int vl = lane & 7, wl = lane >> 3;
-    const int cell = (wl + 1) * 9 + (vl + 1);
+    const int l = threadIdx.x;
+    const int vl = l % BV, wl = l / BV;
+    const int cell = (wl + 1) * GW + (vl + 1);
     for (;;) {
-        if (lane == 0) s_ticket = atomicAdd(&ticket[0], 1);
+        if (l == 0) s_ticket = atomicAdd(&ticket[0], 1);
         __syncthreads();
         const int k = s_ticket;
         __syncthreads();
         if (k >= nblocks) return;
         const int b = order[k];
         const BlockDev B = blocks[b];
-        const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+        const LaneDev& Ln = lanes[(int64_t)b * NT + l];
         const bool valid = Ln.v != 0;
         const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
         const int64_t rp = Ln.rp[R_SELF];
-        // halo role of this lane
+        // halo roles: left column (v = V0-1), bottom row (w = W0-1), corner
         Halo hl;
-        if (lane < 8) {
-            hl.cell = (lane + 1) * 9;
-            hl.rp = lanes[(int64_t)b * LANES + lane * 8].rp[R_VM];
+        if (l < BW) {
+            hl.idx = l;
+            hl.cell = (l + 1) * GW;
+            hl.rp = lanes[(int64_t)b * NT + l * BV].rp[R_VM];
             hl.prod = B.pred[0];
-        } else if (lane < 16) {
-            hl.cell = lane - 7;
-            hl.rp = lanes[(int64_t)b * LANES + (lane - 8)].rp[R_WM];
+        } else if (l < BW + BV) {
+            hl.idx = l;
+            hl.cell = l - BW + 1;
+            hl.rp = lanes[(int64_t)b * NT + (l - BW)].rp[R_WM];
             hl.prod = B.pred[1];
-        } else if (lane == 16) {
+        } else if (l == BW + BV) {
+            hl.idx = l;
             hl.cell = 0;
-            hl.rp = lanes[(int64_t)b * LANES].rp[R_VMWM];
+            hl.rp = lanes[(int64_t)b * NT].rp[R_VMWM];
             hl.prod = B.pred[2];
         }
         if (hl.prod >= 0) {
             hl.ptb = blocks[hl.prod].tb;
             hl.pte = blocks[hl.prod].te;
         }
-        // surrogate coefficients of this row (forward table: 7 x NC)
         T coef[7 * (NC > 0 ? NC : 1)];
         T xm = 0, ihw = 0;
         if (!STORED && valid) {
-            const T* c = tab + ((int64_t)b * LANES + lane) * (2 + 15 * NC);
+            const T* c = tab + ((int64_t)b * NT + l) * (2 + 15 * NC);
             xm = c[0];
             ihw = c[1];
-            #pragma unroll
+#pragma unroll
             for (int i = 0; i < 7 * NC; ++i) coef[i] = c[2 + i];
         }
-        for (int i = lane; i < RING * GRIDC; i += 64) ring[i] = (T)0;
+        for (int i = l; i < 4 * GC; i += NT) grid[i] = (T)0;
         __syncthreads();
         const int tb = B.tb, te = B.te;
-        // prologue: halo slots tb-3 .. tb+H-2 (one wait for the furthest slot)
+        // prologue: halo slots tb-3..tb-1 straight into the grid, tb..tb+H-1 into the stage
         T hreg[H];
         int known = 0, pending = 0;
-        if (hl.cell >= 0) {
+        if (hl.idx >= 0) {
             if (hl.prod >= 0) {
-                const int smax = min(tb + H - 2, hl.pte);
+                const int smax = min(tb + H - 1, hl.pte);
                 if (smax >= hl.ptb) wait_progress(progress, hl.prod, smax - hl.ptb + 1, known, flags);
             }
-            for (int s = tb - 3; s <= tb + H - 2; ++s) {
+            for (int s = tb - 3; s <= tb + H - 1; ++s) {
                 const bool ld = hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                ring[(s & (RING - 1)) * GRIDC + hl.cell] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
+                const T val = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
+                if (s < tb) grid[(s & 3) * GC + hl.cell] = val;
+                else stage[(s & (H - 1)) * NH + hl.idx] = val;
             }
         }
-        // operand prefetch registers for the current batch
-        T rcur[H];
-        double Lcur[STORED ? H * 7 : 1];
+        // operands of two batches in flight: ping-pong buffers A and B (no copies,
+        // so nothing loaded during a batch is touched before its final wait)
+        constexpr int NL = STORED ? H * 7 : 1;
+        T rA[H], rB[H];
+        double LA[NL], LB[NL];
+        auto prefetch = [&](const int T0, T (&rx)[H], double (&Lx)[NL]) {
 #pragma unroll
-        for (int q = 0; q < H; ++q) {
-            const int t = tb + q;
-            rcur[q] = (T)0;
-            if (valid && t <= te) {
-                rcur[q] = r[rp + (int64_t)LANES * t];
-                if (STORED)
+            for (int q = 0; q < H; ++q) {
+                const int t = T0 + q;
+                rx[q] = (T)0;
+                if (valid && t <= te) {
+                    rx[q] = r[rp + (int64_t)NT * t];
+                    if (STORED)
 #pragma unroll
-                    for (int s = 0; s < 7; ++s) Lcur[q * 7 + s] = Lf[(int64_t)s * S + rp + (int64_t)LANES * t];
+                        for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = Lf[(int64_t)s * S + rp + (int64_t)NT * t];
+                }
             }
-        }
+        };
+        prefetch(tb, rA, LA);
         __syncthreads();
-        for (int T0 = tb; T0 <= te; T0 += H) {
-            // commit the halo slots of this batch (loaded during the previous one)
-            if (T0 > tb && hl.cell >= 0) {
+        auto batch = [&](const int T0, T (&rcur)[H], double (&Lcur)[NL], T (&rnxt)[H], double (&Lnxt)[NL]) {
+            if (hl.idx >= 0) {
+                // stage the halo slots of this batch (loaded during the previous one)
+                if (T0 > tb) {
 #pragma unroll
-                for (int q = 0; q < H; ++q) ring[((T0 - 1 + q) & (RING - 1)) * GRIDC + hl.cell] = hreg[q];
-            }
-            // issue halo loads for the next batch: slots T0+H-1 .. T0+2H-2
-            if (hl.cell >= 0) {
+                    for (int q = 0; q < H; ++q) stage[((T0 + q) & (H - 1)) * NH + hl.idx] = hreg[q];
+                }
+                // load the next batch's halo slots T0+H .. T0+2H-1
                 const bool more = T0 + H <= te;
                 if (hl.prod >= 0 && more) {
                     known = max(known, pending);
-                    const int smax = min(T0 + 2 * H - 2, hl.pte);
+                    const int smax = min(T0 + 2 * H - 1, hl.pte);
                     if (smax >= hl.ptb) wait_progress(progress, hl.prod, smax - hl.ptb + 1, known, flags);
                 }
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
-                    const int s = T0 + H - 1 + q;
+                    const int s = T0 + H + q;
                     const bool ld = more && hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
+                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
                 }
-                // refresh the producer's progress for the next batch (arrives with the batch)
                 if (hl.prod >= 0 && more) pending = ld_dev(&progress[hl.prod]);
             }
-            // prefetch operands of the next batch
-            T rnxt[H];
-            double Lnxt[STORED ? H * 7 : 1];
-#pragma unroll
-            for (int q = 0; q < H; ++q) {
-                const int t = T0 + H + q;
-                rnxt[q] = (T)0;
-                if (valid && t <= te) {
-                    rnxt[q] = r[rp + (int64_t)LANES * t];
-                    if (STORED)
-#pragma unroll
-                        for (int s = 0; s < 7; ++s) Lnxt[q * 7 + s] = Lf[(int64_t)s * S + rp + (int64_t)LANES * t];
-                }
-            }
-            __syncthreads();
+            prefetch(T0 + H, rnxt, Lnxt);
+            lds_barrier();
+            // the H hyperplanes of this batch: LDS traffic only
+            T wout[H];
+            unsigned act = 0;
 #pragma unroll
             for (int q = 0; q < H; ++q) {
                 const int t = T0 + q;
+                wout[q] = (T)0;
                 if (t > te) break;
+                if (hl.idx >= 0) grid[(t & 3) * GC + hl.cell] = stage[(t & (H - 1)) * NH + hl.idx];
                 const int x = t - 2 * v - wrow;
                 T val = (T)0;
                 if (valid && x >= 1 && x <= n - 1 - v) {
-                    const T* s1 = ring + ((t - 1) & (RING - 1)) * GRIDC;
-                    const T* s2 = ring + ((t - 2) & (RING - 1)) * GRIDC;
-                    const T* s3 = ring + ((t - 3) & (RING - 1)) * GRIDC;
-                    // neighbours: w (own, t-1), s (VM, t-2), se (VM, t-1), bnw (WM, t-2),
-                    // bn (WM, t-1), bc (VMWM, t-3), be (VMWM, t-2)
-                    const T nb[7] = {s1[cell], s2[cell - 1], s1[cell - 1], s2[cell - 9],
-                                     s1[cell - 9], s3[cell - 10], s2[cell - 10]};
+                    const T* g1 = grid + ((t - 1) & 3) * GC;
+                    const T* g2 = grid + ((t - 2) & 3) * GC;
+                    const T* g3 = grid + ((t - 3) & 3) * GC;
+                    // neighbours p + d: w (own, t-1), s (v-1, t-2), se (v-1, t-1), bnw (w-1, t-2),
+                    // bn (w-1, t-1), bc (v-1 w-1, t-3), be (v-1 w-1, t-2)
+                    const T nb[7] = {g1[cell], g2[cell - 1], g1[cell - 1], g2[cell - GW],
+                                     g1[cell - GW], g3[cell - GW - 1], g2[cell - GW - 1]};
                     T acc = rcur[q];
                     if (STORED) {
 #pragma unroll
-                        for (int s = 0; s < 7; ++s) acc -= (T)Lcur[q * 7 + s] * nb[s];
+                        for (int j = 0; j < 7; ++j) acc -= (T)Lcur[q * 7 + ORD[j]] * nb[ORD[j]];
                     } else {
                         const T eta = ((T)x - xm) * ihw;
+                        T Lv[7];
 #pragma unroll
-                        for (int s = 0; s < 7; ++s) acc -= horner<NC>(coef + s * NC, eta) * nb[s];
+                        for (int s = 0; s < 7; ++s) Lv[s] = horner<NC>(coef + s * NC, eta);
+#pragma unroll
+                        for (int j = 0; j < 7; ++j) acc -= Lv[ORD[j]] * nb[ORD[j]];
                     }
                     val = acc;
-                    st_dev(&w[rp + (int64_t)LANES * t], val);
+                    wout[q] = val;
+                    act |= 1u << q;
                 }
-                ring[(t & (RING - 1)) * GRIDC + cell] = val;
-                __syncthreads();
+                grid[(t & 3) * GC + cell] = val;
+                lds_barrier();
             }
-            // publish progress: all w stores of this batch have completed
+            // write the batch's results with device-coherent stores
+#pragma unroll
+            for (int q = 0; q < H; ++q)
+                if (act & (1u << q)) st_dev(&w[rp + (int64_t)NT * (T0 + q)], wout[q]);
+            // publish progress: every wave's w stores of this batch have completed
             wait_stores();
             __syncthreads();
-            if (lane == 0) st_dev(&progress[b], (int32_t)(min(T0 + H - 1, te) - tb + 1));
-#pragma unroll
-            for (int q = 0; q < H; ++q) {
-                rcur[q] = rnxt[q];
-                if (STORED)
-#pragma unroll
-                    for (int s = 0; s < 7; ++s) Lcur[q * 7 + s] = Lnxt[q * 7 + s];
-            }
+            if (l == 0) st_dev(&progress[b], (int32_t)(min(T0 + H - 1, te) - tb + 1));
+        };
+        for (int T0 = tb; T0 <= te; T0 += 2 * H) {
+            batch(T0, rA, LA, rB, LB);
+            if (T0 + H > te) break;
+            batch(T0 + H, rB, LB, rA, LA);
         }
         __syncthreads();
     }
@@ -255,43 +280,52 @@ __global__ void __launch_bounds__(64) k_fwd_flow(const TetDev* __restrict__ tets
 
 // ----------------------------------------------------------------- backward
 
-template <typename T, bool STORED, int H, int NC>
-__global__ void __launch_bounds__(64) k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                 const LaneDev* __restrict__ lanes, int nblocks, int64_t S,
-                                                 const double* __restrict__ Lb, const T* __restrict__ tab,
-                                                 T* __restrict__ w, double* __restrict__ xs,
-                                                 const int32_t* __restrict__ order, int32_t* __restrict__ progress,
-                                                 int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
-    constexpr int RING = 2 * H >= 8 ? 2 * H : 8;
-    __shared__ T ring[RING * GRIDC];
+template <typename T, bool STORED, int H, int NC, int BV, int BW>
+__global__ void __launch_bounds__(BV* BW) k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                                     const LaneDev* __restrict__ lanes, int nblocks, int64_t S,
+                                                     const double* __restrict__ Lb, const T* __restrict__ tab,
+                                                     T* __restrict__ w, double* __restrict__ xs,
+                                                     const int32_t* __restrict__ order, int32_t* __restrict__ progress,
+                                                     int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+    constexpr int NT = BV * BW;
+    constexpr int GW = BV + 1;
+    constexpr int GC = (BV + 1) * (BW + 1);
+    constexpr int NH = BV + BW + 1;
+    static_assert((H & (H - 1)) == 0, "H must be a power of two");
+    __shared__ T grid[4 * GC];
+    __shared__ T stage[H * NH];
     __shared__ int s_ticket;
-    const int lane = threadIdx.x;
-    const int vl = lane & 7, wl = lane >> 3;
-    const int cell = wl * 9 + vl;  // halo at column 8 and row 8
+    const int l = threadIdx.x;
+    const int vl = l % BV, wl = l / BV;
+    const int cell = wl * GW + vl;  // halo at column BV and row BW
     for (;;) {
-        if (lane == 0) s_ticket = atomicAdd(&ticket[1], 1);
+        if (l == 0) s_ticket = atomicAdd(&ticket[1], 1);
         __syncthreads();
         const int k = s_ticket;
         __syncthreads();
         if (k >= nblocks) return;
         const int b = order[k];
         const BlockDev B = blocks[b];
-        const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+        const LaneDev& Ln = lanes[(int64_t)b * NT + l];
         const bool valid = Ln.v != 0;
         const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
         const int64_t rp = Ln.rp[R_SELF];
+        // halo roles: right column (v = V0+BV), top row (w = W0+BW), corner
         Halo hl;
-        if (lane < 8) {
-            hl.cell = lane * 9 + 8;
-            hl.rp = lanes[(int64_t)b * LANES + lane * 8 + 7].rp[R_VP];
+        if (l < BW) {
+            hl.idx = l;
+            hl.cell = l * GW + BV;
+            hl.rp = lanes[(int64_t)b * NT + l * BV + (BV - 1)].rp[R_VP];
             hl.prod = B.succ[0];
-        } else if (lane < 16) {
-            hl.cell = 72 + (lane - 8);
-            hl.rp = lanes[(int64_t)b * LANES + 56 + (lane - 8)].rp[R_WP];
+        } else if (l < BW + BV) {
+            hl.idx = l;
+            hl.cell = BW * GW + (l - BW);
+            hl.rp = lanes[(int64_t)b * NT + (BW - 1) * BV + (l - BW)].rp[R_WP];
             hl.prod = B.succ[1];
-        } else if (lane == 16) {
-            hl.cell = 80;
-            hl.rp = lanes[(int64_t)b * LANES + 63].rp[R_VPWP];
+        } else if (l == BW + BV) {
+            hl.idx = l;
+            hl.cell = BW * GW + BV;
+            hl.rp = lanes[(int64_t)b * NT + NT - 1].rp[R_VPWP];
             hl.prod = B.succ[2];
         }
         if (hl.prod >= 0) {
@@ -301,126 +335,131 @@ __global__ void __launch_bounds__(64) k_bwd_flow(const TetDev* __restrict__ tets
         T coef[8 * (NC > 0 ? NC : 1)];
         T xm = 0, ihw = 0;
         if (!STORED && valid) {
-            const T* c = tab + ((int64_t)b * LANES + lane) * (2 + 15 * NC);
+            const T* c = tab + ((int64_t)b * NT + l) * (2 + 15 * NC);
             xm = c[0];
             ihw = c[1];
-            #pragma unroll
+#pragma unroll
             for (int i = 0; i < 8 * NC; ++i) coef[i] = c[2 + 7 * NC + i];
         }
-        for (int i = lane; i < RING * GRIDC; i += 64) ring[i] = (T)0;
+        for (int i = l; i < 4 * GC; i += NT) grid[i] = (T)0;
         __syncthreads();
         const int tb = B.tb, te = B.te;
-        // prologue: halo slots te+3 .. te-H+2 (descending; one wait for the furthest slot)
+        // prologue: halo slots te+3..te+1 into the grid, te..te-H+1 into the stage
         T hreg[H];
         int known = 0, pending = 0;
-        if (hl.cell >= 0) {
+        if (hl.idx >= 0) {
             if (hl.prod >= 0) {
-                const int smin = max(te - H + 2, hl.ptb);
+                const int smin = max(te - H + 1, hl.ptb);
                 if (smin <= hl.pte) wait_progress(progress, hl.prod, hl.pte - smin + 1, known, flags);
             }
-            for (int s = te + 3; s >= te - H + 2; --s) {
+            for (int s = te + 3; s >= te - H + 1; --s) {
                 const bool ld = hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                ring[(s & (RING - 1)) * GRIDC + hl.cell] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
+                const T val = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
+                if (s > te) grid[(s & 3) * GC + hl.cell] = val;
+                else stage[(s & (H - 1)) * NH + hl.idx] = val;
             }
         }
-        T wcur[H];
-        double xcur[H];
-        double Lcur[STORED ? H * 8 : 1];
+        constexpr int NL = STORED ? H * 8 : 1;
+        T wA[H], wB[H];
+        double xA[H], xB[H];
+        double LA[NL], LB[NL];
+        auto prefetch = [&](const int T0, T (&wx)[H], double (&xx)[H], double (&Lx)[NL]) {
 #pragma unroll
-        for (int q = 0; q < H; ++q) {
-            const int t = te - q;
-            wcur[q] = (T)0;
-            xcur[q] = 0.0;
-            if (valid && t >= tb) {
-                wcur[q] = w[rp + (int64_t)LANES * t];
-                xcur[q] = xs[rp + (int64_t)LANES * t];
-                if (STORED)
+            for (int q = 0; q < H; ++q) {
+                const int t = T0 - q;
+                wx[q] = (T)0;
+                xx[q] = 0.0;
+                if (valid && t >= tb) {
+                    wx[q] = w[rp + (int64_t)NT * t];
+                    xx[q] = xs[rp + (int64_t)NT * t];
+                    if (STORED)
 #pragma unroll
-                    for (int s = 0; s < 8; ++s) Lcur[q * 8 + s] = Lb[(int64_t)s * S + rp + (int64_t)LANES * t];
+                        for (int s = 0; s < 8; ++s) Lx[q * 8 + s] = Lb[(int64_t)s * S + rp + (int64_t)NT * t];
+                }
             }
-        }
+        };
+        prefetch(te, wA, xA, LA);
         __syncthreads();
-        for (int T0 = te; T0 >= tb; T0 -= H) {
-            if (T0 < te && hl.cell >= 0) {
+        auto batch = [&](const int T0, T (&wcur)[H], double (&xcur)[H], double (&Lcur)[NL], T (&wnxt)[H],
+                         double (&xnxt)[H], double (&Lnxt)[NL]) {
+            if (hl.idx >= 0) {
+                if (T0 < te) {
 #pragma unroll
-                for (int q = 0; q < H; ++q) ring[((T0 + 1 - q) & (RING - 1)) * GRIDC + hl.cell] = hreg[q];
-            }
-            if (hl.cell >= 0) {
+                    for (int q = 0; q < H; ++q) stage[((T0 - q) & (H - 1)) * NH + hl.idx] = hreg[q];
+                }
                 const bool more = T0 - H >= tb;
                 if (hl.prod >= 0 && more) {
                     known = max(known, pending);
-                    const int smin = max(T0 - 2 * H + 2, hl.ptb);
+                    const int smin = max(T0 - 2 * H + 1, hl.ptb);
                     if (smin <= hl.pte) wait_progress(progress, hl.prod, hl.pte - smin + 1, known, flags);
                 }
 #pragma unroll
                 for (int q = 0; q < H; ++q) {
-                    const int s = T0 - H + 1 - q;
+                    const int s = T0 - H - q;
                     const bool ld = more && hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)LANES * s]) : (T)0;
+                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
                 }
                 if (hl.prod >= 0 && more) pending = ld_dev(&progress[hl.prod]);
             }
-            T wnxt[H];
-            double xnxt[H];
-            double Lnxt[STORED ? H * 8 : 1];
-#pragma unroll
-            for (int q = 0; q < H; ++q) {
-                const int t = T0 - H - q;
-                wnxt[q] = (T)0;
-                xnxt[q] = 0.0;
-                if (valid && t >= tb) {
-                    wnxt[q] = w[rp + (int64_t)LANES * t];
-                    xnxt[q] = xs[rp + (int64_t)LANES * t];
-                    if (STORED)
-#pragma unroll
-                        for (int s = 0; s < 8; ++s) Lnxt[q * 8 + s] = Lb[(int64_t)s * S + rp + (int64_t)LANES * t];
-                }
-            }
-            __syncthreads();
+            prefetch(T0 - H, wnxt, xnxt, Lnxt);
+            lds_barrier();
+            T wout[H];
+            double xout[H];
+            unsigned act = 0;
 #pragma unroll
             for (int q = 0; q < H; ++q) {
                 const int t = T0 - q;
+                wout[q] = (T)0;
+                xout[q] = 0.0;
                 if (t < tb) break;
+                if (hl.idx >= 0) grid[(t & 3) * GC + hl.cell] = stage[(t & (H - 1)) * NH + hl.idx];
                 const int x = t - 2 * v - wrow;
                 T val = (T)0;
                 if (valid && x >= 1 && x <= n - 1 - v) {
-                    const T* s1 = ring + ((t + 1) & (RING - 1)) * GRIDC;
-                    const T* s2 = ring + ((t + 2) & (RING - 1)) * GRIDC;
-                    const T* s3 = ring + ((t + 3) & (RING - 1)) * GRIDC;
-                    // upper neighbours p - d: e (own, t+1), n (VP, t+2), nw (VP, t+1),
-                    // tse (WP, t+2), ts (WP, t+1), tc (VPWP, t+3), tw (VPWP, t+2)
-                    const T nb[7] = {s1[cell], s2[cell + 1], s1[cell + 1], s2[cell + 9],
-                                     s1[cell + 9], s3[cell + 10], s2[cell + 10]};
+                    const T* g1 = grid + ((t + 1) & 3) * GC;
+                    const T* g2 = grid + ((t + 2) & 3) * GC;
+                    const T* g3 = grid + ((t + 3) & 3) * GC;
+                    // upper neighbours p - d: e (own, t+1), n (v+1, t+2), nw (v+1, t+1),
+                    // tse (w+1, t+2), ts (w+1, t+1), tc (v+1 w+1, t+3), tw (v+1 w+1, t+2)
+                    const T nb[7] = {g1[cell], g2[cell + 1], g1[cell + 1], g2[cell + GW],
+                                     g1[cell + GW], g3[cell + GW + 1], g2[cell + GW + 1]};
                     T acc;
                     if (STORED) {
                         acc = wcur[q] * (T)Lcur[q * 8];
 #pragma unroll
-                        for (int s = 0; s < 7; ++s) acc -= (T)Lcur[q * 8 + 1 + s] * nb[s];
+                        for (int j = 0; j < 7; ++j) acc -= (T)Lcur[q * 8 + 1 + ORD[j]] * nb[ORD[j]];
                     } else {
                         const T eta = ((T)x - xm) * ihw;
+                        T Uv[7];
+#pragma unroll
+                        for (int s = 0; s < 7; ++s) Uv[s] = horner<NC>(coef + (1 + s) * NC, eta);
                         acc = wcur[q] * horner<NC>(coef, eta);
 #pragma unroll
-                        for (int s = 0; s < 7; ++s) acc -= horner<NC>(coef + (1 + s) * NC, eta) * nb[s];
+                        for (int j = 0; j < 7; ++j) acc -= Uv[ORD[j]] * nb[ORD[j]];
                     }
                     val = acc;
-                    const int64_t idx = rp + (int64_t)LANES * t;
-                    st_dev(&w[idx], val);
-                    xs[idx] = xcur[q] + (double)val;
+                    wout[q] = val;
+                    xout[q] = xcur[q] + (double)val;
+                    act |= 1u << q;
                 }
-                ring[(t & (RING - 1)) * GRIDC + cell] = val;
-                __syncthreads();
+                grid[(t & 3) * GC + cell] = val;
+                lds_barrier();
             }
+#pragma unroll
+            for (int q = 0; q < H; ++q)
+                if (act & (1u << q)) {
+                    const int64_t idx = rp + (int64_t)NT * (T0 - q);
+                    st_dev(&w[idx], wout[q]);
+                    xs[idx] = xout[q];
+                }
             wait_stores();
             __syncthreads();
-            if (lane == 0) st_dev(&progress[b], (int32_t)(te - max(T0 - H + 1, tb) + 1));
-#pragma unroll
-            for (int q = 0; q < H; ++q) {
-                wcur[q] = wnxt[q];
-                xcur[q] = xnxt[q];
-                if (STORED)
-#pragma unroll
-                    for (int s = 0; s < 8; ++s) Lcur[q * 8 + s] = Lnxt[q * 8 + s];
-            }
+            if (l == 0) st_dev(&progress[b], (int32_t)(te - max(T0 - H + 1, tb) + 1));
+        };
+        for (int T0 = te; T0 >= tb; T0 -= 2 * H) {
+            batch(T0, wA, xA, LA, wB, xB, LB);
+            if (T0 - H < tb) break;
+            batch(T0 - H, wB, xB, LB, wA, xA, LA);
         }
         __syncthreads();
     }
@@ -434,70 +473,128 @@ __global__ void k_flow_reset(int32_t* __restrict__ progress, int n, int32_t* __r
 
 // ------------------------------------------------------------------ launchers
 
+namespace {
+
 constexpr int H_F64 = 4;   // stored factors: 8 operands per step are prefetched
 constexpr int H_S64 = 8;   // FP64 surrogate
-constexpr int H_F32 = 16;  // FP32 surrogate
+constexpr int H_F32 = 8;   // FP32 surrogate
 
-template <int NC>
-struct FlowK {
-    static const void* fwd(int variant) {
-        if (variant == 1) return (const void*)k_fwd_flow<double, false, H_S64, NC>;
-        return (const void*)k_fwd_flow<float, false, H_F32, NC>;
+template <int BV, int BW>
+struct Shape {
+    static constexpr int NT = BV * BW;
+    static const void* fwd_stored_ptr() { return (const void*)k_fwd_flow<double, true, H_F64, 0, BV, BW>; }
+    static const void* bwd_stored_ptr() { return (const void*)k_bwd_flow<double, true, H_F64, 0, BV, BW>; }
+    template <int NC>
+    static const void* fwd_ptr(int variant) {
+        if (variant == 1) return (const void*)k_fwd_flow<double, false, H_S64, NC, BV, BW>;
+        return (const void*)k_fwd_flow<float, false, H_F32, NC, BV, BW>;
     }
-    static const void* bwd(int variant) {
-        if (variant == 1) return (const void*)k_bwd_flow<double, false, H_S64, NC>;
-        return (const void*)k_bwd_flow<float, false, H_F32, NC>;
+    template <int NC>
+    static const void* bwd_ptr(int variant) {
+        if (variant == 1) return (const void*)k_bwd_flow<double, false, H_S64, NC, BV, BW>;
+        return (const void*)k_bwd_flow<float, false, H_F32, NC, BV, BW>;
     }
-    static void run_fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
+    static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
+        k_fwd_flow<double, true, H_F64, 0, BV, BW><<<f.grid, NT, 0, st>>>(
+            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, (const double*)c.r, (double*)c.w, f.order_fwd,
+            f.progress, f.ticket, f.flags);
+    }
+    static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
+        k_bwd_flow<double, true, H_F64, 0, BV, BW><<<f.grid, NT, 0, st>>>(
+            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, (double*)c.w, x, f.order_bwd, f.progress,
+            f.ticket, f.flags);
+    }
+    template <int NC>
+    static void fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, H_S64, NC><<<f.grid, 64, 0, st>>>(
+            k_fwd_flow<double, false, H_S64, NC, BV, BW><<<f.grid, NT, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.r, (double*)c.w,
                 f.order_fwd, f.progress, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, H_F32, NC><<<f.grid, 64, 0, st>>>(
+            k_fwd_flow<float, false, H_F32, NC, BV, BW><<<f.grid, NT, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.r, (float*)c.w,
                 f.order_fwd, f.progress, f.ticket, f.flags);
     }
-    static void run_bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
+    template <int NC>
+    static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
         if (variant == 1)
-            k_bwd_flow<double, false, H_S64, NC><<<f.grid, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S,
-                                                                        nullptr, c.tab64, (double*)c.w, x,
-                                                                        f.order_bwd, f.progress, f.ticket, f.flags);
+            k_bwd_flow<double, false, H_S64, NC, BV, BW><<<f.grid, NT, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (double*)c.w, x, f.order_bwd,
+                f.progress, f.ticket, f.flags);
         else
-            k_bwd_flow<float, false, H_F32, NC><<<f.grid, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S,
-                                                                       nullptr, c.tab32, (float*)c.w, x, f.order_bwd,
-                                                                       f.progress, f.ticket, f.flags);
+            k_bwd_flow<float, false, H_F32, NC, BV, BW><<<f.grid, NT, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (float*)c.w, x, f.order_bwd,
+                f.progress, f.ticket, f.flags);
     }
 };
 
-#define ILU_NC_DISPATCH(NCV, EXPR)      \
-    switch (NCV) {                      \
-    case 1: { constexpr int N_ = 1; EXPR; } break; \
-    case 2: { constexpr int N_ = 2; EXPR; } break; \
-    case 3: { constexpr int N_ = 3; EXPR; } break; \
-    case 4: { constexpr int N_ = 4; EXPR; } break; \
-    case 5: { constexpr int N_ = 5; EXPR; } break; \
-    case 6: { constexpr int N_ = 6; EXPR; } break; \
-    default: { constexpr int N_ = 7; EXPR; } break; \
+// NC = dg_x + 1 in [1, 7]; stored factors use NC = 0 (one instantiation)
+#define ILU_NC_SWITCH(NCV, CALL) \
+    switch ((NCV)) {             \
+    case 1: CALL(1); break;      \
+    case 2: CALL(2); break;      \
+    case 3: CALL(3); break;      \
+    case 4: CALL(4); break;      \
+    case 5: CALL(5); break;      \
+    case 6: CALL(6); break;      \
+    default: CALL(7); break;     \
     }
 
-int flow_max_resident(int variant, int NC) {
+template <int BV, int BW>
+int resident(int variant, int NC) {
+    const void* kf = nullptr;
+    const void* kb = nullptr;
+    if (variant == 0) {
+        kf = Shape<BV, BW>::fwd_stored_ptr();
+        kb = Shape<BV, BW>::bwd_stored_ptr();
+    } else {
+#define ILU_PTRS(N) (kf = Shape<BV, BW>::template fwd_ptr<N>(variant), kb = Shape<BV, BW>::template bwd_ptr<N>(variant))
+        ILU_NC_SWITCH(NC, ILU_PTRS)
+#undef ILU_PTRS
+    }
+    int a = 0, b = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, BV * BW, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, BV * BW, 0);
+    return a < b ? a : b;
+}
+
+template <int BV, int BW>
+void run_fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
+    if (variant == 0) {
+        Shape<BV, BW>::fwd_stored(c, f, st);
+        return;
+    }
+#define ILU_FWD(N) Shape<BV, BW>::template fwd<N>(c, f, variant, st)
+    ILU_NC_SWITCH(c.NC, ILU_FWD)
+#undef ILU_FWD
+}
+
+template <int BV, int BW>
+void run_bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
+    if (variant == 0) {
+        Shape<BV, BW>::bwd_stored(c, f, x, st);
+        return;
+    }
+#define ILU_BWD(N) Shape<BV, BW>::template bwd<N>(c, f, variant, x, st)
+    ILU_NC_SWITCH(c.NC, ILU_BWD)
+#undef ILU_BWD
+}
+
+}  // namespace
+
+bool flow_shape_supported(int bv, int bw) {
+    return (bv == 8 && bw == 8) || (bv == 16 && bw == 16) || (bv == 16 && bw == 32);
+}
+
+int flow_max_resident(int variant, int NC, int bv, int bw) {
     int dev = 0;
     hipGetDevice(&dev);
     int cus = 0;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const void* kf = nullptr;
-    const void* kb = nullptr;
-    if (variant == 0) {
-        kf = (const void*)k_fwd_flow<double, true, H_F64, 0>;
-        kb = (const void*)k_bwd_flow<double, true, H_F64, 0>;
-    } else {
-        ILU_NC_DISPATCH(NC, (kf = FlowK<N_>::fwd(variant), kb = FlowK<N_>::bwd(variant)));
-    }
-    int a = 0, b = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, 64, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, 64, 0);
-    int per_cu = a < b ? a : b;
+    int per_cu = 1;
+    if (bv == 8 && bw == 8) per_cu = resident<8, 8>(variant, NC);
+    else if (bv == 16 && bw == 16) per_cu = resident<16, 16>(variant, NC);
+    else per_cu = resident<16, 32>(variant, NC);
     if (per_cu < 1) per_cu = 1;
     return per_cu * cus;
 }
@@ -508,21 +605,15 @@ void launch_flow_reset(const Ctx& c, const Flow& f, hipStream_t st) {
 }
 
 void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
-    if (variant == 0)
-        k_fwd_flow<double, true, H_F64, 0><<<f.grid, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf,
-                                                                   nullptr, (const double*)c.r, (double*)c.w,
-                                                                   f.order_fwd, f.progress, f.ticket, f.flags);
-    else
-        ILU_NC_DISPATCH(c.NC, FlowK<N_>::run_fwd(c, f, variant, st));
+    if (c.bv == 8 && c.bw == 8) run_fwd<8, 8>(c, f, variant, st);
+    else if (c.bv == 16 && c.bw == 16) run_fwd<16, 16>(c, f, variant, st);
+    else run_fwd<16, 32>(c, f, variant, st);
 }
 
 void launch_bwd_flow(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
-    if (variant == 0)
-        k_bwd_flow<double, true, H_F64, 0><<<f.grid, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb,
-                                                                   nullptr, (double*)c.w, x, f.order_bwd, f.progress,
-                                                                   f.ticket, f.flags);
-    else
-        ILU_NC_DISPATCH(c.NC, FlowK<N_>::run_bwd(c, f, variant, x, st));
+    if (c.bv == 8 && c.bw == 8) run_bwd<8, 8>(c, f, variant, x, st);
+    else if (c.bv == 16 && c.bw == 16) run_bwd<16, 16>(c, f, variant, x, st);
+    else run_bwd<16, 32>(c, f, variant, x, st);
 }
 
 }  // namespace ilu

@@ -8,15 +8,16 @@
 // components, and the hyperplane index of the wavefront schedule is
 //     t = x + 2y + 3z = u + v + w.
 // A "row" is a fixed (v, w), i.e. a fixed (y, z); it runs along x (= along u).
-// Rows are tiled into 8 x 8 blocks in (v, w); one wavefront of 64 lanes owns
-// one block, lane = 8 (w - W0) + (v - V0).
+// Rows are tiled into BV x BW blocks in (v, w) (BV*BW a multiple of 64); one
+// workgroup owns one block, lane = BV (w - W0) + (v - V0).
 //
 // Stream layout.  Every per-point array (x, b, r, w, stencil and factor
 // arrays) is stored block by block; inside a block the element of lane l at
-// hyperplane t sits at  base + (t - tlo) * 64 + l.  A lane's row pointer is
-// rp = base - tlo * 64 + l, so point (row, t) lives at rp + 64 t.  At a fixed
-// t the 64 lanes of a block are contiguous: every access of the sweep kernels
-// is one coalesced 512 B (FP64) or 256 B (FP32) transaction.  Block windows
+// hyperplane t sits at  base + (t - tlo) * LPB + l, LPB = BV*BW lanes per
+// block.  A lane's row pointer is rp = base - tlo * LPB + l, so point
+// (row, t) lives at rp + LPB t.  At a fixed t the lanes of a block are
+// contiguous: every wavefront access of the sweep kernels is one coalesced
+// 512 B (FP64) or 256 B (FP32) transaction.  Block windows
 // are padded by PAD zero steps on both sides so that neighbour reads of
 // interior points never leave their block; rows outside the lattice point to
 // the zero region at the start of every stream.
@@ -26,9 +27,7 @@
 
 namespace ilu {
 
-constexpr int BV = 8;       // block extent in v
-constexpr int BW = 8;       // block extent in w
-constexpr int LANES = 64;   // rows per block = wavefront size
+constexpr int WAVE = 64;    // wavefront size; point kernels handle 64-lane groups
 constexpr int PAD = 2;      // zero steps on each side of a block window
 constexpr int NDIR = 15;
 constexpr int NLOW = 7;
@@ -61,6 +60,9 @@ struct BlockDev {
     int32_t pad_;
     int64_t base;        // stream index of (tlo, lane 0)
 };
+
+// Lane-group decoding for the point-parallel kernels: workgroup x-index g
+// covers lanes [64 (g % groups), +64) of block g / groups.
 
 struct LaneDev {
     int64_t rp[7];       // row pointers, RowSlot order; zero-region pointer if the row is outside

@@ -24,6 +24,13 @@ __host__ __device__ constexpr int up_row(int s) {
 }
 __host__ __device__ constexpr int up_dt(int s) { return -low_dt(s); }
 
+// Point-parallel kernels launch (blocks x 64-lane groups) workgroups: decode
+// the block and the lane of this thread (the single place this mapping lives).
+__device__ __forceinline__ void decode_group(int groups, int& b, int& lane) {
+    b = (int)blockIdx.x / groups;
+    lane = (int)(blockIdx.x % groups) * WAVE + (int)(threadIdx.x & (WAVE - 1));
+}
+
 __device__ __forceinline__ bool interior(int n, int x, int y, int z) {
     return x >= 1 && y >= 1 && z >= 1 && x + y + z <= n - 1;
 }

@@ -60,12 +60,12 @@ __device__ int stencil_slot(int dx, int dy, int dz) {
 // neighbour is on the macro boundary are stored as 0: the restricted matrix
 // drops them), slot order [c, w, s, se, bnw, bn, bc, be].
 __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                           const LaneDev* __restrict__ lanes, int nblocks, int64_t S, double* __restrict__ A8,
+                           const LaneDev* __restrict__ lanes, int lpb, int groups, int nblocks, int64_t S, double* __restrict__ A8,
                            double* __restrict__ Afull /* optional [15][S] */) {
-    const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const TetDev& T = tets[B.tet];
     const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
@@ -130,7 +130,7 @@ __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __re
                 }
             }
         }
-        const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
         A8[idx] = Ad[7];
         for (int s = 0; s < NLOW; ++s) {
             const bool in = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
@@ -158,19 +158,19 @@ __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __re
 // of Alg. 1).  Factors are written to Lf[7][S] (lower weights) and Df[S].
 // The first point with D <= 0 is reported through flags[0].
 __global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                               const LaneDev* __restrict__ lanes, int t_glob, int64_t S, const double* __restrict__ A8,
+                               const LaneDev* __restrict__ lanes, int lpb, int groups, int t_glob, int64_t S, const double* __restrict__ A8,
                                double* __restrict__ Lf, double* __restrict__ Df, int* __restrict__ flags) {
-    const int b = blockIdx.x;
-    const int lane = threadIdx.x;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev& B = blocks[b];
     const int t = t_glob;
     if (t < B.tb || t > B.te) return;
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w;
     const int x = t - 2 * v - w;
     if (x < 1 || x > n - 1 - v) return;
-    const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+    const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
 
     // neighbour positions, interior flags, pivots
     int64_t q[NLOW];
@@ -178,7 +178,7 @@ __global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* 
     double Dn[NLOW];
 #pragma unroll
     for (int s = 0; s < NLOW; ++s) {
-        q[s] = Ln.rp[low_row(s)] + (int64_t)LANES * (t + low_dt(s));
+        q[s] = Ln.rp[low_row(s)] + (int64_t)lpb * (t + low_dt(s));
         in[s] = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
         Dn[s] = in[s] ? Df[q[s]] : 1.0;
     }
@@ -210,23 +210,23 @@ __global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* 
 // (the transposed factor, read from the upper neighbour; 0 if that neighbour
 // is not interior).
 __global__ void k_transpose_factors(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                    const LaneDev* __restrict__ lanes, int64_t S, const double* __restrict__ Lf,
+                                    const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S, const double* __restrict__ Lf,
                                     const double* __restrict__ Df, double* __restrict__ Lb) {
-    const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w;
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;
         if (x < 1 || x > n - 1 - v) continue;
-        const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
         Lb[idx] = 1.0 / Df[idx];
 #pragma unroll
         for (int s = 0; s < NLOW; ++s) {
             const bool in = interior(n, x - low_dx(s), y - low_dy(s), z - low_dz(s));
-            const int64_t qq = Ln.rp[up_row(s)] + (int64_t)LANES * (t + up_dt(s));
+            const int64_t qq = Ln.rp[up_row(s)] + (int64_t)lpb * (t + up_dt(s));
             Lb[(int64_t)(1 + s) * S + idx] = in ? Lf[(int64_t)s * S + qq] : 0.0;
         }
     }
@@ -246,19 +246,19 @@ __device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz) 
 }
 
 __global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                 const LaneDev* __restrict__ lanes, int64_t S, const double* __restrict__ Lf,
+                                 const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S, const double* __restrict__ Lf,
                                  const double* __restrict__ Df, double* __restrict__ samples) {
-    const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const TetDev& T = tets[B.tet];
     const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w, st = T.stride;
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;
         if (x < 1 || x > n - 1 - v) continue;
-        const int64_t idx = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
         for (int f = 0; f < NFIT; ++f) {
             const int dx = f < NLOW ? low_dx(f) : 0, dy = f < NLOW ? low_dy(f) : 0, dz = f < NLOW ? low_dz(f) : 0;
             const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
@@ -432,7 +432,7 @@ __global__ void k_qr_solve(const QrJob* __restrict__ jobs, int njobs, int m, con
 //   backward table [8][NC]: 1/D at (x, y, z), then L_d at p - d
 // Row record layout: [xm, 1/hw, fwd 7*NC, bwd 8*NC].
 __global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                             const LaneDev* __restrict__ lanes, int nslots, const double* __restrict__ coef,
+                             const LaneDev* __restrict__ lanes, int lpb, int groups, int nslots, const double* __restrict__ coef,
                              int NC, double* __restrict__ tab, float* __restrict__ tab32) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= nslots) return;
@@ -445,7 +445,7 @@ __global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __
             for (int k = 0; k < rec; ++k) tab32[(int64_t)slot * rec + k] = 0.f;
         return;
     }
-    const BlockDev& B = blocks[slot / LANES];
+    const BlockDev& B = blocks[slot / lpb];
     const TetDev& T = tets[B.tet];
     const int n = T.n, y = Ln.v - Ln.w, z = Ln.w;
     const int dgx = T.deg[0], dgy = T.deg[1], dgz = T.deg[2];
@@ -505,13 +505,13 @@ __global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __
 // mode 0: stream -> lex (dst[lex] = src[stream]); mode 1: lex -> stream.
 // Stencil/factor exports use `count` arrays spaced `sstride` / `lstride` apart.
 __global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                          const LaneDev* __restrict__ lanes, int mode, int count, const double* __restrict__ src,
+                          const LaneDev* __restrict__ lanes, int lpb, int groups, int mode, int count, const double* __restrict__ src,
                           double* __restrict__ dst, int64_t sstride, int lmul, int only_tet) {
-    const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
     if (only_tet >= 0 && B.tet != only_tet) return;
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const TetDev& T = tets[B.tet];
     const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
@@ -519,7 +519,7 @@ __global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __res
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;
         if (x < 1 || x > n - 1 - v) continue;
-        const int64_t si = Ln.rp[R_SELF] + (int64_t)LANES * t;
+        const int64_t si = Ln.rp[R_SELF] + (int64_t)lpb * t;
         const int64_t li = lexbase + lex_index(n, x, y, z);
         for (int k = 0; k < count; ++k) {
             if (mode == 0) dst[li * lmul + k] = src[k * sstride + si];
@@ -533,19 +533,19 @@ __global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __res
 namespace ilu {
 
 void launch_assemble(const Ctx& c, double* A8, double* Afull, hipStream_t st) {
-    k_assemble<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.nblocks, c.S, A8, Afull);
+    k_assemble<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.nblocks, c.S, A8, Afull);
 }
 
 void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags, hipStream_t st) {
-    k_factor_plane<<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, c.A8, Lf, Df, flags);
+    k_factor_plane<<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.A8, Lf, Df, flags);
 }
 
 void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st) {
-    k_transpose_factors<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, Lf, Df, Lb);
+    k_transpose_factors<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df, Lb);
 }
 
 void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st) {
-    k_gather_samples<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, Lf, Df, samples);
+    k_gather_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df, samples);
 }
 
 void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
@@ -560,12 +560,12 @@ void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, doubl
 }
 
 void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, double* tab, float* tab32, hipStream_t st) {
-    k_row_tables<<<(nslots + 127) / 128, 128, 0, st>>>(c.tets, c.blocks, c.lanes, nslots, coef, NC, tab, tab32);
+    k_row_tables<<<(nslots + 127) / 128, 128, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, nslots, coef, NC, tab, tab32);
 }
 
 void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,
                     int only_tet, hipStream_t st) {
-    k_permute<<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, mode, count, src, dst, sstride, lmul, only_tet);
+    k_permute<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, mode, count, src, dst, sstride, lmul, only_tet);
 }
 
 

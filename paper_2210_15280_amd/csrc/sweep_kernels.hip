@@ -19,16 +19,16 @@ namespace ilu {
 // go to `partial` (deterministic reduction afterwards).
 template <typename RT>
 __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                  const LaneDev* __restrict__ lanes, int64_t S,
+                                                  const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S,
                                                   const double* __restrict__ A8, const double* __restrict__ x,
                                                   const double* __restrict__ b, RT* __restrict__ r, int subtract,
                                                   double* __restrict__ partial) {
     __shared__ double red[256];
-    const int blk = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int blk, lane;
+    decode_group(groups, blk, lane);
     const int sub = threadIdx.x >> 6;
     const BlockDev& B = blocks[blk];
-    const LaneDev& Ln = lanes[(int64_t)blk * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)blk * lpb + lane];
     double acc2 = 0.0;
     const int t0 = B.tb + (int)blockIdx.y * RES_T;
     if (Ln.v != 0 && t0 <= B.te) {
@@ -36,14 +36,14 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
         int64_t rpl[NLOW], rpu[NLOW];
 #pragma unroll
         for (int s = 0; s < NLOW; ++s) {
-            rpl[s] = Ln.rp[low_row(s)] + (int64_t)LANES * low_dt(s);
-            rpu[s] = Ln.rp[up_row(s)] + (int64_t)LANES * up_dt(s);
+            rpl[s] = Ln.rp[low_row(s)] + (int64_t)lpb * low_dt(s);
+            rpu[s] = Ln.rp[up_row(s)] + (int64_t)lpb * up_dt(s);
         }
         const int t1 = min(B.te, t0 + RES_T - 1);
         for (int t = t0 + sub; t <= t1; t += 4) {
             const int xx = t - 2 * v - w;
             if (xx < 1 || xx > n - 1 - v) continue;
-            const int64_t off = (int64_t)LANES * t;
+            const int64_t off = (int64_t)lpb * t;
             const int64_t idx = Ln.rp[R_SELF] + off;
             double acc = A8[idx] * x[idx];
 #pragma unroll
@@ -68,13 +68,13 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
 
 // sum of squares of a stream vector restricted to active points (for ||b||)
 __global__ void __launch_bounds__(256) k_sumsq(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                               const LaneDev* __restrict__ lanes, const double* __restrict__ v_s,
+                                               const LaneDev* __restrict__ lanes, int lpb, int groups, const double* __restrict__ v_s,
                                                double* __restrict__ partial) {
     __shared__ double red[256];
-    const int blk = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int blk, lane;
+    decode_group(groups, blk, lane);
     const BlockDev& B = blocks[blk];
-    const LaneDev& Ln = lanes[(int64_t)blk * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)blk * lpb + lane];
     double acc2 = 0.0;
     const int t0 = B.tb + (int)blockIdx.y * RES_T;
     if (Ln.v != 0 && t0 <= B.te) {
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) k_sumsq(const TetDev* __restrict__ tets, 
         for (int t = t0 + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
             const int xx = t - 2 * Ln.v - Ln.w;
             if (xx < 1 || xx > n - 1 - Ln.v) continue;
-            const double a = v_s[Ln.rp[R_SELF] + (int64_t)LANES * t];
+            const double a = v_s[Ln.rp[R_SELF] + (int64_t)lpb * t];
             acc2 += a * a;
         }
     }
@@ -122,33 +122,41 @@ __device__ __forceinline__ T horner(const T* __restrict__ c, int NC, T eta) {
 }
 
 // Forward substitution on hyperplane t (Alg. 2, first loop, after the
-// residual):  w^p = r^p - sum_{d in D_l} L^p_d w^{p+d}.
+// residual):  w^p = r^p - sum_{d in D_l} L^p_d w^{p+d}.  The products are
+// accumulated in the order s, bnw, bc, be, w, se, bn (neighbours on older
+// hyperplanes first), the order the dataflow kernels use.
 template <typename T, bool STORED>
 __global__ void __launch_bounds__(64) k_fwd_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                  const LaneDev* __restrict__ lanes, int t, int64_t S,
+                                                  const LaneDev* __restrict__ lanes, int lpb, int groups, int t, int64_t S,
                                                   const double* __restrict__ Lf, const T* __restrict__ tab, int NC,
                                                   const T* __restrict__ r, T* __restrict__ w) {
-    const int b = blockIdx.x;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev& B = blocks[b];
     if (t < B.tb || t > B.te) return;
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + threadIdx.x];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const int n = tets[B.tet].n, v = Ln.v;
     const int x = t - 2 * v - Ln.w;
     if (x < 1 || x > n - 1 - v) return;
-    const int64_t off = (int64_t)LANES * t;
+    const int64_t off = (int64_t)lpb * t;
     const int64_t idx = Ln.rp[R_SELF] + off;
     T acc = r[idx];
+    constexpr int ord[7] = {1, 3, 5, 6, 0, 2, 4};
     if (STORED) {
 #pragma unroll
-        for (int s = 0; s < NLOW; ++s)
-            acc -= (T)Lf[(int64_t)s * S + idx] * w[Ln.rp[low_row(s)] + off + LANES * low_dt(s)];
+        for (int j = 0; j < NLOW; ++j) {
+            const int s = ord[j];
+            acc -= (T)Lf[(int64_t)s * S + idx] * w[Ln.rp[low_row(s)] + off + lpb * low_dt(s)];
+        }
     } else {
-        const T* c = tab + ((int64_t)b * LANES + threadIdx.x) * (2 + 15 * NC);
+        const T* c = tab + ((int64_t)b * lpb + lane) * (2 + 15 * NC);
         const T eta = ((T)x - c[0]) * c[1];
 #pragma unroll
-        for (int s = 0; s < NLOW; ++s)
-            acc -= horner(c + 2 + s * NC, NC, eta) * w[Ln.rp[low_row(s)] + off + LANES * low_dt(s)];
+        for (int j = 0; j < NLOW; ++j) {
+            const int s = ord[j];
+            acc -= horner(c + 2 + s * NC, NC, eta) * w[Ln.rp[low_row(s)] + off + lpb * low_dt(s)];
+        }
     }
     w[idx] = acc;
 }
@@ -158,32 +166,38 @@ __global__ void __launch_bounds__(64) k_fwd_plane(const TetDev* __restrict__ tet
 //   w^p = (D^p)^{-1} w^p - sum_{d in D_l} L^{p-d}_d w^{p-d};  x^p += w^p.
 template <typename T, bool STORED>
 __global__ void __launch_bounds__(64) k_bwd_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                  const LaneDev* __restrict__ lanes, int t, int64_t S,
+                                                  const LaneDev* __restrict__ lanes, int lpb, int groups, int t, int64_t S,
                                                   const double* __restrict__ Lb, const T* __restrict__ tab, int NC,
                                                   T* __restrict__ w, double* __restrict__ x) {
-    const int b = blockIdx.x;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev& B = blocks[b];
     if (t < B.tb || t > B.te) return;
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + threadIdx.x];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const int n = tets[B.tet].n, v = Ln.v;
     const int xx = t - 2 * v - Ln.w;
     if (xx < 1 || xx > n - 1 - v) return;
-    const int64_t off = (int64_t)LANES * t;
+    const int64_t off = (int64_t)lpb * t;
     const int64_t idx = Ln.rp[R_SELF] + off;
     T acc;
+    constexpr int ord[7] = {1, 3, 5, 6, 0, 2, 4};
     if (STORED) {
         acc = w[idx] * (T)Lb[idx];
 #pragma unroll
-        for (int s = 0; s < NLOW; ++s)
-            acc -= (T)Lb[(int64_t)(1 + s) * S + idx] * w[Ln.rp[up_row(s)] + off + LANES * up_dt(s)];
+        for (int j = 0; j < NLOW; ++j) {
+            const int s = ord[j];
+            acc -= (T)Lb[(int64_t)(1 + s) * S + idx] * w[Ln.rp[up_row(s)] + off + lpb * up_dt(s)];
+        }
     } else {
-        const T* c = tab + ((int64_t)b * LANES + threadIdx.x) * (2 + 15 * NC);
+        const T* c = tab + ((int64_t)b * lpb + lane) * (2 + 15 * NC);
         const T eta = ((T)xx - c[0]) * c[1];
         acc = w[idx] * horner(c + 2 + 7 * NC, NC, eta);
 #pragma unroll
-        for (int s = 0; s < NLOW; ++s)
-            acc -= horner(c + 2 + (8 + s) * NC, NC, eta) * w[Ln.rp[up_row(s)] + off + LANES * up_dt(s)];
+        for (int j = 0; j < NLOW; ++j) {
+            const int s = ord[j];
+            acc -= horner(c + 2 + (8 + s) * NC, NC, eta) * w[Ln.rp[up_row(s)] + off + lpb * up_dt(s)];
+        }
     }
     w[idx] = acc;
     x[idx] += (double)acc;
@@ -193,16 +207,16 @@ __global__ void __launch_bounds__(64) k_bwd_plane(const TetDev* __restrict__ tet
 // lexicographic order (inspection only).
 template <typename T>
 __global__ void k_export_surrogate(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                   const LaneDev* __restrict__ lanes, const T* __restrict__ tab, int NC, int only_tet,
+                                   const LaneDev* __restrict__ lanes, int lpb, int groups, const T* __restrict__ tab, int NC, int only_tet,
                                    double* __restrict__ L_out, double* __restrict__ Dinv_out) {
-    const int b = blockIdx.x;
-    const int lane = threadIdx.x & 63;
+    int b, lane;
+    decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
     if (B.tet != only_tet) return;
-    const LaneDev& Ln = lanes[(int64_t)b * LANES + lane];
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w;
-    const T* c = tab + ((int64_t)b * LANES + lane) * (2 + 15 * NC);
+    const T* c = tab + ((int64_t)b * lpb + lane) * (2 + 15 * NC);
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;
         if (x < 1 || x > n - 1 - v) continue;
@@ -218,26 +232,26 @@ __global__ void k_export_surrogate(const TetDev* __restrict__ tets, const BlockD
 
 void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, double* Dinv_out, hipStream_t st) {
     if (f32)
-        k_export_surrogate<float><<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.tab32, c.NC, tet, L_out,
+        k_export_surrogate<float><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.tab32, c.NC, tet, L_out,
                                                              Dinv_out);
     else
-        k_export_surrogate<double><<<c.nblocks, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.tab64, c.NC, tet, L_out,
+        k_export_surrogate<double><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.tab64, c.NC, tet, L_out,
                                                               Dinv_out);
 }
 
 void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
                      hipStream_t st) {
-    dim3 grid(c.nblocks, c.res_chunks);
+    dim3 grid(c.nblocks * c.groups, c.res_chunks);
     if (f32)
-        k_residual<float><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, c.A8, x, b, (float*)r, subtract, partial);
+        k_residual<float><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (float*)r, subtract, partial);
     else
-        k_residual<double><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.S, c.A8, x, b, (double*)r, subtract,
+        k_residual<double><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (double*)r, subtract,
                                                   partial);
 }
 
 void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st) {
-    dim3 grid(c.nblocks, c.res_chunks);
-    k_sumsq<<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, v, partial);
+    dim3 grid(c.nblocks * c.groups, c.res_chunks);
+    k_sumsq<<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, v, partial);
 }
 
 void launch_reduce(const double* partial, int64_t count, double* out, int slot, hipStream_t st) {
@@ -246,25 +260,25 @@ void launch_reduce(const double* partial, int64_t count, double* out, int slot, 
 
 void launch_fwd_plane(const Ctx& c, int variant, int t, hipStream_t st) {
     if (variant == 0)
-        k_fwd_plane<double, true><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, c.Lf, nullptr, 0,
+        k_fwd_plane<double, true><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.Lf, nullptr, 0,
                                                             (const double*)c.r, (double*)c.w);
     else if (variant == 1)
-        k_fwd_plane<double, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab64, c.NC,
+        k_fwd_plane<double, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab64, c.NC,
                                                              (const double*)c.r, (double*)c.w);
     else
-        k_fwd_plane<float, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab32, c.NC,
+        k_fwd_plane<float, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab32, c.NC,
                                                             (const float*)c.r, (float*)c.w);
 }
 
 void launch_bwd_plane(const Ctx& c, int variant, int t, double* x, hipStream_t st) {
     if (variant == 0)
-        k_bwd_plane<double, true><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, c.Lb, nullptr, 0,
+        k_bwd_plane<double, true><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.Lb, nullptr, 0,
                                                             (double*)c.w, x);
     else if (variant == 1)
-        k_bwd_plane<double, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab64, c.NC,
+        k_bwd_plane<double, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab64, c.NC,
                                                              (double*)c.w, x);
     else
-        k_bwd_plane<float, false><<<c.nblocks, 64, 0, st>>>(c.tets, c.blocks, c.lanes, t, c.S, nullptr, c.tab32, c.NC,
+        k_bwd_plane<float, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab32, c.NC,
                                                             (float*)c.w, x);
 }
 

@@ -40,11 +40,12 @@ def _cases():
     ]
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (16, 32)])
 @pytest.mark.parametrize("ti", range(5))
-def test_stencil_assembly_parity(torch, pkg, ti):
+def test_stencil_assembly_parity(torch, pkg, ti, tile):
     t = _cases()[ti]
     P = O.Problem.from_tet(t)
-    sm = pkg.Smoother([t], pkg.STORED_F64)
+    sm = pkg.Smoother([t], pkg.STORED_F64, tile=tile)
     A = sm.stencil(0).cpu().numpy()
     want = np.where(P.col >= 0, P.A, 0.0)
     assert _rel(A, want) < 1e-13
@@ -53,26 +54,30 @@ def test_stencil_assembly_parity(torch, pkg, ti):
     assert _rel(y, P.apply(x)) < 1e-13
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32)])
 @pytest.mark.parametrize("ti", range(5))
-def test_stored_factor_parity(torch, pkg, ti):
+def test_stored_factor_parity(torch, pkg, ti, tile):
     t = _cases()[ti]
     P = O.Problem.from_tet(t)
     L, U, D = P.ilu0()
-    sm = pkg.Smoother([t], pkg.STORED_F64)
+    sm = pkg.Smoother([t], pkg.STORED_F64, tile=tile)
     Lg, Dg = sm.factors(0)
     assert _rel(Lg.cpu().numpy(), L) < 1e-12
     assert _rel(Dg.cpu().numpy(), D) < 1e-12
 
 
-@pytest.mark.parametrize("sched", ["plane", "dataflow"])
+SCHEDS = {"plane": (1, (0, 0)), "flow8x8": (2, (8, 8)), "flow16x16": (2, (16, 16)), "flow16x32": (2, (16, 32))}
+
+
+@pytest.mark.parametrize("sched", list(SCHEDS))
 @pytest.mark.parametrize("ti", range(5))
 def test_stored_sweep_parity(torch, pkg, sched, ti):
     t = _cases()[ti]
     P = O.Problem.from_tet(t)
     L, U, D = P.ilu0()
     b = t.rhs()
-    s = pkg.SCHED_PLANE if sched == "plane" else pkg.SCHED_DATAFLOW
-    sm = pkg.Smoother([t], pkg.STORED_F64, schedule=s)
+    s, tile = SCHEDS[sched]
+    sm = pkg.Smoother([t], pkg.STORED_F64, schedule=s, tile=tile)
     x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
     bt = torch.tensor(b, device="cuda")
     done = 0
@@ -83,24 +88,28 @@ def test_stored_sweep_parity(torch, pkg, sched, ti):
         assert _rel(x.cpu().numpy(), want) < 1e-12, (sched, ti, done)
 
 
-def test_schedules_agree_bitwise(torch, pkg):
-    t = W.make_tet(9, 6, *W.KAPPA_SIN, jitter=0.15)
+@pytest.mark.parametrize("level", [6, 7])
+def test_schedules_and_shapes_agree_bitwise(torch, pkg, level):
+    # the per-point arithmetic is the same in every schedule and block shape
+    t = W.make_tet(9, level, *W.KAPPA_SIN, jitter=0.15)
     b = torch.tensor(t.rhs(), device="cuda")
-    out = []
-    for s in (pkg.SCHED_PLANE, pkg.SCHED_DATAFLOW):
-        for v in (pkg.STORED_F64, pkg.SURR_F32):
-            sm = pkg.Smoother([t], v, degree=3, stride=4, schedule=s)
+    for v in (pkg.STORED_F64, pkg.SURR_F64, pkg.SURR_F32):
+        out = []
+        for s, tile in SCHEDS.values():
+            sm = pkg.Smoother([t], v, degree=3, stride=4, schedule=s, tile=tile)
             x = torch.zeros_like(b)
             sm.smooth(x, b, 4)
             out.append(x.cpu().numpy())
-    assert np.array_equal(out[0], out[2])
-    assert np.array_equal(out[1], out[3])
+        for o in out[1:]:
+            assert np.array_equal(o, out[0]), v
 
 
-def test_batch_equals_solo(torch, pkg):
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_batch_equals_solo(torch, pkg, tile):
     tets = W.batch_tets(11, 6, (4, 5, 6))
     for variant in (pkg.STORED_F64, pkg.SURR_F32):
         kw = dict(degree=2, stride=2) if variant != pkg.STORED_F64 else {}
+        kw["tile"] = tile
         sm = pkg.Smoother(tets, variant, **kw)
         b = torch.tensor(np.concatenate([t.rhs() for t in tets]), device="cuda")
         x = torch.zeros_like(b)
@@ -133,7 +142,7 @@ def test_surrogate_fit_parity(torch, pkg, level, deg, stride):
     assert _rel(Dg.cpu().numpy(), Do) < 1e-7
 
 
-@pytest.mark.parametrize("sched", ["plane", "dataflow"])
+@pytest.mark.parametrize("sched", list(SCHEDS))
 def test_surrogate_f64_sweep_parity(torch, pkg, sched):
     # same coefficients on both sides (the oracle's), so only evaluation order differs
     t = W.make_tet(6, 6, *W.KAPPA_SIN, jitter=0.15)
@@ -142,8 +151,8 @@ def test_surrogate_f64_sweep_parity(torch, pkg, sched):
     L, U, D = P.ilu0()
     c = O.fit_surrogate(6, L, D, deg, 4)
     Lw, Dinv = O.eval_surrogate(6, c, deg)
-    s = pkg.SCHED_PLANE if sched == "plane" else pkg.SCHED_DATAFLOW
-    sm = pkg.Smoother([t], pkg.SURR_F64, degree=deg, stride=4, schedule=s)
+    s, tile = SCHEDS[sched]
+    sm = pkg.Smoother([t], pkg.SURR_F64, degree=deg, stride=4, schedule=s, tile=tile)
     sm.set_surrogate(0, c)
     Lg, Dg = sm.surrogate_values(0)
     assert _rel(Lg.cpu().numpy(), Lw) < 1e-12
@@ -155,7 +164,7 @@ def test_surrogate_f64_sweep_parity(torch, pkg, sched):
     assert _rel(x.cpu().numpy(), want) < 1e-11
 
 
-@pytest.mark.parametrize("sched", ["plane", "dataflow"])
+@pytest.mark.parametrize("sched", list(SCHEDS))
 def test_surrogate_f32_mixed_parity(torch, pkg, sched):
     # FP32 weights and substitutions: per-sweep differences are a few FP32 ulps
     # of the correction; the FP64 residual keeps both iterations on the same path.
@@ -165,8 +174,8 @@ def test_surrogate_f32_mixed_parity(torch, pkg, sched):
     L, U, D = P.ilu0()
     c = O.fit_surrogate(6, L, D, deg, 4)
     Lw, Dinv = O.eval_surrogate(6, c, deg)
-    s = pkg.SCHED_PLANE if sched == "plane" else pkg.SCHED_DATAFLOW
-    sm = pkg.Smoother([t], pkg.SURR_F32, degree=deg, stride=4, schedule=s)
+    s, tile = SCHEDS[sched]
+    sm = pkg.Smoother([t], pkg.SURR_F32, degree=deg, stride=4, schedule=s, tile=tile)
     sm.set_surrogate(0, c)
     Lg, Dg = sm.surrogate_values(0)
     assert _rel(Lg.cpu().numpy(), Lw) < 1e-5
