@@ -29,10 +29,10 @@ def kernel_bytes(variant: str):
     res = 8 + 8 + 64 + wb                    # x, b, A (8 weights), r
     if variant == "stored_f64":
         fwd = 8 + 56 + 8                      # r, L (7), w
-        bwd = 8 + 8 + 56 + 8 + 8 + 8          # w in, 1/D, L^T (7), w out, x in, x out
+        bwd = 8 + 8 + 56 + 8 + 8              # w in, 1/D, L^T (7), x in, x out
     else:
         fwd = wb + wb                         # r, w
-        bwd = wb + wb + 8 + 8                 # w in, w out, x in, x out
+        bwd = wb + 8 + 8                      # w in, x in, x out
     return {"residual": res, "forward": fwd, "backward": bwd}
 
 

@@ -77,6 +77,7 @@ struct ilu_handle_s {
     int NC = 0, K = 0;
     int bv = 8, bw = 8;  // block shape in rows
     int64_t S = 0;
+    int64_t XE = 0;  // exchange entries (all blocks)
     int64_t nlex = 0;
     int tmin = 0, tmax = 0;
     std::vector<TetDev> tets;
@@ -87,7 +88,7 @@ struct ilu_handle_s {
     DevBuf A8, Lf, Df, Lb, tab64, tab32, coef_d;
     DevBuf xs, bs, r, w;
     DevBuf partial, norms, flags;
-    DevBuf order_fwd, order_bwd, progress, ticket;
+    DevBuf order_fwd, order_bwd, xch, ticket;
     int64_t npartial = 0;
     int flow_grid = 0;
     hipEvent_t ev[8] = {};
@@ -124,7 +125,7 @@ struct ilu_handle_s {
         Flow f;
         f.order_fwd = order_fwd.as<int32_t>();
         f.order_bwd = order_bwd.as<int32_t>();
-        f.progress = progress.as<int32_t>();
+        f.xch = xch.as<uint64_t>();
         f.ticket = ticket.as<int32_t>();
         f.flags = flags.as<int32_t>();
         f.grid = flow_grid;
@@ -169,7 +170,7 @@ int build_layout(ilu_handle_t h) {
     int nmax = 0;
     for (auto& T : h->tets) nmax = std::max(nmax, T.n);
     const int64_t Z = (int64_t)lpb * (3 * nmax + 8);
-    int64_t S = Z;
+    int64_t S = Z, XE = 0;
     std::vector<std::vector<int>> bmap(h->ntets);
     std::vector<int> nbv(h->ntets), nbw(h->ntets);
     int64_t lexoff = 0;
@@ -205,12 +206,15 @@ int build_layout(ilu_handle_t h) {
                 B.len = te - tb + 1 + 2 * PAD;
                 B.base = S;
                 S += (int64_t)B.len * lpb;
+                B.xoff = XE;
+                XE += (int64_t)B.len * (bv + bw);
                 bmap[ti][(size_t)kv * nbw[ti] + kw] = (int)h->blocks.size();
                 h->blocks.push_back(B);
             }
         T.nblk = (int)h->blocks.size() - T.blk0;
     }
     h->S = S;
+    h->XE = XE;
     h->nlex = lexoff;
     auto block_at = [&](int ti, int kv, int kw) -> int {
         if (kv < 0 || kw < 0 || kv >= nbv[ti] || kw >= nbw[ti]) return -1;
@@ -449,6 +453,9 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
         h->bv = h->bw = 8;
         if (ntets == 1 && lmax >= 8) { h->bv = 16; h->bw = 32; }
         else if (ntets == 1 && lmax == 7) { h->bv = 16; h->bw = 16; }
+        // FP64 surrogate polynomials with 4+ coefficients per row do not fit the
+        // registers of a 9-wave workgroup
+        if (h->variant == ILU_SURR_F64 && h->NC >= 4 && h->bw == 32) h->bw = 16;
     }
     if (int e = build_layout(h)) return e;
     *nsamples = soff;
@@ -509,8 +516,9 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         return ILU_ENOMEM;
     if (upload(h->order_fwd, topo_order(h->blocks, true), st) || upload(h->order_bwd, topo_order(h->blocks, false), st))
         return ILU_ENOMEM;
-    if (h->progress.alloc(std::max<size_t>(1, h->blocks.size()) * sizeof(int32_t), st) ||
-        h->ticket.alloc(2 * sizeof(int32_t), st))
+    // exchange entries: one 64-bit word (FP32 values) or two (FP64), cleared to tag 0
+    const size_t xwords = (size_t)h->XE * (h->variant == ILU_SURR_F32 ? 1 : 2);
+    if (h->xch.alloc(std::max<size_t>(1, xwords) * sizeof(uint64_t), st) || h->ticket.alloc(4 * sizeof(int32_t), st))
         return ILU_ENOMEM;
     h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->bv, h->bw));
     for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
@@ -587,32 +595,66 @@ int64_t check_layout(ilu_handle_t h) {
                     }
             }
         }
-        // dataflow halo rows: forward (pred) and backward (succ)
-        for (int dir = 0; dir < 2; ++dir)
-            for (int hl = 0; hl < bv + bw + 1; ++hl) {
-                int64_t rp;
-                int prod;
-                if (dir == 0) {
-                    if (hl < bw) { rp = h->lanes[b * LANES + hl * bv].rp[R_VM]; prod = B.pred[0]; }
-                    else if (hl < bw + bv) { rp = h->lanes[b * LANES + (hl - bw)].rp[R_WM]; prod = B.pred[1]; }
-                    else { rp = h->lanes[b * LANES].rp[R_VMWM]; prod = B.pred[2]; }
-                } else {
-                    if (hl < bw) { rp = h->lanes[b * LANES + hl * bv + bv - 1].rp[R_VP]; prod = B.succ[0]; }
-                    else if (hl < bw + bv) {
-                        rp = h->lanes[b * LANES + (bw - 1) * bv + (hl - bw)].rp[R_WP];
-                        prod = B.succ[1];
-                    } else { rp = h->lanes[b * LANES + LANES - 1].rp[R_VPWP]; prod = B.succ[2]; }
-                }
-                if (prod < 0) { bad += rp != 0; continue; }
-                const BlockDev& PB = h->blocks[prod];
-                for (int sl = PB.tb; sl <= PB.te; ++sl) {
-                    const int64_t q = rp + (int64_t)LANES * sl;
-                    if (q < 0 || q >= S) { ++bad; continue; }
-                    if (rp != 0 && (q < PB.base || q >= PB.base + (int64_t)PB.len * LANES)) ++bad;
-                    if (owner[q] >= 0 && owner[q] / LANES != prod) ++bad;
+    }
+    // dataflow exchange: replay the outgoing-entry stores of every block and
+    // hyperplane with the kernels' own index functions, then check that every
+    // halo read lands on a word written by the producer lane that owns the
+    // halo row (rows outside the lattice: no producer, or an unused producer
+    // lane, which writes zeros)
+    for (int dir = 0; dir < 2; ++dir)
+        for (int wds = 1; wds <= 2; ++wds) {
+            const int nx = bv + bw;
+            const int64_t nw = h->XE * wds;
+            std::vector<int64_t> wr_lane(nw, -1);
+            std::vector<int32_t> wr_t(nw, -1);
+            for (size_t b = 0; b < h->blocks.size(); ++b) {
+                const BlockDev& B = h->blocks[b];
+                for (int j = 0; j < nx; ++j) {
+                    int vl, wl;
+                    xch_out_lane(dir, j, bv, bw, &vl, &wl);
+                    const int l = wl * bv + vl;
+                    if (vl < 0 || vl >= bv || wl < 0 || wl >= bw) { ++bad; continue; }
+                    for (int t = B.tb; t <= B.te; ++t) {
+                        const int64_t q = xch_word(B.xoff, B.tlo, nx, wds, t, j);
+                        if (q < B.xoff * wds || q + wds > (B.xoff + (int64_t)B.len * nx) * wds || q + wds > nw) {
+                            ++bad;
+                            continue;
+                        }
+                        if (wr_lane[q] != -1) ++bad;  // one writer per word and sweep
+                        wr_lane[q] = (int64_t)(b * LANES + l);
+                        wr_t[q] = t;
+                    }
                 }
             }
-    }
+            for (size_t b = 0; b < h->blocks.size(); ++b) {
+                const BlockDev& B = h->blocks[b];
+                const int n = h->tets[B.tet].n;
+                for (int l = 0; l < LANES; ++l) {
+                    int k, j;
+                    if (!xch_halo_role(dir, l, bv, bw, &k, &j)) continue;
+                    // the halo row this role stands for
+                    const int edge_v = dir == 0 ? B.V0 - 1 : B.V0 + bv, edge_w = dir == 0 ? B.W0 - 1 : B.W0 + bw;
+                    int v, w;
+                    if (k == 0) { v = edge_v; w = B.W0 + l; }
+                    else if (k == 1) { v = B.V0 + (l - bw); w = edge_w; }
+                    else { v = edge_v; w = edge_w; }
+                    const bool in = v >= 2 && v <= n - 2 && w >= 1 && w <= v - 1;
+                    const int prod = dir == 0 ? B.pred[k] : B.succ[k];
+                    if (prod < 0) { bad += in; continue; }
+                    const BlockDev& PB = h->blocks[prod];
+                    if (PB.tet != B.tet) { ++bad; continue; }
+                    for (int s = PB.tb; s <= PB.te; ++s) {
+                        const int64_t q = xch_word(PB.xoff, PB.tlo, nx, wds, s, j);
+                        if (q < 0 || q + wds > nw || wr_lane[q] < 0 || wr_t[q] != s || wr_lane[q] / LANES != prod) {
+                            ++bad;
+                            continue;
+                        }
+                        const LaneDev& PL = h->lanes[wr_lane[q]];
+                        if (in ? (PL.v != v || PL.w != w) : PL.v != 0) ++bad;
+                    }
+                }
+            }
+        }
     // topological orders
     for (int dir = 0; dir < 2; ++dir) {
         std::vector<int32_t> ord = topo_order(h->blocks, dir == 0);
@@ -658,7 +700,7 @@ void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
         for (int t = h->tmin; t <= h->tmax; ++t) launch_fwd_plane(c, h->variant, t, st);
     } else {
         const Flow f = h->flow();
-        launch_flow_reset(c, f, st);
+        launch_flow_reset(f, st);
         launch_fwd_flow(c, f, h->variant, st);
     }
 }
@@ -668,7 +710,7 @@ void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
         for (int t = h->tmax; t >= h->tmin; --t) launch_bwd_plane(c, h->variant, t, h->xs.as<double>(), st);
     } else {
         const Flow f = h->flow();
-        launch_flow_reset(c, f, st);
+        launch_flow_reset(f, st);
         launch_bwd_flow(c, f, h->variant, h->xs.as<double>(), st);
     }
 }

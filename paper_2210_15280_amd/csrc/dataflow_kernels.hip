@@ -7,21 +7,31 @@
 // workgroup that took its ticket earlier: the wait chain always ends.
 //
 // Inside a block all lanes advance hyperplane by hyperplane in lock step (one
-// workgroup barrier per hyperplane).  The values of the last three
+// LDS-only workgroup barrier per hyperplane).  The values of the last three
 // hyperplanes live in a 4-slot LDS grid of (BV+1) x (BW+1) cells: the block's
 // own rows plus one halo column and one halo row holding rows of the
-// neighbouring blocks.  Halo values come from other workgroups: halo threads
-// read them from the w stream with device-coherent loads once the producer's
-// progress counter covers them, one batch of H hyperplanes ahead of use, park
-// them in a staging ring, and copy one hyperplane per step into the grid.
-// w is written with device-coherent stores; each block publishes its progress
-// once per batch after waiting for those stores.
+// neighbouring blocks.
 //
-// The seven products of a point are accumulated oldest hyperplane first
-// (the t-2 / t-3 neighbours, then the three t-1 neighbours), so only three
-// fused multiply-adds sit on the hyperplane-to-hyperplane dependency chain.
+// Blocks hand boundary values to each other through an exchange buffer.  A
+// separate halo wave in every workgroup does all of this traffic, so the
+// compute waves never wait on another block's memory: after every
+// hyperplane it copies the block's outgoing edge values (last column and last
+// row in sweep direction) from LDS to the buffer, each with a 32-bit launch
+// tag in one 64-bit word (FP64 values: two words, one per half); it loads the
+// incoming entries D hyperplanes ahead and checks the tag right before the
+// value goes into the LDS grid; only a stale entry is polled again.  No block ever waits
+// for its own stores, and no progress counter sits between producer and
+// consumer.  The tag is a device counter that the reset kernel advances
+// before every sweep, so graph replays never see entries of earlier sweeps
+// (tags repeat after 2^32 sweeps).
 //
-// A wait that exceeds a fixed bound sets flags[2] and gives up, so a logic
+// Per-lane operands (r, w, x, stored factors) stream through register rings
+// loaded U hyperplanes ahead.  The seven products of a point are accumulated
+// oldest hyperplane first (the t-2 / t-3 neighbours, then the three t-1
+// neighbours), so only three fused multiply-adds sit on the
+// hyperplane-to-hyperplane dependency chain.
+//
+// A poll that exceeds a fixed bound sets flags[2] and gives up, so a logic
 // error can never hang the device.
 #include <hip/hip_runtime.h>
 
@@ -32,7 +42,7 @@ namespace ilu {
 
 namespace {
 
-constexpr long SPIN_LIMIT = 1L << 24;
+constexpr long SPIN_LIMIT = 1L << 20;
 // accumulation order over D_l: s, bnw, bc, be (older hyperplanes) then w, se, bn
 constexpr int ORD[7] = {1, 3, 5, 6, 0, 2, 4};
 
@@ -43,11 +53,6 @@ __device__ __forceinline__ void st_dev(T* p, T v) {
 template <typename T>
 __device__ __forceinline__ T ld_dev(const T* p) {
     return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void wait_stores() {
-    // s_waitcnt vmcnt(0): every earlier vector memory access of this wave
-    // (including the device-coherent w stores) has completed.
-    __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
 // Workgroup barrier that orders LDS traffic only: a full __syncthreads()
@@ -66,57 +71,113 @@ __device__ __forceinline__ T horner(const T* c, T eta) {
     return acc;
 }
 
-// Wait until block `prod` has published at least `need` finished hyperplanes.
-// `known` caches the last value observed, so most calls return at once.
-// A wait that exceeds the bound (or a bound hit anywhere else) gives up.
-__device__ __forceinline__ void wait_progress(const int32_t* progress, int prod, int need, int& known,
-                                              int32_t* flags) {
-    if (known >= need) return;
-    long spins = 0;
-    int v = ld_dev(&progress[prod]);
-    while (v < need) {
-        __builtin_amdgcn_s_sleep(1);
-        ++spins;
-        if ((spins & 1023) == 0 && ld_dev(&flags[2])) break;
-        if (spins > SPIN_LIMIT) {
-            atomicOr(&flags[2], 1);
-            break;
-        }
-        v = ld_dev(&progress[prod]);
-    }
-    known = v;
+// ---- tagged exchange entries: 32-bit payload | 32-bit tag per 64-bit word
+template <typename T>
+struct XEnt;
+template <>
+struct XEnt<float> {
+    static constexpr int W = 1;
+    uint64_t u[1];
+};
+template <>
+struct XEnt<double> {
+    static constexpr int W = 2;
+    uint64_t u[2];
+};
+
+__device__ __forceinline__ void x_put(uint64_t* p, float v, uint32_t tag) {
+    st_dev(p, ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v));
+}
+__device__ __forceinline__ void x_put(uint64_t* p, double v, uint32_t tag) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    st_dev(p, ((uint64_t)tag << 32) | (b & (uint64_t)0xffffffffu));
+    st_dev(p + 1, ((uint64_t)tag << 32) | (b >> 32));
+}
+template <typename T>
+__device__ __forceinline__ void x_get(XEnt<T>& e, const uint64_t* p) {
+#pragma unroll
+    for (int k = 0; k < XEnt<T>::W; ++k) e.u[k] = ld_dev(p + k);
+}
+template <typename T>
+__device__ __forceinline__ bool x_ok(const XEnt<T>& e, uint32_t tag) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < XEnt<T>::W; ++k) ok = ok && (uint32_t)(e.u[k] >> 32) == tag;
+    return ok;
+}
+__device__ __forceinline__ float x_val(const XEnt<float>& e) { return __uint_as_float((uint32_t)e.u[0]); }
+__device__ __forceinline__ double x_val(const XEnt<double>& e) {
+    return __longlong_as_double((long long)((e.u[0] & (uint64_t)0xffffffffu) | (e.u[1] << 32)));
 }
 
+// Halo role of a thread: one incoming row (column halo, row halo or corner).
 struct Halo {
-    int idx = -1;      // halo row index in the staging ring (-1: no halo role)
-    int cell = 0;      // grid cell of the halo row
-    int64_t rp = 0;    // row pointer of the halo row
-    int prod = -1;     // producing block (-1: no block, value 0)
-    int ptb = 0, pte = 0;
+    bool role = false;
+    int cell = 0;          // grid cell the row's value goes to
+    int ptb = 1, pte = 0;  // producer's hyperplane range (empty: no producer, value 0)
+    int ptlo = 0, j = 0;   // producer's time origin and the entry of this row
+    int64_t pxoff = 0;     // producer's exchange window
+    __device__ bool has(int s) const { return s >= ptb && s <= pte; }
 };
+
+template <typename T>
+__device__ __forceinline__ const uint64_t* halo_at(const Halo& h, const uint64_t* xch, int nx, int s) {
+    return xch + xch_word(h.pxoff, h.ptlo, nx, XEnt<T>::W, s, h.j);
+}
+
+template <typename T>
+__device__ __forceinline__ void halo_issue(const Halo& h, const uint64_t* xch, int nx, int s, XEnt<T>& e) {
+    if (h.has(s)) x_get(e, halo_at<T>(h, xch, nx, s));
+}
+
+// Value of the halo row at hyperplane s from an entry loaded earlier; a stale
+// entry is polled until the producer's store with this launch's tag arrives.
+template <typename T>
+__device__ __forceinline__ T halo_take(const Halo& h, const uint64_t* xch, int nx, int s, XEnt<T>& e, uint32_t tag,
+                                       int32_t* flags) {
+    if (!h.has(s)) return (T)0;
+    if (!x_ok(e, tag)) {
+        long spins = 0;
+        for (;;) {
+            __builtin_amdgcn_s_sleep(1);
+            x_get(e, halo_at<T>(h, xch, nx, s));
+            if (x_ok(e, tag)) break;
+            ++spins;
+            if ((spins & 255) == 0 && ld_dev(&flags[2])) break;
+            if (spins > SPIN_LIMIT) {
+                atomicOr(&flags[2], 1);
+                break;
+            }
+        }
+    }
+    return x_val(e);
+}
 
 }  // namespace
 
 // ------------------------------------------------------------------ forward
+//
+// Workgroup = BV*BW compute threads (one per row) + one halo wave.  Halo-wave
+// lane i < BW+BV+1 owns incoming halo row i (column, row, corner) and lane
+// i < BW+BV outgoing entry i; the producer lane of each entry is the one
+// xch_out_lane names.  Both paths pass the same barriers.
 
-template <typename T, bool STORED, int H, int NC, int BV, int BW>
-__global__ void __launch_bounds__(BV* BW) k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                     const LaneDev* __restrict__ lanes, int nblocks, int64_t S,
-                                                     const double* __restrict__ Lf, const T* __restrict__ tab,
-                                                     const T* __restrict__ r, T* __restrict__ w,
-                                                     const int32_t* __restrict__ order, int32_t* __restrict__ progress,
-                                                     int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
+__global__ void __launch_bounds__(BV* BW + WAVE)
+    k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
+               int nblocks, int64_t S, const double* __restrict__ Lf, const T* __restrict__ tab,
+               const T* __restrict__ r, T* __restrict__ w, const int32_t* __restrict__ order,
+               uint64_t* __restrict__ xch, int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
     constexpr int NT = BV * BW;
     constexpr int GW = BV + 1;
     constexpr int GC = (BV + 1) * (BW + 1);
-    constexpr int NH = BV + BW + 1;
-    static_assert((H & (H - 1)) == 0, "H must be a power of two");
+    constexpr int NX = BV + BW;
+    constexpr int XW = XEnt<T>::W;
+    static_assert(NT % WAVE == 0 && NX + 1 <= WAVE, "block shape");
     __shared__ T grid[4 * GC];
-    __shared__ T stage[H * NH];
     __shared__ int s_ticket;
     const int l = threadIdx.x;
-    const int vl = l % BV, wl = l / BV;
-    const int cell = (wl + 1) * GW + (vl + 1);
+    const uint32_t tag = (uint32_t)ticket[2];
     for (;;) {
         if (l == 0) s_ticket = atomicAdd(&ticket[0], 1);
         __syncthreads();
@@ -125,154 +186,138 @@ __global__ void __launch_bounds__(BV* BW) k_fwd_flow(const TetDev* __restrict__ 
         if (k >= nblocks) return;
         const int b = order[k];
         const BlockDev B = blocks[b];
-        const LaneDev& Ln = lanes[(int64_t)b * NT + l];
-        const bool valid = Ln.v != 0;
-        const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
-        const int64_t rp = Ln.rp[R_SELF];
-        // halo roles: left column (v = V0-1), bottom row (w = W0-1), corner
-        Halo hl;
-        if (l < BW) {
-            hl.idx = l;
-            hl.cell = (l + 1) * GW;
-            hl.rp = lanes[(int64_t)b * NT + l * BV].rp[R_VM];
-            hl.prod = B.pred[0];
-        } else if (l < BW + BV) {
-            hl.idx = l;
-            hl.cell = l - BW + 1;
-            hl.rp = lanes[(int64_t)b * NT + (l - BW)].rp[R_WM];
-            hl.prod = B.pred[1];
-        } else if (l == BW + BV) {
-            hl.idx = l;
-            hl.cell = 0;
-            hl.rp = lanes[(int64_t)b * NT].rp[R_VMWM];
-            hl.prod = B.pred[2];
-        }
-        if (hl.prod >= 0) {
-            hl.ptb = blocks[hl.prod].tb;
-            hl.pte = blocks[hl.prod].te;
-        }
-        T coef[7 * (NC > 0 ? NC : 1)];
-        T xm = 0, ihw = 0;
-        if (!STORED && valid) {
-            const T* c = tab + ((int64_t)b * NT + l) * (2 + 15 * NC);
-            xm = c[0];
-            ihw = c[1];
-#pragma unroll
-            for (int i = 0; i < 7 * NC; ++i) coef[i] = c[2 + i];
-        }
-        for (int i = l; i < 4 * GC; i += NT) grid[i] = (T)0;
-        __syncthreads();
         const int tb = B.tb, te = B.te;
-        // prologue: halo slots tb-3..tb-1 straight into the grid, tb..tb+H-1 into the stage
-        T hreg[H];
-        int known = 0, pending = 0;
-        if (hl.idx >= 0) {
-            if (hl.prod >= 0) {
-                const int smax = min(tb + H - 1, hl.pte);
-                if (smax >= hl.ptb) wait_progress(progress, hl.prod, smax - hl.ptb + 1, known, flags);
+        for (int i = l; i < 4 * GC; i += NT + WAVE) grid[i] = (T)0;
+        if (l >= NT) {
+            // ---------------- halo wave
+            const int hlane = l - NT;
+            Halo hin;
+            int kk = 0, j = 0;
+            if (xch_halo_role(0, hlane, BV, BW, &kk, &j)) {
+                hin.role = true;
+                hin.cell = kk == 0 ? (hlane + 1) * GW : kk == 1 ? hlane - BW + 1 : 0;
+                const int prod = kk == 0 ? B.pred[0] : kk == 1 ? B.pred[1] : B.pred[2];
+                if (prod >= 0) {
+                    const BlockDev& P = blocks[prod];
+                    hin.ptb = P.tb;
+                    hin.pte = P.te;
+                    hin.ptlo = P.tlo;
+                    hin.pxoff = P.xoff;
+                    hin.j = j;
+                }
             }
-            for (int s = tb - 3; s <= tb + H - 1; ++s) {
-                const bool ld = hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                const T val = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
-                if (s < tb) grid[(s & 3) * GC + hl.cell] = val;
-                else stage[(s & (H - 1)) * NH + hl.idx] = val;
-            }
-        }
-        // operands of two batches in flight: ping-pong buffers A and B (no copies,
-        // so nothing loaded during a batch is touched before its final wait)
-        constexpr int NL = STORED ? H * 7 : 1;
-        T rA[H], rB[H];
-        double LA[NL], LB[NL];
-        auto prefetch = [&](const int T0, T (&rx)[H], double (&Lx)[NL]) {
+            const bool out = hlane < NX;
+            int ovl = 0, owl = 0;
+            if (out) xch_out_lane(0, hlane, BV, BW, &ovl, &owl);
+            const int ocell = (owl + 1) * GW + (ovl + 1);
+            __syncthreads();
+            XEnt<T> hx[D];
+            if (hin.role) {
+                for (int s = tb - 3; s < tb; ++s) {
+                    XEnt<T> e;
+                    halo_issue(hin, xch, NX, s, e);
+                    grid[(s & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, s, e, tag, flags);
+                }
 #pragma unroll
-            for (int q = 0; q < H; ++q) {
-                const int t = T0 + q;
-                rx[q] = (T)0;
-                if (valid && t <= te) {
-                    rx[q] = r[rp + (int64_t)NT * t];
+                for (int q = 0; q < D; ++q) halo_issue(hin, xch, NX, tb + q, hx[q]);
+            }
+            __syncthreads();
+            for (int T0 = tb; T0 <= te; T0 += D) {
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    const int t = T0 + q;
+                    if (t > te) break;
+                    // outgoing values of hyperplane t-1 (published by the last barrier)
+                    if (out && t > tb)
+                        x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, t - 1, hlane), grid[((t - 1) & 3) * GC + ocell], tag);
+                    if (hin.role) {
+                        grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx[q], tag, flags);
+                        halo_issue(hin, xch, NX, t + D, hx[q]);
+                    }
+                    lds_barrier();
+                }
+            }
+            if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, te, hlane), grid[(te & 3) * GC + ocell], tag);
+        } else {
+            // ---------------- compute waves
+            const int vl = l % BV, wl = l / BV;
+            const int cell = (wl + 1) * GW + (vl + 1);
+            const LaneDev& Ln = lanes[(int64_t)b * NT + l];
+            const bool valid = Ln.v != 0;
+            const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
+            const int64_t rp = Ln.rp[R_SELF];
+            T coef[7 * (NC > 0 ? NC : 1)];
+            T xm = 0, ihw = 0;
+            if (!STORED && valid) {
+                const T* c = tab + ((int64_t)b * NT + l) * (2 + 15 * NC);
+                xm = c[0];
+                ihw = c[1];
+#pragma unroll
+                for (int i = 0; i < 7 * NC; ++i) coef[i] = c[2 + i];
+            }
+            // Operands of two batches of U hyperplanes in flight, in ping-pong buffers:
+            // a batch issues the next batch's loads, then runs its U hyperplanes.  Every
+            // load and store is issued unconditionally (hyperplanes clamped to the block
+            // window; unused lanes address the zero region), so the number of memory
+            // operations between a load and its use is the same on every path and the
+            // wait before a use covers that load only.
+            constexpr int NL = STORED ? 7 * U : 1;
+            T rA[U], rB[U];
+            double LA[NL], LB[NL];
+            auto prefetch = [&](const int T0, T (&rx)[U], double (&Lx)[NL]) {
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int64_t i = rp + (int64_t)NT * min(T0 + q, te);
+                    rx[q] = r[i];
                     if (STORED)
 #pragma unroll
-                        for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = Lf[(int64_t)s * S + rp + (int64_t)NT * t];
+                        for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = Lf[(int64_t)s * S + i];
                 }
-            }
-        };
-        prefetch(tb, rA, LA);
-        __syncthreads();
-        auto batch = [&](const int T0, T (&rcur)[H], double (&Lcur)[NL], T (&rnxt)[H], double (&Lnxt)[NL]) {
-            if (hl.idx >= 0) {
-                // stage the halo slots of this batch (loaded during the previous one)
-                if (T0 > tb) {
+            };
+            auto batch = [&](const int T0, T (&rcur)[U], double (&Lcur)[NL], T (&rnxt)[U], double (&Lnxt)[NL]) {
+                prefetch(T0 + U, rnxt, Lnxt);
 #pragma unroll
-                    for (int q = 0; q < H; ++q) stage[((T0 + q) & (H - 1)) * NH + hl.idx] = hreg[q];
-                }
-                // load the next batch's halo slots T0+H .. T0+2H-1
-                const bool more = T0 + H <= te;
-                if (hl.prod >= 0 && more) {
-                    known = max(known, pending);
-                    const int smax = min(T0 + 2 * H - 1, hl.pte);
-                    if (smax >= hl.ptb) wait_progress(progress, hl.prod, smax - hl.ptb + 1, known, flags);
-                }
+                for (int q = 0; q < U; ++q) {
+                    const int t = T0 + q;
+                    if (t > te) break;
+                    const int x = t - 2 * v - wrow;
+                    T val = (T)0;
+                    if (valid && x >= 1 && x <= n - 1 - v) {
+                        const T* g1 = grid + ((t - 1) & 3) * GC;
+                        const T* g2 = grid + ((t - 2) & 3) * GC;
+                        const T* g3 = grid + ((t - 3) & 3) * GC;
+                        // neighbours p + d: w (own, t-1), s (v-1, t-2), se (v-1, t-1), bnw (w-1, t-2),
+                        // bn (w-1, t-1), bc (v-1 w-1, t-3), be (v-1 w-1, t-2)
+                        const T nb[7] = {g1[cell], g2[cell - 1], g1[cell - 1], g2[cell - GW],
+                                         g1[cell - GW], g3[cell - GW - 1], g2[cell - GW - 1]};
+                        T acc = rcur[q];
+                        if (STORED) {
 #pragma unroll
-                for (int q = 0; q < H; ++q) {
-                    const int s = T0 + H + q;
-                    const bool ld = more && hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
-                }
-                if (hl.prod >= 0 && more) pending = ld_dev(&progress[hl.prod]);
-            }
-            prefetch(T0 + H, rnxt, Lnxt);
-            lds_barrier();
-            // the H hyperplanes of this batch: LDS traffic only
-            T wout[H];
-            unsigned act = 0;
+                            for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 7 + ORD[jj]] * nb[ORD[jj]];
+                        } else {
+                            const T eta = ((T)x - xm) * ihw;
+                            T Lv[7];
 #pragma unroll
-            for (int q = 0; q < H; ++q) {
-                const int t = T0 + q;
-                wout[q] = (T)0;
-                if (t > te) break;
-                if (hl.idx >= 0) grid[(t & 3) * GC + hl.cell] = stage[(t & (H - 1)) * NH + hl.idx];
-                const int x = t - 2 * v - wrow;
-                T val = (T)0;
-                if (valid && x >= 1 && x <= n - 1 - v) {
-                    const T* g1 = grid + ((t - 1) & 3) * GC;
-                    const T* g2 = grid + ((t - 2) & 3) * GC;
-                    const T* g3 = grid + ((t - 3) & 3) * GC;
-                    // neighbours p + d: w (own, t-1), s (v-1, t-2), se (v-1, t-1), bnw (w-1, t-2),
-                    // bn (w-1, t-1), bc (v-1 w-1, t-3), be (v-1 w-1, t-2)
-                    const T nb[7] = {g1[cell], g2[cell - 1], g1[cell - 1], g2[cell - GW],
-                                     g1[cell - GW], g3[cell - GW - 1], g2[cell - GW - 1]};
-                    T acc = rcur[q];
-                    if (STORED) {
+                            for (int s = 0; s < 7; ++s) Lv[s] = horner<NC>(coef + s * NC, eta);
 #pragma unroll
-                        for (int j = 0; j < 7; ++j) acc -= (T)Lcur[q * 7 + ORD[j]] * nb[ORD[j]];
-                    } else {
-                        const T eta = ((T)x - xm) * ihw;
-                        T Lv[7];
-#pragma unroll
-                        for (int s = 0; s < 7; ++s) Lv[s] = horner<NC>(coef + s * NC, eta);
-#pragma unroll
-                        for (int j = 0; j < 7; ++j) acc -= Lv[ORD[j]] * nb[ORD[j]];
+                            for (int jj = 0; jj < 7; ++jj) acc -= Lv[ORD[jj]] * nb[ORD[jj]];
+                        }
+                        val = acc;
                     }
-                    val = acc;
-                    wout[q] = val;
-                    act |= 1u << q;
+                    // inactive points store 0 into a slot that stays 0 (own padding or the zero region)
+                    w[rp + (int64_t)NT * t] = val;
+                    grid[(t & 3) * GC + cell] = val;
+                    lds_barrier();
                 }
-                grid[(t & 3) * GC + cell] = val;
-                lds_barrier();
-            }
-            // write the batch's results with device-coherent stores
-#pragma unroll
-            for (int q = 0; q < H; ++q)
-                if (act & (1u << q)) st_dev(&w[rp + (int64_t)NT * (T0 + q)], wout[q]);
-            // publish progress: every wave's w stores of this batch have completed
-            wait_stores();
+            };
             __syncthreads();
-            if (l == 0) st_dev(&progress[b], (int32_t)(min(T0 + H - 1, te) - tb + 1));
-        };
-        for (int T0 = tb; T0 <= te; T0 += 2 * H) {
-            batch(T0, rA, LA, rB, LB);
-            if (T0 + H > te) break;
-            batch(T0 + H, rB, LB, rA, LA);
+            prefetch(tb, rA, LA);
+            __syncthreads();
+            for (int T0 = tb; T0 <= te; T0 += 2 * U) {
+                batch(T0, rA, LA, rB, LB);
+                if (T0 + U > te) break;
+                batch(T0 + U, rB, LB, rA, LA);
+            }
         }
         __syncthreads();
     }
@@ -280,24 +325,22 @@ __global__ void __launch_bounds__(BV* BW) k_fwd_flow(const TetDev* __restrict__ 
 
 // ----------------------------------------------------------------- backward
 
-template <typename T, bool STORED, int H, int NC, int BV, int BW>
-__global__ void __launch_bounds__(BV* BW) k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                                     const LaneDev* __restrict__ lanes, int nblocks, int64_t S,
-                                                     const double* __restrict__ Lb, const T* __restrict__ tab,
-                                                     T* __restrict__ w, double* __restrict__ xs,
-                                                     const int32_t* __restrict__ order, int32_t* __restrict__ progress,
-                                                     int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
+__global__ void __launch_bounds__(BV* BW + WAVE)
+    k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
+               int nblocks, int64_t S, const double* __restrict__ Lb, const T* __restrict__ tab,
+               const T* __restrict__ w, double* __restrict__ xs, const int32_t* __restrict__ order,
+               uint64_t* __restrict__ xch, int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
     constexpr int NT = BV * BW;
     constexpr int GW = BV + 1;
     constexpr int GC = (BV + 1) * (BW + 1);
-    constexpr int NH = BV + BW + 1;
-    static_assert((H & (H - 1)) == 0, "H must be a power of two");
+    constexpr int NX = BV + BW;
+    constexpr int XW = XEnt<T>::W;
+    static_assert(NT % WAVE == 0 && NX + 1 <= WAVE, "block shape");
     __shared__ T grid[4 * GC];
-    __shared__ T stage[H * NH];
     __shared__ int s_ticket;
     const int l = threadIdx.x;
-    const int vl = l % BV, wl = l / BV;
-    const int cell = wl * GW + vl;  // halo at column BV and row BW
+    const uint32_t tag = (uint32_t)ticket[2];
     for (;;) {
         if (l == 0) s_ticket = atomicAdd(&ticket[1], 1);
         __syncthreads();
@@ -306,225 +349,212 @@ __global__ void __launch_bounds__(BV* BW) k_bwd_flow(const TetDev* __restrict__ 
         if (k >= nblocks) return;
         const int b = order[k];
         const BlockDev B = blocks[b];
-        const LaneDev& Ln = lanes[(int64_t)b * NT + l];
-        const bool valid = Ln.v != 0;
-        const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
-        const int64_t rp = Ln.rp[R_SELF];
-        // halo roles: right column (v = V0+BV), top row (w = W0+BW), corner
-        Halo hl;
-        if (l < BW) {
-            hl.idx = l;
-            hl.cell = l * GW + BV;
-            hl.rp = lanes[(int64_t)b * NT + l * BV + (BV - 1)].rp[R_VP];
-            hl.prod = B.succ[0];
-        } else if (l < BW + BV) {
-            hl.idx = l;
-            hl.cell = BW * GW + (l - BW);
-            hl.rp = lanes[(int64_t)b * NT + (BW - 1) * BV + (l - BW)].rp[R_WP];
-            hl.prod = B.succ[1];
-        } else if (l == BW + BV) {
-            hl.idx = l;
-            hl.cell = BW * GW + BV;
-            hl.rp = lanes[(int64_t)b * NT + NT - 1].rp[R_VPWP];
-            hl.prod = B.succ[2];
-        }
-        if (hl.prod >= 0) {
-            hl.ptb = blocks[hl.prod].tb;
-            hl.pte = blocks[hl.prod].te;
-        }
-        T coef[8 * (NC > 0 ? NC : 1)];
-        T xm = 0, ihw = 0;
-        if (!STORED && valid) {
-            const T* c = tab + ((int64_t)b * NT + l) * (2 + 15 * NC);
-            xm = c[0];
-            ihw = c[1];
-#pragma unroll
-            for (int i = 0; i < 8 * NC; ++i) coef[i] = c[2 + 7 * NC + i];
-        }
-        for (int i = l; i < 4 * GC; i += NT) grid[i] = (T)0;
-        __syncthreads();
         const int tb = B.tb, te = B.te;
-        // prologue: halo slots te+3..te+1 into the grid, te..te-H+1 into the stage
-        T hreg[H];
-        int known = 0, pending = 0;
-        if (hl.idx >= 0) {
-            if (hl.prod >= 0) {
-                const int smin = max(te - H + 1, hl.ptb);
-                if (smin <= hl.pte) wait_progress(progress, hl.prod, hl.pte - smin + 1, known, flags);
+        for (int i = l; i < 4 * GC; i += NT + WAVE) grid[i] = (T)0;
+        if (l >= NT) {
+            // ---------------- halo wave (halo at column BV and row BW of the grid)
+            const int hlane = l - NT;
+            Halo hin;
+            int kk = 0, j = 0;
+            if (xch_halo_role(1, hlane, BV, BW, &kk, &j)) {
+                hin.role = true;
+                hin.cell = kk == 0 ? hlane * GW + BV : kk == 1 ? BW * GW + (hlane - BW) : BW * GW + BV;
+                const int prod = kk == 0 ? B.succ[0] : kk == 1 ? B.succ[1] : B.succ[2];
+                if (prod >= 0) {
+                    const BlockDev& P = blocks[prod];
+                    hin.ptb = P.tb;
+                    hin.pte = P.te;
+                    hin.ptlo = P.tlo;
+                    hin.pxoff = P.xoff;
+                    hin.j = j;
+                }
             }
-            for (int s = te + 3; s >= te - H + 1; --s) {
-                const bool ld = hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                const T val = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
-                if (s > te) grid[(s & 3) * GC + hl.cell] = val;
-                else stage[(s & (H - 1)) * NH + hl.idx] = val;
-            }
-        }
-        constexpr int NL = STORED ? H * 8 : 1;
-        T wA[H], wB[H];
-        double xA[H], xB[H];
-        double LA[NL], LB[NL];
-        auto prefetch = [&](const int T0, T (&wx)[H], double (&xx)[H], double (&Lx)[NL]) {
+            const bool out = hlane < NX;
+            int ovl = 0, owl = 0;
+            if (out) xch_out_lane(1, hlane, BV, BW, &ovl, &owl);
+            const int ocell = owl * GW + ovl;
+            __syncthreads();
+            XEnt<T> hx[D];
+            if (hin.role) {
+                for (int s = te + 3; s > te; --s) {
+                    XEnt<T> e;
+                    halo_issue(hin, xch, NX, s, e);
+                    grid[(s & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, s, e, tag, flags);
+                }
 #pragma unroll
-            for (int q = 0; q < H; ++q) {
-                const int t = T0 - q;
-                wx[q] = (T)0;
-                xx[q] = 0.0;
-                if (valid && t >= tb) {
-                    wx[q] = w[rp + (int64_t)NT * t];
-                    xx[q] = xs[rp + (int64_t)NT * t];
+                for (int q = 0; q < D; ++q) halo_issue(hin, xch, NX, te - q, hx[q]);
+            }
+            __syncthreads();
+            for (int T0 = te; T0 >= tb; T0 -= D) {
+#pragma unroll
+                for (int q = 0; q < D; ++q) {
+                    const int t = T0 - q;
+                    if (t < tb) break;
+                    if (out && t < te)
+                        x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, t + 1, hlane), grid[((t + 1) & 3) * GC + ocell], tag);
+                    if (hin.role) {
+                        grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx[q], tag, flags);
+                        halo_issue(hin, xch, NX, t - D, hx[q]);
+                    }
+                    lds_barrier();
+                }
+            }
+            if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, tb, hlane), grid[(tb & 3) * GC + ocell], tag);
+        } else {
+            // ---------------- compute waves
+            const int vl = l % BV, wl = l / BV;
+            const int cell = wl * GW + vl;
+            const LaneDev& Ln = lanes[(int64_t)b * NT + l];
+            const bool valid = Ln.v != 0;
+            const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
+            const int64_t rp = Ln.rp[R_SELF];
+            T coef[8 * (NC > 0 ? NC : 1)];
+            T xm = 0, ihw = 0;
+            if (!STORED && valid) {
+                const T* c = tab + ((int64_t)b * NT + l) * (2 + 15 * NC);
+                xm = c[0];
+                ihw = c[1];
+#pragma unroll
+                for (int i = 0; i < 8 * NC; ++i) coef[i] = c[2 + 7 * NC + i];
+            }
+            // ping-pong operand buffers and unconditional memory operations, as in the
+            // forward sweep
+            constexpr int NL = STORED ? 8 * U : 1;
+            T wA[U], wB[U];
+            double xA[U], xB[U];
+            double LA[NL], LB[NL];
+            auto prefetch = [&](const int T0, T (&wx)[U], double (&xx)[U], double (&Lx)[NL]) {
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    const int64_t i = rp + (int64_t)NT * max(T0 - q, tb);
+                    wx[q] = w[i];
+                    xx[q] = xs[i];
                     if (STORED)
 #pragma unroll
-                        for (int s = 0; s < 8; ++s) Lx[q * 8 + s] = Lb[(int64_t)s * S + rp + (int64_t)NT * t];
+                        for (int s = 0; s < 8; ++s) Lx[q * 8 + s] = Lb[(int64_t)s * S + i];
                 }
-            }
-        };
-        prefetch(te, wA, xA, LA);
-        __syncthreads();
-        auto batch = [&](const int T0, T (&wcur)[H], double (&xcur)[H], double (&Lcur)[NL], T (&wnxt)[H],
-                         double (&xnxt)[H], double (&Lnxt)[NL]) {
-            if (hl.idx >= 0) {
-                if (T0 < te) {
+            };
+            auto batch = [&](const int T0, T (&wcur)[U], double (&xcur)[U], double (&Lcur)[NL], T (&wnxt)[U],
+                             double (&xnxt)[U], double (&Lnxt)[NL]) {
+                prefetch(T0 - U, wnxt, xnxt, Lnxt);
 #pragma unroll
-                    for (int q = 0; q < H; ++q) stage[((T0 - q) & (H - 1)) * NH + hl.idx] = hreg[q];
-                }
-                const bool more = T0 - H >= tb;
-                if (hl.prod >= 0 && more) {
-                    known = max(known, pending);
-                    const int smin = max(T0 - 2 * H + 1, hl.ptb);
-                    if (smin <= hl.pte) wait_progress(progress, hl.prod, hl.pte - smin + 1, known, flags);
-                }
+                for (int q = 0; q < U; ++q) {
+                    const int t = T0 - q;
+                    if (t < tb) break;
+                    const int x = t - 2 * v - wrow;
+                    T val = (T)0;
+                    if (valid && x >= 1 && x <= n - 1 - v) {
+                        const T* g1 = grid + ((t + 1) & 3) * GC;
+                        const T* g2 = grid + ((t + 2) & 3) * GC;
+                        const T* g3 = grid + ((t + 3) & 3) * GC;
+                        // upper neighbours p - d: e (own, t+1), n (v+1, t+2), nw (v+1, t+1),
+                        // tse (w+1, t+2), ts (w+1, t+1), tc (v+1 w+1, t+3), tw (v+1 w+1, t+2)
+                        const T nb[7] = {g1[cell], g2[cell + 1], g1[cell + 1], g2[cell + GW],
+                                         g1[cell + GW], g3[cell + GW + 1], g2[cell + GW + 1]};
+                        T acc;
+                        if (STORED) {
+                            acc = wcur[q] * (T)Lcur[q * 8];
 #pragma unroll
-                for (int q = 0; q < H; ++q) {
-                    const int s = T0 - H - q;
-                    const bool ld = more && hl.prod >= 0 && s >= hl.ptb && s <= hl.pte;
-                    hreg[q] = ld ? ld_dev(&w[hl.rp + (int64_t)NT * s]) : (T)0;
-                }
-                if (hl.prod >= 0 && more) pending = ld_dev(&progress[hl.prod]);
-            }
-            prefetch(T0 - H, wnxt, xnxt, Lnxt);
-            lds_barrier();
-            T wout[H];
-            double xout[H];
-            unsigned act = 0;
+                            for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 8 + 1 + ORD[jj]] * nb[ORD[jj]];
+                        } else {
+                            const T eta = ((T)x - xm) * ihw;
+                            T Uv[7];
 #pragma unroll
-            for (int q = 0; q < H; ++q) {
-                const int t = T0 - q;
-                wout[q] = (T)0;
-                xout[q] = 0.0;
-                if (t < tb) break;
-                if (hl.idx >= 0) grid[(t & 3) * GC + hl.cell] = stage[(t & (H - 1)) * NH + hl.idx];
-                const int x = t - 2 * v - wrow;
-                T val = (T)0;
-                if (valid && x >= 1 && x <= n - 1 - v) {
-                    const T* g1 = grid + ((t + 1) & 3) * GC;
-                    const T* g2 = grid + ((t + 2) & 3) * GC;
-                    const T* g3 = grid + ((t + 3) & 3) * GC;
-                    // upper neighbours p - d: e (own, t+1), n (v+1, t+2), nw (v+1, t+1),
-                    // tse (w+1, t+2), ts (w+1, t+1), tc (v+1 w+1, t+3), tw (v+1 w+1, t+2)
-                    const T nb[7] = {g1[cell], g2[cell + 1], g1[cell + 1], g2[cell + GW],
-                                     g1[cell + GW], g3[cell + GW + 1], g2[cell + GW + 1]};
-                    T acc;
-                    if (STORED) {
-                        acc = wcur[q] * (T)Lcur[q * 8];
+                            for (int s = 0; s < 7; ++s) Uv[s] = horner<NC>(coef + (1 + s) * NC, eta);
+                            acc = wcur[q] * horner<NC>(coef, eta);
 #pragma unroll
-                        for (int j = 0; j < 7; ++j) acc -= (T)Lcur[q * 8 + 1 + ORD[j]] * nb[ORD[j]];
-                    } else {
-                        const T eta = ((T)x - xm) * ihw;
-                        T Uv[7];
-#pragma unroll
-                        for (int s = 0; s < 7; ++s) Uv[s] = horner<NC>(coef + (1 + s) * NC, eta);
-                        acc = wcur[q] * horner<NC>(coef, eta);
-#pragma unroll
-                        for (int j = 0; j < 7; ++j) acc -= Uv[ORD[j]] * nb[ORD[j]];
+                            for (int jj = 0; jj < 7; ++jj) acc -= Uv[ORD[jj]] * nb[ORD[jj]];
+                        }
+                        val = acc;
                     }
-                    val = acc;
-                    wout[q] = val;
-                    xout[q] = xcur[q] + (double)val;
-                    act |= 1u << q;
+                    // inactive points write their (zero) x slot back unchanged
+                    xs[rp + (int64_t)NT * t] = xcur[q] + (double)val;
+                    grid[(t & 3) * GC + cell] = val;
+                    lds_barrier();
                 }
-                grid[(t & 3) * GC + cell] = val;
-                lds_barrier();
-            }
-#pragma unroll
-            for (int q = 0; q < H; ++q)
-                if (act & (1u << q)) {
-                    const int64_t idx = rp + (int64_t)NT * (T0 - q);
-                    st_dev(&w[idx], wout[q]);
-                    xs[idx] = xout[q];
-                }
-            wait_stores();
+            };
             __syncthreads();
-            if (l == 0) st_dev(&progress[b], (int32_t)(te - max(T0 - H + 1, tb) + 1));
-        };
-        for (int T0 = te; T0 >= tb; T0 -= 2 * H) {
-            batch(T0, wA, xA, LA, wB, xB, LB);
-            if (T0 - H < tb) break;
-            batch(T0 - H, wB, xB, LB, wA, xA, LA);
+            prefetch(te, wA, xA, LA);
+            __syncthreads();
+            for (int T0 = te; T0 >= tb; T0 -= 2 * U) {
+                batch(T0, wA, xA, LA, wB, xB, LB);
+                if (T0 - U < tb) break;
+                batch(T0 - U, wB, xB, LB, wA, xA, LA);
+            }
         }
         __syncthreads();
     }
 }
 
-__global__ void k_flow_reset(int32_t* __restrict__ progress, int n, int32_t* __restrict__ ticket) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) progress[i] = 0;
-    if (i < 2) ticket[i] = 0;
+// Before every dataflow sweep: reset the work counters and advance the tag.
+__global__ void k_flow_reset(int32_t* __restrict__ ticket) {
+    if (threadIdx.x == 0) {
+        ticket[0] = 0;
+        ticket[1] = 0;
+        uint32_t e = (uint32_t)ticket[2] + 1u;
+        if (e == 0) e = 1;  // tag 0 is the cleared buffer
+        ticket[2] = (int32_t)e;
+    }
 }
 
 // ------------------------------------------------------------------ launchers
 
 namespace {
 
-constexpr int H_F64 = 4;   // stored factors: 8 operands per step are prefetched
-constexpr int H_S64 = 8;   // FP64 surrogate
-constexpr int H_F32 = 8;   // FP32 surrogate
+// Batch depth U (operands of the next U hyperplanes are loaded while the
+// current U run) and halo distance D.  Both batches of loads must fit the
+// 63-entry vector memory counter: stored factors load 8 (forward) or 10
+// (backward) values per hyperplane.
+constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 4;  // stored factors
+constexpr int U_S64 = 4, D_S64 = 4;              // FP64 surrogate
+constexpr int U_F32 = 8, D_F32 = 4;              // FP32 surrogate
 
 template <int BV, int BW>
 struct Shape {
     static constexpr int NT = BV * BW;
-    static const void* fwd_stored_ptr() { return (const void*)k_fwd_flow<double, true, H_F64, 0, BV, BW>; }
-    static const void* bwd_stored_ptr() { return (const void*)k_bwd_flow<double, true, H_F64, 0, BV, BW>; }
+    static const void* fwd_stored_ptr() { return (const void*)k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW>; }
+    static const void* bwd_stored_ptr() { return (const void*)k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW>; }
     template <int NC>
     static const void* fwd_ptr(int variant) {
-        if (variant == 1) return (const void*)k_fwd_flow<double, false, H_S64, NC, BV, BW>;
-        return (const void*)k_fwd_flow<float, false, H_F32, NC, BV, BW>;
+        if (variant == 1) return (const void*)k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW>;
+        return (const void*)k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW>;
     }
     template <int NC>
     static const void* bwd_ptr(int variant) {
-        if (variant == 1) return (const void*)k_bwd_flow<double, false, H_S64, NC, BV, BW>;
-        return (const void*)k_bwd_flow<float, false, H_F32, NC, BV, BW>;
+        if (variant == 1) return (const void*)k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW>;
+        return (const void*)k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW>;
     }
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
-        k_fwd_flow<double, true, H_F64, 0, BV, BW><<<f.grid, NT, 0, st>>>(
+        k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, (const double*)c.r, (double*)c.w, f.order_fwd,
-            f.progress, f.ticket, f.flags);
+            f.xch, f.ticket, f.flags);
     }
     static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
-        k_bwd_flow<double, true, H_F64, 0, BV, BW><<<f.grid, NT, 0, st>>>(
-            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, (double*)c.w, x, f.order_bwd, f.progress,
+        k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, (const double*)c.w, x, f.order_bwd, f.xch,
             f.ticket, f.flags);
     }
     template <int NC>
     static void fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, H_S64, NC, BV, BW><<<f.grid, NT, 0, st>>>(
+            k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.r, (double*)c.w,
-                f.order_fwd, f.progress, f.ticket, f.flags);
+                f.order_fwd, f.xch, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, H_F32, NC, BV, BW><<<f.grid, NT, 0, st>>>(
+            k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.r, (float*)c.w,
-                f.order_fwd, f.progress, f.ticket, f.flags);
+                f.order_fwd, f.xch, f.ticket, f.flags);
     }
     template <int NC>
     static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
         if (variant == 1)
-            k_bwd_flow<double, false, H_S64, NC, BV, BW><<<f.grid, NT, 0, st>>>(
-                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (double*)c.w, x, f.order_bwd,
-                f.progress, f.ticket, f.flags);
+            k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.w, x, f.order_bwd,
+                f.xch, f.ticket, f.flags);
         else
-            k_bwd_flow<float, false, H_F32, NC, BV, BW><<<f.grid, NT, 0, st>>>(
-                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (float*)c.w, x, f.order_bwd,
-                f.progress, f.ticket, f.flags);
+            k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.w, x, f.order_bwd,
+                f.xch, f.ticket, f.flags);
     }
 };
 
@@ -553,8 +583,9 @@ int resident(int variant, int NC) {
 #undef ILU_PTRS
     }
     int a = 0, b = 0;
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, BV * BW, 0);
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, BV * BW, 0);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, BV * BW + WAVE, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, BV * BW + WAVE, 0) != hipSuccess)
+        return 1;
     return a < b ? a : b;
 }
 
@@ -587,10 +618,10 @@ bool flow_shape_supported(int bv, int bw) {
 }
 
 int flow_max_resident(int variant, int NC, int bv, int bw) {
-    int dev = 0;
-    hipGetDevice(&dev);
-    int cus = 0;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 1;
     int per_cu = 1;
     if (bv == 8 && bw == 8) per_cu = resident<8, 8>(variant, NC);
     else if (bv == 16 && bw == 16) per_cu = resident<16, 16>(variant, NC);
@@ -599,10 +630,7 @@ int flow_max_resident(int variant, int NC, int bv, int bw) {
     return per_cu * cus;
 }
 
-void launch_flow_reset(const Ctx& c, const Flow& f, hipStream_t st) {
-    const int n = c.nblocks > 2 ? c.nblocks : 2;
-    k_flow_reset<<<(n + 255) / 256, 256, 0, st>>>(f.progress, c.nblocks, f.ticket);
-}
+void launch_flow_reset(const Flow& f, hipStream_t st) { k_flow_reset<<<1, 64, 0, st>>>(f.ticket); }
 
 void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
     if (c.bv == 8 && c.bw == 8) run_fwd<8, 8>(c, f, variant, st);

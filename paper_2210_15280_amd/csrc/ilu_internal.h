@@ -59,6 +59,7 @@ struct BlockDev {
     int32_t succ[3];     // backward-sweep predecessors: (V+1,W), (V,W+1), (V+1,W+1)
     int32_t pad_;
     int64_t base;        // stream index of (tlo, lane 0)
+    int64_t xoff;        // first entry of the block's exchange window: len x (BV + BW) entries
 };
 
 // Lane-group decoding for the point-parallel kernels: workgroup x-index g
@@ -68,6 +69,32 @@ struct LaneDev {
     int64_t rp[7];       // row pointers, RowSlot order; zero-region pointer if the row is outside
     int32_t v, w;        // row coordinates; v = 0 marks an unused lane
 };
+
+// Dataflow exchange buffer: word index of entry j (0 <= j < nx = BV + BW) at
+// hyperplane t of the block whose window starts at entry xoff and whose
+// storage time origin is tlo; wds 64-bit words per entry.  Used by the sweep
+// kernels and by the host-side layout replay alike.
+__host__ __device__ inline int64_t xch_word(int64_t xoff, int tlo, int nx, int wds, int t, int j) {
+    return (xoff + (int64_t)(t - tlo) * nx + j) * wds;
+}
+
+// Producer lane (vl, wl) of outgoing exchange entry j (0 <= j < BV + BW) in
+// sweep direction dir (0 = forward, 1 = backward): j < BW is the column entry
+// of row wl = j on the last column in sweep direction, j >= BW the row entry
+// of column vl = j - BW on the last row.  The corner lane appears in both.
+__host__ __device__ inline void xch_out_lane(int dir, int j, int bv, int bw, int* vl, int* wl) {
+    if (j < bw) { *vl = dir == 0 ? bv - 1 : 0; *wl = j; }
+    else { *vl = j - bw; *wl = dir == 0 ? bw - 1 : 0; }
+}
+// Incoming halo role of thread l: k = producer slot (0: column neighbour,
+// 1: row neighbour, 2: corner; pred[k] forward, succ[k] backward) and the
+// producer's entry j.  Returns false for threads without a role.
+__host__ __device__ inline bool xch_halo_role(int dir, int l, int bv, int bw, int* k, int* j) {
+    if (l < bw) { *k = 0; *j = l; return true; }
+    if (l < bw + bv) { *k = 1; *j = l; return true; }
+    if (l == bw + bv) { *k = 2; *j = dir == 0 ? bw + bv - 1 : bw; return true; }
+    return false;
+}
 
 // Fitted directions: 0..6 = lower directions of D_l, 7 = centre (fits 1/D).
 constexpr int NFIT = 8;

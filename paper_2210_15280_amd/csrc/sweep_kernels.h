@@ -18,12 +18,12 @@ void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, dou
 struct Flow {
     const int32_t* order_fwd = nullptr;  // block ids in a topological order of the forward sweep
     const int32_t* order_bwd = nullptr;  // ... and of the backward sweep
-    int32_t* progress = nullptr;         // [nblocks] last finished hyperplane + 1 (0 = not started)
-    int32_t* ticket = nullptr;           // [2] work counters
+    uint64_t* xch = nullptr;             // tagged boundary values of every block and hyperplane
+    int32_t* ticket = nullptr;           // [4] work counters (fwd, bwd) and the launch tag
     int32_t* flags = nullptr;            // [4] error flags (flags[2]: wait limit hit)
     int grid = 0;                        // resident workgroups
 };
-void launch_flow_reset(const Ctx& c, const Flow& f, hipStream_t st);
+void launch_flow_reset(const Flow& f, hipStream_t st);
 void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st);
 void launch_bwd_flow(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st);
 int flow_max_resident(int variant, int NC, int bv, int bw);
