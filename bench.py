@@ -5,10 +5,17 @@ workload: FP64 residual, forward substitution, backward substitution with the
 update (every part of the hot path).  The timed region is one ilu_smooth call
 of K sweeps with x and b already resident in HBM (it includes the call's
 layout conversion of x and b).  Prints one JSON line.
+
+Default workload: one jittered macro-tetrahedron at refinement level 9
+(22,108,415 interior DOFs), coefficient exp(0.5 sin(4 pi x) cos(4 pi y)),
+surrogate degree 6: FP32 surrogate sweeps with FP64 residual and update,
+beside FP64 stored-factor sweeps and FP64 surrogate sweeps.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -18,8 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-FP64_PEAK_TF = 78.6        # vector FP64
-FP32_PEAK_TF = 157.3       # vector FP32
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
 
 # Algorithmic bytes per interior DOF and kernel (each array touched once per
 # kernel; stencil weights: 8 unique FP64 values per point, the other 7 are the
@@ -40,20 +47,48 @@ def kernel_flops(variant: str, dg: int):
     res = 30                                  # 15 multiply-adds
     if variant == "stored_f64":
         return {"residual": res, "forward": 14, "backward": 16}
+    # Horner: dg multiply-adds per direction (7 forward, 8 backward) plus the sweep
     return {"residual": res, "forward": 14 + 14 * dg, "backward": 16 + 16 * dg}
 
 
 VARIANTS = {"stored_f64": 0, "surr_f64": 1, "surr_f32": 2}
+KERNEL_NAMES = {"residual": "k_residual", "forward": "k_fwd_flow", "backward": "k_bwd_flow"}
+
+
+def source_hash() -> str:
+    """SHA-256 over the library's kernel and host sources (sorted by name)."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2210_15280_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, variant: str, kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current sources; None otherwise."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_hash():
+        return None
+    e = t.get("entries", {}).get("%s/%s/%s" % (workload, variant, kernel))
+    if not e:
+        return None
+    return e["fetch_bytes"] + e["write_bytes"]
 
 
 def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
+    import numpy as np
     kw = {} if variant == "stored_f64" else dict(degree=wl.degree, stride=wl.stride)
     kw["tile"] = tile
     t0 = time.perf_counter()
     sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    import numpy as np
     b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
     x = torch.zeros_like(b)
     if warmup:
@@ -68,7 +103,8 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     loop_ms = sm.timing()[0]
-    # relative residual reached, then per-kernel timing in a separate run
+    # relative residual reached, then per-kernel timing (HIP events on the
+    # library's stream around every kernel) in a separate run
     rel, _ = sm.smooth(x, b, 0, want_relres=True)
     sm.set_kernel_timing(True)
     x2 = torch.zeros_like(b)
@@ -78,12 +114,12 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     n = sm.n_total
     out = dict(variant=variant, n_dof=n, setup_s=setup_s, ms_per_step=ms / steps,
                loop_ms_per_step=loop_ms / steps, value=n * steps / (ms * 1e-3), relres_after=rel,
-               kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms))
+               kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms), tile=list(sm.tile))
     sm.close()
     return out
 
 
-def roofline(res, variant, dg):
+def roofline(res, variant, dg, workload):
     bpd = kernel_bytes(variant)
     fpd = kernel_flops(variant, dg)
     km = res["kernel_ms"]
@@ -91,18 +127,23 @@ def roofline(res, variant, dg):
     n = res["n_dof"]
     t = km[dom] * 1e-3
     gbs = bpd[dom] * n / t / 1e9
-    out = {"bound": "hbm", "kernel": dom, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
-           "bytes_per_dof": bpd[dom], "flops_per_dof": fpd[dom],
-           "kernel_ms_per_launch": round(km[dom], 5)}
-    return out
+    return {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+            "traffic": measured_traffic(workload, variant, KERNEL_NAMES[dom]),
+            "algorithmic_bytes_per_launch": bpd[dom] * n, "bytes_per_dof": bpd[dom], "flops_per_dof": fpd[dom],
+            "kernel_ms_per_launch": round(km[dom], 5)}
 
 
-def cpu_baseline(wl, variant, budget_s=12.0):
-    """The oracle (plain C, one thread) on a bounded sample of the same workload."""
+def cpu_baseline(wl, variant, budget_s=12.0, sample_level=7):
+    """The oracle (plain C, one thread) on a bounded sample of the workload: its
+    first tetrahedron (same geometry, coefficient, surrogate degree and stride)
+    at refinement level min(level, sample_level); sweeps timed, setup not."""
     import numpy as np
     import oracle as O
-    t = wl.tets[0]
+    import workloads as W
+    t0 = wl.tets[0]
+    lvl = min(t0.level, sample_level)
+    t = W.Tet(t0.verts, lvl, t0.coeff_kind, t0.coeff_params, t0.rhs_state)
     P = O.Problem.from_tet(t)
     L, U, D = P.ilu0()
     b = t.rhs()
@@ -116,19 +157,33 @@ def cpu_baseline(wl, variant, budget_s=12.0):
         if variant == "surr_f32":
             Lw32, Di32 = Lw.astype(np.float32), Dinv.astype(np.float32)
             run = lambda k: P.smooth_stencil_f32(Lw32, Di32, b, nsweeps=k)
-            kind = "Alg. 2 stencil sweep, FP32 weights/substitutions, FP64 residual"
+            kind = "stencil sweep with FP32 surrogate weights and substitutions, FP64 residual"
         else:
             run = lambda k: P.smooth_stencil(Lw, Dinv, b, nsweeps=k)
-            kind = "Alg. 2 stencil sweep, FP64"
-    t0 = time.perf_counter()
+            kind = "stencil sweep with FP64 surrogate weights"
+    tt = time.perf_counter()
     run(1)
-    one = max(time.perf_counter() - t0, 1e-4)
+    one = max(time.perf_counter() - tt, 1e-4)
     k = max(1, min(1000, int(budget_s / one)))
-    t0 = time.perf_counter()
+    tt = time.perf_counter()
     run(k)
-    el = time.perf_counter() - t0
+    el = time.perf_counter() - tt
     return {"value": P.N * k / el, "unit": "DOF-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%s: tet 0 of the workload (%d DOFs), %d sweeps, %s, %.1f s" % (wl.name, P.N, k, kind, el)}
+            "sample": "%s tetrahedron 0 at level %d (%d DOFs; workload level %d), %d sweeps, %s, %.1f s" % (
+                wl.name, lvl, P.N, t0.level, k, kind, el)}
+
+
+def copy_calibration(torch, nbytes, reps=3):
+    """A plain streaming copy of known size (reads and writes nbytes each launch),
+    for scaling the HBM byte counters."""
+    src = torch.rand(nbytes // 4, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print("# copy calibration: %d launches, %d bytes read + %d bytes written each" % (reps, nbytes, nbytes),
+          file=sys.stderr, flush=True)
 
 
 def main():
@@ -136,10 +191,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="jit_L7_sin")
+    ap.add_argument("--workload", default="jit_L9_exp")
     ap.add_argument("--variants", default="surr_f32,stored_f64,surr_f64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="auto", help="block shape BVxBW of the sweep schedule, e.g. 16x32")
+    ap.add_argument("--copy-bytes", type=int, default=0, help="also run a streaming copy of this size")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -155,9 +211,11 @@ def main():
     results = {}
     for v in variants:
         results[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
-        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, kernels %s" % (
+        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, tile %s, kernels %s" % (
             v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],
-            json.dumps(results[v]["kernel_ms"])), file=sys.stderr, flush=True)
+            "x".join(map(str, results[v]["tile"])), json.dumps(results[v]["kernel_ms"])), file=sys.stderr, flush=True)
+    if a.copy_bytes:
+        copy_calibration(torch, a.copy_bytes)
     head = variants[0]
     hr = results[head]
     line = {
@@ -171,15 +229,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"surr_f32": "f32 sweeps + f64 residual/update", "surr_f64": "f64",
+        "dtype": {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
                   "stored_f64": "f64"}[head],
         "data": "synthetic (seeded jittered macro-tetrahedra, seeded RHS)",
         "config": {"workload": wl.name, "variant": head, "n_tets": len(wl.tets),
                    "levels": sorted({t.level for t in wl.tets}), "n_dof": hr["n_dof"],
-                   "surrogate_degree": wl.degree, "sample_stride": wl.stride, "parallelism": "single GPU"},
+                   "surrogate_degree": wl.degree, "sample_stride": wl.stride, "tile": hr["tile"],
+                   "parallelism": "single GPU"},
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "loop_ms_per_step", "relres_after", "setup_s",
-                                            "kernel_ms")} for v, r in results.items()},
-        "roofline": roofline(hr, head, wl.degree),
+                                            "kernel_ms", "tile")} for v, r in results.items()},
+        "roofline": roofline(hr, head, wl.degree, wl.name),
     }
     if "stored_f64" in results and head != "stored_f64":
         line["speedup_vs_stored_f64"] = hr["value"] / results["stored_f64"]["value"]

@@ -149,6 +149,10 @@ int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double *L_out, double 
 /* Effective sample stride chosen for tetrahedron `tet` (surrogate variants). */
 int ilu_sample_stride(ilu_handle_t h, int32_t tet, int32_t *stride_out);
 
+/* Block shape (rows in v, rows in w) of the sweep schedule the handle uses:
+ * the one requested in ilu_opts.tile, or the automatic choice. */
+int ilu_tile(ilu_handle_t h, int32_t *bv_out, int32_t *bw_out);
+
 /* Device times (ms) of the last ilu_smooth call, from HIP events on its
  * stream: the whole sweep loop, and per sweep the forward substitution, the
  * backward substitution and the residual (averaged over all sweeps when

@@ -65,6 +65,7 @@ def lib():
         L.ilu_set_surrogate.argtypes = [P, I32, P, P]
         L.ilu_get_surrogate_values.argtypes = [P, I32, P, P, P]
         L.ilu_sample_stride.argtypes = [P, I32, ctypes.POINTER(I32)]
+        L.ilu_tile.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.ilu_last_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.ilu_set_kernel_timing.argtypes = [P, I32]
         L.ilu_check_layout.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, ctypes.POINTER(ilu_opts),
@@ -202,6 +203,13 @@ class Smoother:
         s = ctypes.c_int32()
         _check(self.L.ilu_sample_stride(self.h, tet, ctypes.byref(s)), "ilu_sample_stride")
         return s.value
+
+    @property
+    def tile(self):
+        """Block shape (BV, BW) of the sweep schedule in use."""
+        bv, bw = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L.ilu_tile(self.h, ctypes.byref(bv), ctypes.byref(bw)), "ilu_tile")
+        return bv.value, bw.value
 
     def timing(self):
         """(sweep loop ms, forward ms, backward ms, residual ms) of the last smooth call."""

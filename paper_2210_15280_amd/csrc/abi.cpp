@@ -213,6 +213,7 @@ int build_layout(ilu_handle_t h) {
             }
         T.nblk = (int)h->blocks.size() - T.blk0;
     }
+    S += (int64_t)lpb * TAIL;
     h->S = S;
     h->XE = XE;
     h->nlex = lexoff;
@@ -596,6 +597,23 @@ int64_t check_layout(ilu_handle_t h) {
             }
         }
     }
+    // residual: every load and store address of every lane and hyperplane of
+    // the block range (inactive points and the clamped second point included)
+    for (size_t b = 0; b < h->blocks.size(); ++b) {
+        const BlockDev& B = h->blocks[b];
+        for (int l = 0; l < LANES; ++l) {
+            const LaneDev& L = h->lanes[b * LANES + l];
+            for (int t = B.tb; t <= B.te + 1; ++t) {
+                const int64_t off = (int64_t)LANES * t;
+                if (L.rp[R_SELF] + off < 0 || L.rp[R_SELF] + off >= S) ++bad;
+                for (int s = 0; s < 7; ++s) {
+                    const int64_t ql = L.rp[lrow[s]] + off + (int64_t)LANES * (dx[s] + 2 * dy[s] + 3 * dz[s]);
+                    const int64_t qu = L.rp[urow[s]] + off - (int64_t)LANES * (dx[s] + 2 * dy[s] + 3 * dz[s]);
+                    if (ql < 0 || ql >= S || qu < 0 || qu >= S) ++bad;
+                }
+            }
+        }
+    }
     // dataflow exchange: replay the outgoing-entry stores of every block and
     // hyperplane with the kernels' own index functions, then check that every
     // halo read lands on a word written by the producer lane that owns the
@@ -944,6 +962,13 @@ int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double* L_out, double*
     launch_export_surrogate(h->ctx(), h->variant == ILU_SURR_F32, tet, L_out, Dinv_out, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_tile(ilu_handle_t h, int32_t* bv_out, int32_t* bw_out) {
+    if (!h || !bv_out || !bw_out) return ILU_EINVAL;
+    *bv_out = h->bv;
+    *bw_out = h->bw;
     return ILU_OK;
 }
 

@@ -258,16 +258,18 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
             // Operands of two batches of U hyperplanes in flight, in ping-pong buffers:
             // a batch issues the next batch's loads, then runs its U hyperplanes.  Every
             // load and store is issued unconditionally (hyperplanes clamped to the block
-            // window; unused lanes address the zero region), so the number of memory
-            // operations between a load and its use is the same on every path and the
-            // wait before a use covers that load only.
+            // window; inactive points and unused lanes load from the zero region), so
+            // the number of memory operations between a load and its use is the same on
+            // every path and the wait before a use covers that load only.
             constexpr int NL = STORED ? 7 * U : 1;
             T rA[U], rB[U];
             double LA[NL], LB[NL];
             auto prefetch = [&](const int T0, T (&rx)[U], double (&Lx)[NL]) {
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
-                    const int64_t i = rp + (int64_t)NT * min(T0 + q, te);
+                    // inactive points read the (cache-resident) zero region, not padding
+                    const int t = min(T0 + q, te), xq = t - 2 * v - wrow;
+                    const int64_t i = valid && xq >= 1 && xq <= n - 1 - v ? rp + (int64_t)NT * t : 0;
                     rx[q] = r[i];
                     if (STORED)
 #pragma unroll
@@ -426,7 +428,8 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
             auto prefetch = [&](const int T0, T (&wx)[U], double (&xx)[U], double (&Lx)[NL]) {
 #pragma unroll
                 for (int q = 0; q < U; ++q) {
-                    const int64_t i = rp + (int64_t)NT * max(T0 - q, tb);
+                    const int t = max(T0 - q, tb), xq = t - 2 * v - wrow;
+                    const int64_t i = valid && xq >= 1 && xq <= n - 1 - v ? rp + (int64_t)NT * t : 0;
                     wx[q] = w[i];
                     xx[q] = xs[i];
                     if (STORED)

@@ -29,6 +29,7 @@ namespace ilu {
 
 constexpr int WAVE = 64;    // wavefront size; point kernels handle 64-lane groups
 constexpr int PAD = 2;      // zero steps on each side of a block window
+constexpr int TAIL = 4;     // zero steps after the last block (unconditional neighbour loads)
 constexpr int NDIR = 15;
 constexpr int NLOW = 7;
 

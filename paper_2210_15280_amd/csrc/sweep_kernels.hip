@@ -13,15 +13,21 @@ namespace ilu {
 // r = b - A x on the interior (Sec. 2.1 stencil matvec, FP64).  The centre and
 // lower weights of p are stored at p; the upper weight A^p_{-d} equals the
 // lower weight A^{p-d}_d stored at the upper neighbour (symmetric form).
-// Neighbours on the macro boundary read stored zeros.  With `subtract` = 0 it
-// computes y = A x instead (r holds y, b is ignored).  One workgroup handles
-// 64 lanes x RES_T hyperplanes of one block; per-workgroup partial sums of r^2
-// go to `partial` (deterministic reduction afterwards).
-template <typename RT>
+// Neighbours on the macro boundary read stored zeros.  SUB = false computes
+// y = A x instead (r holds y, b is not read).  One workgroup handles 64 lanes
+// x RES_T hyperplanes of one block; wave k takes hyperplanes t0 + k + 8i and
+// t0 + k + 4 + 8i together.  All 62 loads of the two points are issued before
+// any arithmetic and without conditions (the second point of the last chunk is
+// clamped to the block's own padding slot te + 1, inactive points store 0 to
+// slots that stay 0, and neighbour rows may read up to 3 hyperplanes past a
+// window, into the stream tail), so the loads overlap instead of waiting one by
+// one.  Per-workgroup partial sums of r^2 go to `partial` (deterministic
+// reduction afterwards).
+template <typename RT, bool SUB>
 __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                                   const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S,
                                                   const double* __restrict__ A8, const double* __restrict__ x,
-                                                  const double* __restrict__ b, RT* __restrict__ r, int subtract,
+                                                  const double* __restrict__ b, RT* __restrict__ r,
                                                   double* __restrict__ partial) {
     __shared__ double red[256];
     int blk, lane;
@@ -31,8 +37,10 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
     const LaneDev& Ln = lanes[(int64_t)blk * lpb + lane];
     double acc2 = 0.0;
     const int t0 = B.tb + (int)blockIdx.y * RES_T;
-    if (Ln.v != 0 && t0 <= B.te) {
+    if (t0 <= B.te) {
         const int n = tets[B.tet].n, v = Ln.v, w = Ln.w;
+        const bool valid = v != 0;
+        const int64_t rs = Ln.rp[R_SELF];
         int64_t rpl[NLOW], rpu[NLOW];
 #pragma unroll
         for (int s = 0; s < NLOW; ++s) {
@@ -40,21 +48,39 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
             rpu[s] = Ln.rp[up_row(s)] + (int64_t)lpb * up_dt(s);
         }
         const int t1 = min(B.te, t0 + RES_T - 1);
-        for (int t = t0 + sub; t <= t1; t += 4) {
-            const int xx = t - 2 * v - w;
-            if (xx < 1 || xx > n - 1 - v) continue;
-            const int64_t off = (int64_t)lpb * t;
-            const int64_t idx = Ln.rp[R_SELF] + off;
-            double acc = A8[idx] * x[idx];
+        for (int t = t0 + sub; t <= t1; t += 8) {
+            const int tp[2] = {t, min(t + 4, B.te + 1)};
+            bool act[2];
+            double a[2][15], xv[2][15], bv[2];
 #pragma unroll
-            for (int s = 0; s < NLOW; ++s) {
-                acc += A8[(int64_t)(1 + s) * S + idx] * x[rpl[s] + off];
-                const int64_t qu = rpu[s] + off;
-                acc += A8[(int64_t)(1 + s) * S + qu] * x[qu];
+            for (int p = 0; p < 2; ++p) {
+                const int xx = tp[p] - 2 * v - w;
+                act[p] = valid && xx >= 1 && xx <= n - 1 - v && (p == 0 || t + 4 <= t1);
+                // inactive points read the zero region (cache resident) instead of
+                // padding slots, so padding costs no memory traffic
+                const int64_t off = act[p] ? (int64_t)lpb * tp[p] : 0;
+                const int64_t idx = act[p] ? rs + off : 0;
+                a[p][0] = A8[idx];
+                xv[p][0] = x[idx];
+                bv[p] = SUB ? b[idx] : 0.0;
+#pragma unroll
+                for (int s = 0; s < NLOW; ++s) {
+                    const int64_t ql = act[p] ? rpl[s] + off : 0, qu = act[p] ? rpu[s] + off : 0;
+                    a[p][1 + 2 * s] = A8[(int64_t)(1 + s) * S + idx];
+                    xv[p][1 + 2 * s] = x[ql];
+                    a[p][2 + 2 * s] = A8[(int64_t)(1 + s) * S + qu];
+                    xv[p][2 + 2 * s] = x[qu];
+                }
             }
-            const double rv = subtract ? b[idx] - acc : acc;
-            r[idx] = (RT)rv;
-            acc2 += rv * rv;
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                double acc = a[p][0] * xv[p][0];
+#pragma unroll
+                for (int k = 1; k < 15; ++k) acc += a[p][k] * xv[p][k];
+                const double rv = act[p] ? (SUB ? bv[p] - acc : acc) : 0.0;
+                r[rs + (int64_t)lpb * tp[p]] = (RT)rv;
+                acc2 += rv * rv;
+            }
         }
     }
     red[threadIdx.x] = acc2;
@@ -242,11 +268,18 @@ void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, dou
 void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
                      hipStream_t st) {
     dim3 grid(c.nblocks * c.groups, c.res_chunks);
-    if (f32)
-        k_residual<float><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (float*)r, subtract, partial);
+    if (f32 && subtract)
+        k_residual<float, true><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (float*)r,
+                                                       partial);
+    else if (f32)
+        k_residual<float, false><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (float*)r,
+                                                        partial);
+    else if (subtract)
+        k_residual<double, true><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (double*)r,
+                                                        partial);
     else
-        k_residual<double><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b, (double*)r, subtract,
-                                                  partial);
+        k_residual<double, false><<<grid, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8, x, b,
+                                                         (double*)r, partial);
 }
 
 void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st) {
