@@ -163,8 +163,19 @@ int ilu_last_timing(ilu_handle_t h, double *sweep_ms, double *fwd_kernel_ms, dou
                     double *res_kernel_ms);
 
 /* Record events around every kernel of every sweep (diagnostics; adds a
- * little launch overhead).  Off by default. */
+ * little launch overhead).  Off by default.  While on, sweeps run eagerly. */
 int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable);
+
+/* Graph replay (on by default).  An ilu_smooth call with rel_tol == 0 runs its
+ * sweeps as replays of one captured graph per handle.  That graph holds the
+ * batched sweep over every tetrahedron: the residual kernel, the forward
+ * substitution and the backward substitution with the update, each one
+ * persistent launch.  The graph is captured on the first such call, on a
+ * private stream, and replayed on the caller's stream.  Calls with
+ * rel_tol > 0 (which test the residual between sweeps) and calls with kernel
+ * timing on run eagerly.  Results are identical either way.  Per-kernel times
+ * of ilu_last_timing are 0 after a graph call. */
+int ilu_set_graph(ilu_handle_t h, int32_t enable);
 
 /* Host-only self check (no device needed): builds the stream layout for the
  * given tetrahedra and replays every index the kernels form, counting

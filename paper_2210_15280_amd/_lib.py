@@ -68,6 +68,7 @@ def lib():
         L.ilu_tile.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.ilu_last_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.ilu_set_kernel_timing.argtypes = [P, I32]
+        L.ilu_set_graph.argtypes = [P, I32]
         L.ilu_check_layout.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, ctypes.POINTER(ilu_opts),
                                        ctypes.POINTER(I64)]
         _lib = L
@@ -220,6 +221,10 @@ class Smoother:
 
     def set_kernel_timing(self, enable: bool):
         _check(self.L.ilu_set_kernel_timing(self.h, 1 if enable else 0), "ilu_set_kernel_timing")
+
+    def set_graph(self, enable: bool):
+        """Replay fixed-count sweeps from a captured graph (default on)."""
+        _check(self.L.ilu_set_graph(self.h, 1 if enable else 0), "ilu_set_graph")
 
     def close(self):
         if getattr(self, "h", None) and self.h.value:

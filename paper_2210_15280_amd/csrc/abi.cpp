@@ -96,6 +96,9 @@ struct ilu_handle_s {
     bool kernel_timing = false;          // events around every kernel of every sweep
     std::vector<hipEvent_t> kev;         // 4 per sweep: res begin/end = fwd begin, fwd end = bwd begin, bwd end
     int kev_sweeps = 0;
+    bool use_graph = true;               // replay fixed-count sweeps from a captured graph
+    hipStream_t cap = nullptr;           // private stream the sweep graph is captured on
+    hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
 
     Ctx ctx() const {
         Ctx c;
@@ -132,6 +135,8 @@ struct ilu_handle_s {
         return f;
     }
     ~ilu_handle_s() {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (cap) hipStreamDestroy(cap);
         for (auto& e : ev)
             if (e) hipEventDestroy(e);
         for (auto& e : kev)
@@ -512,7 +517,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         h->w.alloc((size_t)S * es, st))
         return ILU_ENOMEM;
     const Ctx c = h->ctx();
-    h->npartial = (int64_t)c.nblocks * c.groups * c.res_chunks;
+    h->npartial = res_partials(c);
     if (h->partial.alloc((size_t)h->npartial * sizeof(double), st) || h->norms.alloc(4 * sizeof(double), st))
         return ILU_ENOMEM;
     if (upload(h->order_fwd, topo_order(h->blocks, true), st) || upload(h->order_bwd, topo_order(h->blocks, false), st))
@@ -733,6 +738,29 @@ void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
     }
 }
 
+// Capture one sweep (residual, forward and backward substitution over every
+// tetrahedron of the handle) into an executable graph.  It only touches
+// handle-owned buffers, so it stays valid for the life of the handle; it holds
+// kernel nodes only, and the dataflow tag is advanced by a kernel on device,
+// so every replay is a fresh sweep.
+int capture_sweep(ilu_handle_t h, const Ctx& c) {
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, h->variant == ILU_SURR_F32, 1, nullptr, h->cap);
+    sweep_fwd(h, c, h->cap);
+    sweep_bwd(h, c, h->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+    const hipError_t e2 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        h->gexec = nullptr;
+        return hip_fail(e2, "hipGraphInstantiate", __LINE__);
+    }
+    return ILU_OK;
+}
+
 double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
     double v = 0.0;
     *err = hipMemcpyAsync(&v, h->norms.as<double>() + slot, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -857,8 +885,16 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
         return hipSuccess;
     };
     int done = 0;
+    // fixed number of sweeps: replay the captured one-sweep graph
+    const bool graph = h->use_graph && rel_tol == 0.0 && !h->kernel_timing && nsweeps > 0;
+    if (graph && !h->gexec)
+        if (int e = capture_sweep(h, c)) return e;
     HIPCHK(hipEventRecord(h->ev[0], st));
-    for (int k = 0; k < nsweeps; ++k) {
+    for (int k = 0; graph && k < nsweeps; ++k) {
+        HIPCHK(hipGraphLaunch(h->gexec, st));
+        ++done;
+    }
+    for (int k = 0; !graph && k < nsweeps; ++k) {
         HIPCHK(mark(k, 0));
         launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1,
                         rel_tol > 0.0 ? h->partial.as<double>() : nullptr, st);
@@ -882,7 +918,7 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
     HIPCHK(hipEventRecord(h->ev[1], st));
     HIPCHK(hipGetLastError());
     h->have_timing = done > 0;
-    h->kev_sweeps = h->kernel_timing ? done : (done > 0 ? 1 : 0);
+    h->kev_sweeps = graph ? 0 : h->kernel_timing ? done : (done > 0 ? 1 : 0);
     if (want_norm && !converged) {
         launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1, h->partial.as<double>(), st);
         launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 1, st);
@@ -1006,6 +1042,12 @@ int ilu_last_timing(ilu_handle_t h, double* sweep_ms, double* fwd_kernel_ms, dou
 int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable) {
     if (!h) return ILU_EINVAL;
     h->kernel_timing = enable != 0;
+    return ILU_OK;
+}
+
+int ilu_set_graph(ilu_handle_t h, int32_t enable) {
+    if (!h) return ILU_EINVAL;
+    h->use_graph = enable != 0;
     return ILU_OK;
 }
 

@@ -8,6 +8,8 @@ namespace ilu {
 void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
                      hipStream_t st);
 void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st);
+// number of partial sums the residual and norm kernels write
+int64_t res_partials(const Ctx& c);
 void launch_reduce(const double* partial, int64_t count, double* out, int slot, hipStream_t st);
 void launch_fwd_plane(const Ctx& c, int variant, int t, hipStream_t st);
 void launch_bwd_plane(const Ctx& c, int variant, int t, double* x, hipStream_t st);

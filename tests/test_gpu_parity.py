@@ -256,3 +256,32 @@ def test_large_level_properties(torch, pkg):
         ok = j >= 0
         y[ok] += Lg[ok, s] * z[j[ok]]
     assert _rel(y, b) < 1e-12
+
+
+@pytest.mark.parametrize("variant,tile", [("STORED_F64", (8, 8)), ("SURR_F32", (16, 16)), ("SURR_F64", (16, 32))])
+def test_graph_replays_match_eager(torch, pkg, variant, tile):
+    # the captured one-sweep graph, replayed several times with eager library
+    # and torch work and synchronisations in between, reproduces the eager
+    # sweeps bit for bit on every replay
+    t = W.make_tet(10, 6, *W.KAPPA_SIN, jitter=0.15)
+    v = getattr(pkg, variant)
+    kw = {} if v == pkg.STORED_F64 else dict(degree=3, stride=4)
+    sm = pkg.Smoother([t], v, tile=tile, **kw)
+    b = torch.tensor(t.rhs(), device="cuda")
+    sm.set_graph(False)
+    xe = torch.zeros_like(b)
+    sm.smooth(xe, b, 4)
+    ref = xe.cpu().numpy()
+    sm.set_graph(True)
+    for rep in range(3):
+        x = torch.zeros_like(b)
+        sm.smooth(x, b, 4)
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), ref), (variant, rep)
+        y = sm.apply(x)
+        assert float((y * 2.0).abs().sum()) > 0.0
+        sm.set_graph(False)
+        xr = torch.zeros_like(b)
+        sm.smooth(xr, b, 1)
+        sm.set_graph(True)
+        torch.cuda.synchronize()
