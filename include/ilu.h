@@ -78,7 +78,10 @@ typedef struct ilu_opts {
     int32_t schedule;       /* ILU_SCHED_* */
     int32_t tile[2];        /* rows per block (BV, BW) of the sweep schedule in the
                                skewed row coordinates (v, w) = (y+z, z): (8,8), (16,16)
-                               or (16,32); (0,0) = chosen from the levels */
+                               or (16,32).  (0,0) = autotuned: setup builds the smoother
+                               with every shape (least-squares fit once), times a few
+                               sweeps of each on the device and keeps the fastest
+                               (hyperplane schedule: chosen from the levels) */
     int32_t reserved[2];    /* must be 0 */
 } ilu_opts;
 

@@ -46,7 +46,7 @@ struct DevBuf {
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
     }
@@ -97,6 +97,7 @@ struct ilu_handle_s {
     std::vector<hipEvent_t> kev;         // 4 per sweep: res begin/end = fwd begin, fwd end = bwd begin, bwd end
     int kev_sweeps = 0;
     bool use_graph = true;               // replay fixed-count sweeps from a captured graph
+    double tuned_ms = 0.0;               // autotuner: measured sweep time of the chosen block shape
     hipStream_t cap = nullptr;           // private stream the sweep graph is captured on
     hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
 
@@ -135,12 +136,12 @@ struct ilu_handle_s {
         return f;
     }
     ~ilu_handle_s() {
-        if (gexec) hipGraphExecDestroy(gexec);
-        if (cap) hipStreamDestroy(cap);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cap) (void)hipStreamDestroy(cap);
         for (auto& e : ev)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
         for (auto& e : kev)
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -468,10 +469,18 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
     return ILU_OK;
 }
 
-int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t h) {
+void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
+void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
+
+// Full setup of one handle.  With `coef_in` (surrogate variants only) the
+// least-squares fit is skipped and these coefficients are used: the fit does
+// not depend on the block shape, so the tile autotuner fits once.
+int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t h,
+               const std::vector<double>* coef_in = nullptr) {
     int64_t soff = 0;
     if (int e = prepare(tets, ntets, opts, h, &soff)) return e;
     const bool surr = h->variant != ILU_STORED_F64;
+    const bool refit = !(surr && coef_in);
     if (upload(h->tets_d, h->tets, st) || upload(h->blocks_d, h->blocks, st) || upload(h->lanes_d, h->lanes, st))
         return ILU_ENOMEM;
     if (h->flags.alloc(4 * sizeof(int32_t), st) != hipSuccess) return ILU_ENOMEM;
@@ -480,18 +489,24 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     launch_assemble(h->ctx(), h->A8.as<double>(), nullptr, st);
     HIPCHK(hipGetLastError());
     // factorisation on the hyperplane schedule
-    if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    {
+    int32_t fl[4];
+    if (refit) {
+        if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+        if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         const Ctx c = h->ctx();
         for (int t = h->tmin; t <= h->tmax; ++t)
             launch_factor_plane(c, t, h->Lf.as<double>(), h->Df.as<double>(), h->flags.as<int>(), st);
         HIPCHK(hipGetLastError());
+        if (int e = read_flags(h, st, fl)) return e;
+        if (fl[0]) return ILU_EBREAKDOWN;
     }
-    int32_t fl[4];
-    if (int e = read_flags(h, st, fl)) return e;
-    if (fl[0]) return ILU_EBREAKDOWN;
-    if (!surr) {
+    if (!refit) {
+        h->coef_h = *coef_in;
+        if (h->coef_d.alloc(h->coef_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
+        HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+        if (int e = build_tables(h, st)) return e;
+    } else if (!surr) {
         if (h->Lb.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         launch_transpose(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->Lb.as<double>(), st);
         HIPCHK(hipGetLastError());
@@ -529,6 +544,74 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->bv, h->bw));
     for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+// Device time (ms) of one sweep (residual, forward and backward substitution)
+// on zero vectors: the sweep kernels have no data-dependent control flow, so
+// the values do not matter.  One warm-up sweep, then the mean of `reps`.
+int time_sweep(ilu_handle_t h, hipStream_t st, int reps, double* ms) {
+    const Ctx c = h->ctx();
+    HIPCHK(hipMemsetAsync(h->xs.p, 0, h->xs.bytes, st));
+    HIPCHK(hipMemsetAsync(h->bs.p, 0, h->bs.bytes, st));
+    for (int k = 0; k <= reps; ++k) {
+        if (k == 1) HIPCHK(hipEventRecord(h->ev[0], st));
+        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, h->variant == ILU_SURR_F32, 1, nullptr, st);
+        sweep_fwd(h, c, st);
+        sweep_bwd(h, c, st);
+    }
+    HIPCHK(hipEventRecord(h->ev[1], st));
+    HIPCHK(hipEventSynchronize(h->ev[1]));
+    float a = 0;
+    HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+    *ms = a / reps;
+    int32_t fl[4];
+    if (int e = read_flags(h, st, fl)) return e;
+    return fl[2] ? ILU_EHIP : ILU_OK;
+}
+
+// Tile autotuner: set the handle up with every supported block shape (the
+// least-squares fit only once), time a few sweeps of each and keep the fastest.
+// Shapes whose sweep kernels would spill registers are skipped.
+int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t* out) {
+    static const int shapes[3][2] = {{8, 8}, {16, 16}, {16, 32}};
+    ilu_handle_t best = nullptr;
+    double best_ms = 0.0;
+    const std::vector<double>* coef = nullptr;
+    std::vector<double> coef_keep;
+    for (const auto& sh : shapes) {
+        if (opts->variant == ILU_SURR_F64 && opts->degree[0] >= 3 && sh[1] == 32) continue;
+        ilu_opts o = *opts;
+        o.tile[0] = sh[0];
+        o.tile[1] = sh[1];
+        ilu_handle_t h = new (std::nothrow) ilu_handle_s();
+        if (!h) {
+            delete best;
+            return ILU_ENOMEM;
+        }
+        int rc = setup_impl(tets, ntets, &o, st, h, coef);
+        double ms = 0.0;
+        if (rc == ILU_OK) rc = time_sweep(h, st, 3, &ms);
+        if (rc != ILU_OK) {
+            (void)hipStreamSynchronize(st);
+            delete h;
+            delete best;
+            return rc;
+        }
+        if (h->variant != ILU_STORED_F64 && !coef) {
+            coef_keep = h->coef_h;
+            coef = &coef_keep;
+        }
+        if (!best || ms < best_ms) {
+            delete best;
+            best = h;
+            best_ms = ms;
+        } else {
+            delete h;
+        }
+    }
+    best->tuned_ms = best_ms;
+    *out = best;
     return ILU_OK;
 }
 
@@ -815,11 +898,13 @@ int ilu_setup_surrogate(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts*
     if (!tets || !opts || !out || ntets <= 0) return ILU_EINVAL;
     *out = nullptr;
     if (int e = validate_args(tets, ntets, opts)) return e;
+    if (opts->tile[0] == 0 && opts->tile[1] == 0 && opts->schedule != ILU_SCHED_PLANE)
+        return setup_autotuned(tets, ntets, opts, (hipStream_t)hip_stream, out);
     ilu_handle_t h = new (std::nothrow) ilu_handle_s();
     if (!h) return ILU_ENOMEM;
     const int rc = setup_impl(tets, ntets, opts, (hipStream_t)hip_stream, h);
     if (rc != ILU_OK) {
-        hipStreamSynchronize((hipStream_t)hip_stream);
+        (void)hipStreamSynchronize((hipStream_t)hip_stream);
         delete h;
         return rc;
     }
@@ -841,7 +926,7 @@ int ilu_check_layout(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* op
 
 int ilu_destroy(ilu_handle_t h) {
     if (!h) return ILU_OK;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     delete h;
     return ILU_OK;
 }

@@ -285,3 +285,24 @@ def test_graph_replays_match_eager(torch, pkg, variant, tile):
         sm.smooth(xr, b, 1)
         sm.set_graph(True)
         torch.cuda.synchronize()
+
+
+def test_autotuned_tile(torch, pkg):
+    # tile (0, 0): setup times every supported block shape and keeps one; the
+    # result equals an explicitly tiled run bit for bit (the per-point
+    # arithmetic does not depend on the shape), FP64 surrogates of degree >= 3
+    # never take the 16 x 32 shape (its kernels would spill registers)
+    t = W.make_tet(12, 6, *W.KAPPA_SIN, jitter=0.15)
+    b = torch.tensor(t.rhs(), device="cuda")
+    for v, kw in ((pkg.STORED_F64, {}), (pkg.SURR_F32, dict(degree=3, stride=4)), (pkg.SURR_F64, dict(degree=3, stride=4))):
+        auto = pkg.Smoother([t], v, **kw)
+        assert auto.tile in ((8, 8), (16, 16), (16, 32))
+        if v == pkg.SURR_F64:
+            assert auto.tile != (16, 32)
+        fixed = pkg.Smoother([t], v, tile=(8, 8), **kw)
+        xa, xf = torch.zeros_like(b), torch.zeros_like(b)
+        auto.smooth(xa, b, 3)
+        fixed.smooth(xf, b, 3)
+        assert torch.equal(xa, xf), (v, auto.tile)
+        auto.close()
+        fixed.close()
