@@ -119,6 +119,32 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     return out
 
 
+def run_to_tol(pkg, torch, wl, variant, tol, cap, tile=(0, 0)):
+    """One ilu_smooth call from x = 0 until ||b - A x|| / ||b|| <= tol (FP64
+    residual; for the FP32 variant this is its FP64 iterative refinement)."""
+    import numpy as np
+    kw = {} if variant == "stored_f64" else dict(degree=wl.degree, stride=wl.stride)
+    kw["tile"] = tile
+    sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
+    b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
+    x = torch.zeros_like(b)
+    sm.smooth(x, b, 3)
+    x.zero_()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rel, ok = sm.smooth(x, b, cap, rel_tol=tol, want_relres=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k = sm.last_sweeps
+    out = dict(variant=variant, n_dof=sm.n_total, sweeps=k, ms=ms, value=sm.n_total * k / (ms * 1e-3),
+               relres_after=rel, converged=bool(ok), tile=list(sm.tile), x=x.cpu().numpy())
+    sm.close()
+    return out
+
+
 def roofline(res, variant, dg, workload):
     bpd = kernel_bytes(variant)
     fpd = kernel_flops(variant, dg)
@@ -196,6 +222,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", default="auto", help="block shape BVxBW of the sweep schedule, e.g. 16x32")
     ap.add_argument("--copy-bytes", type=int, default=0, help="also run a streaming copy of this size")
+    ap.add_argument("--to-tol", type=float, default=0.0,
+                    help="instead of fixed sweeps: time each variant's refinement to this relative residual")
+    ap.add_argument("--max-sweeps", type=int, default=20000)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -208,6 +237,8 @@ def main():
     wl = W.workload(a.workload)
     variants = a.variants.split(",")
     tile = (0, 0) if a.tile == "auto" else tuple(int(c) for c in a.tile.split("x"))
+    if a.to_tol > 0:
+        return main_to_tol(a, torch, pkg, wl, variants, tile)
     results = {}
     for v in variants:
         results[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
@@ -244,6 +275,40 @@ def main():
         line["speedup_vs_stored_f64"] = hr["value"] / results["stored_f64"]["value"]
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, head)
+    print(json.dumps(line))
+
+
+def main_to_tol(a, torch, pkg, wl, variants, tile):
+    import numpy as np
+    res = {}
+    for v in variants:
+        res[v] = run_to_tol(pkg, torch, wl, v, a.to_tol, a.max_sweeps, tile)
+        r = res[v]
+        print("# %s: %d sweeps to relres %.3e (%s) in %.1f ms, %.3e DOF-updates/s, tile %s" % (
+            v, r["sweeps"], r["relres_after"], "converged" if r["converged"] else "NOT converged", r["ms"], r["value"],
+            "x".join(map(str, r["tile"]))), file=sys.stderr, flush=True)
+    head = variants[0]
+    hr = res[head]
+    ref = res.get("stored_f64")
+    for v, r in res.items():
+        r["rel_diff_vs_stored_f64"] = (float(np.linalg.norm(r["x"] - ref["x"]) / np.linalg.norm(ref["x"]))
+                                       if ref is not None else None)
+    line = {
+        "metric": "smoothed DOF-updates/s (ILU(0) sweep) on 1 MI355X; FP32 surrogate vs FP64 stored",
+        "value": hr["value"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": hr["sweeps"], "warmup": 3,
+        "ms_per_step": hr["ms"] / max(1, hr["sweeps"]), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
+                  "stored_f64": "f64"}[head],
+        "data": "synthetic (seeded jittered macro-tetrahedra, seeded RHS)",
+        "config": {"workload": wl.name, "variant": head, "n_tets": len(wl.tets), "n_dof": hr["n_dof"],
+                   "levels": sorted({t.level for t in wl.tets}), "surrogate_degree": wl.degree,
+                   "sample_stride": wl.stride, "rel_tol": a.to_tol, "tile": hr["tile"], "parallelism": "single GPU"},
+        "to_tol": {v: {k: r[k] for k in ("sweeps", "ms", "value", "relres_after", "converged", "tile",
+                                          "rel_diff_vs_stored_f64")} for v, r in res.items()},
+    }
+    if ref is not None and head != "stored_f64":
+        line["time_to_tol_speedup_vs_stored_f64"] = ref["ms"] / hr["ms"]
     print(json.dumps(line))
 
 

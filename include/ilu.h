@@ -96,13 +96,17 @@ typedef struct ilu_handle_s *ilu_handle_t;
 int ilu_setup_surrogate(const ilu_tet_desc *tets, int32_t ntets, const ilu_opts *opts, void *hip_stream,
                         ilu_handle_t *out);
 
-/* Apply `nsweeps` smoothing steps x <- x + C^{-1}(b - A x) (Alg. 2) to every
- * tetrahedron.  x (in/out) and b (in) are FP64 device arrays in the layout
- * above.  If rel_tol > 0 the loop stops early once ||b - A x||_2 / ||b||_2 <=
- * rel_tol over all tetrahedra (checked after every sweep; this synchronises)
- * and returns ILU_ENOTCONV if it is not reached.  relres_out (host, may be
- * NULL) receives the final relative residual, which is only computed when
- * rel_tol > 0 or relres_out != NULL.  Otherwise stream-ordered. */
+/* Apply up to `nsweeps` smoothing steps x <- x + C^{-1}(b - A x) (Alg. 2) to
+ * every tetrahedron.  x (in/out) and b (in) are FP64 device arrays in the
+ * layout above.  If rel_tol > 0 the loop stops early once
+ * ||b - A x||_2 / ||b||_2 <= rel_tol over all tetrahedra (the FP64 iterative
+ * refinement of the FP32 variant): every sweep's residual kernel reduces the
+ * norm on the device, the host reads the norms after every 8 sweeps (this
+ * synchronises), and a hit is confirmed on the current x.  ILU_ENOTCONV if the
+ * tolerance is not reached.  relres_out (host, may be NULL) receives the
+ * relative residual of the returned x, computed when rel_tol > 0 or
+ * relres_out != NULL.  With rel_tol == 0 the sweeps replay a captured graph
+ * (see ilu_set_graph) and the call is stream-ordered apart from relres_out. */
 int ilu_smooth(ilu_handle_t h, double *x, const double *b, int32_t nsweeps, double rel_tol, double *relres_out,
                void *hip_stream);
 
@@ -151,6 +155,11 @@ int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double *L_out, double 
 
 /* Effective sample stride chosen for tetrahedron `tet` (surrogate variants). */
 int ilu_sample_stride(ilu_handle_t h, int32_t tet, int32_t *stride_out);
+
+/* Number of sweeps the last ilu_smooth call ran (with rel_tol > 0 the
+ * tolerance is tested after every 8 sweeps, so up to 7 sweeps may follow the
+ * first one that met it). */
+int ilu_last_sweeps(ilu_handle_t h, int32_t *sweeps_out);
 
 /* Block shape (rows in v, rows in w) of the sweep schedule the handle uses:
  * the one requested in ilu_opts.tile, or the automatic choice. */

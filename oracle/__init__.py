@@ -8,6 +8,7 @@ least-squares fit uses numpy/scipy library primitives.
 Functions and the passage they follow:
   interior_points, index_of   Sec. 2.1 logical coordinates, lexicographic order
   assemble, apply              Sec. 2.1 bilinear form and stencil matvec
+  stencil_at                   Sec. 2.1 stencil rows of single points
   ilu0                         Sec. 3 definition of ILU(0) (IKJ on CSR)
   ilu0_stencil                 Sec. 3 stencil equations / Alg. 1
   smooth                       Sec. 2.1 Richardson smoother with C = L D L^T
@@ -64,6 +65,8 @@ def _L():
         lib.oracle_assemble.restype = i64
         lib.oracle_assemble.argtypes = [p, i32, i32, p, p, p]
         lib.oracle_apply.argtypes = [i64, p, p, p, p]
+        lib.oracle_stencil_at.restype = i32
+        lib.oracle_stencil_at.argtypes = [p, i32, i32, p, i64, p, p]
         lib.oracle_ilu0_csr_inplace.restype = i64
         lib.oracle_ilu0_csr_inplace.argtypes = [i64, p, p, p]
         lib.oracle_ilu0_csr.restype = i64
@@ -105,6 +108,36 @@ def element_stiffness(P, kappa: float = 1.0):
     K = np.zeros(16)
     det = _L().oracle_element_stiffness(_ptr(P), float(kappa), _ptr(K))
     return K.reshape(4, 4), det
+
+
+def stencil_at(tet, xyz) -> np.ndarray:
+    """(k,15) stencil rows A^p_d of the given interior points of `tet`, summed
+    point by point over the incident micro-tets (Sec. 2.1); boundary
+    neighbours give 0."""
+    xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.int32).reshape(-1, 3))
+    verts = np.ascontiguousarray(np.asarray(tet.verts, dtype=np.float64).reshape(12))
+    cp = tuple(tet.coeff_params)
+    params = np.ascontiguousarray(np.asarray(cp + (0.0,) * (4 - len(cp)), dtype=np.float64))
+    out = np.zeros((len(xyz), 15))
+    if _L().oracle_stencil_at(_ptr(verts), int(tet.level), int(tet.coeff_kind), _ptr(params), len(xyz),
+                              _ptr(xyz), _ptr(out)) != 0:
+        raise ValueError("point not interior")
+    return out
+
+
+def random_interior(level: int, count: int, seed: int) -> np.ndarray:
+    """`count` distinct uniformly drawn interior points (rejection sampling)."""
+    n = 1 << level
+    rng = np.random.default_rng(seed)
+    pts = set()
+    while len(pts) < count:
+        c = rng.integers(1, n - 2, size=(4 * count, 3), endpoint=True)
+        c = c[c.sum(1) <= n - 1]
+        for p in map(tuple, c):
+            pts.add(p)
+            if len(pts) == count:
+                break
+    return np.array(sorted(pts), dtype=np.int32)
 
 
 class Problem:

@@ -12,7 +12,8 @@
  *   lattice / DOF numbering            [Sec. 2.1, logical grid coordinates and
  *                                       the lexicographic ordering]
  *   micro-mesh, P1 element stiffness,  [Sec. 2.1, bilinear form a(u,v) and the
- *   assembly of R_t A R_t^T             stencil notation A^p_d]
+ *   assembly of R_t A R_t^T,            stencil notation A^p_d]
+ *   stencil rows of single points
  *   ILU(0), definition (IKJ on CSR)    [Sec. 3, (L D L^T)_ij = A_ij on S_A]
  *   ILU(0), stencil recurrences        [Sec. 3, eq. (matrix-equations); Alg. 1]
  *   smoothing step, matrix form        [Sec. 2.1 Richardson smoother with
@@ -250,6 +251,61 @@ int64_t oracle_assemble(const double *verts, int level, int kind, const double *
                 }
     lattice_free(&lt);
     return ntets;
+}
+
+/* Stencil rows A^p_d (d in listing order) of `count` given interior points,
+ * each summed directly over the micro-tets incident to the point (Sec. 2.1,
+ * the same element matrices as oracle_assemble, one point at a time, so it
+ * serves lattices too large to assemble whole).  Point p is vertex k of the
+ * Kuhn tetrahedron (q, sigma) exactly when q = p - (first k unit steps of
+ * sigma) in the (a, b, c) coordinates; entries whose neighbour lies on the
+ * macro boundary are 0.  Returns 0, or -1 for a point that is not interior. */
+int oracle_stencil_at(const double *verts, int level, int kind, const double *params, int64_t count,
+                      const int32_t *xyz, double *A_out) {
+    const int64_t n = (int64_t)1 << level;
+    static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    for (int64_t i = 0; i < count; ++i) {
+        double *row = A_out + NDIR * i;
+        for (int s = 0; s < NDIR; ++s) row[s] = 0.0;
+        const int64_t px = xyz[3 * i], py = xyz[3 * i + 1], pz = xyz[3 * i + 2];
+        if (!is_interior(n, px, py, pz)) return -1;
+        const int64_t p_abc[3] = {px, px + py, px + py + pz};
+        for (int s = 0; s < 6; ++s)
+            for (int k = 0; k < 4; ++k) {
+                int64_t abc[4][3];
+                for (int m = 0; m < 3; ++m) abc[0][m] = p_abc[m];
+                for (int m = 0; m < k; ++m) abc[0][perm[s][m]] -= 1;
+                int ok = 1;
+                for (int m = 0; m < 3; ++m) ok = ok && abc[0][m] >= 0 && abc[0][m] <= n - 1;
+                if (!ok) continue;
+                for (int v = 1; v < 4; ++v) {
+                    for (int m = 0; m < 3; ++m) abc[v][m] = abc[v - 1][m];
+                    if (v < 3) abc[v][perm[s][v - 1]] += 1;
+                    else for (int m = 0; m < 3; ++m) abc[v][m] = abc[0][m] + 1;
+                }
+                for (int v = 0; v < 4 && ok; ++v)
+                    ok = 0 <= abc[v][0] && abc[v][0] <= abc[v][1] && abc[v][1] <= abc[v][2] && abc[v][2] <= n;
+                if (!ok) continue;
+                int64_t vx[4][3];
+                double P[12], cen[3] = {0, 0, 0};
+                for (int v = 0; v < 4; ++v) {
+                    vx[v][0] = abc[v][0];
+                    vx[v][1] = abc[v][1] - abc[v][0];
+                    vx[v][2] = abc[v][2] - abc[v][1];
+                    micro_position(verts, n, vx[v][0], vx[v][1], vx[v][2], P + 3 * v);
+                    for (int m = 0; m < 3; ++m) cen[m] += 0.25 * P[3 * v + m];
+                }
+                double K[16];
+                oracle_element_stiffness(P, kappa_at(kind, params, cen), K);
+                for (int j = 0; j < 4; ++j) {
+                    if (!is_interior(n, vx[j][0], vx[j][1], vx[j][2])) continue;
+                    const int sl = slot_of((int)(vx[j][0] - px), (int)(vx[j][1] - py), (int)(vx[j][2] - pz));
+                    if (sl < 0) return -1;
+                    row[sl] += K[4 * k + j];
+                }
+            }
+    }
+    return 0;
 }
 
 /* y = (R_t A R_t^T) x on the interior (Sec. 2.1 stencil matvec). */

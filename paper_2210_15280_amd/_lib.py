@@ -66,6 +66,7 @@ def lib():
         L.ilu_get_surrogate_values.argtypes = [P, I32, P, P, P]
         L.ilu_sample_stride.argtypes = [P, I32, ctypes.POINTER(I32)]
         L.ilu_tile.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.ilu_last_sweeps.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_last_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.ilu_set_kernel_timing.argtypes = [P, I32]
         L.ilu_set_graph.argtypes = [P, I32]
@@ -204,6 +205,13 @@ class Smoother:
         s = ctypes.c_int32()
         _check(self.L.ilu_sample_stride(self.h, tet, ctypes.byref(s)), "ilu_sample_stride")
         return s.value
+
+    @property
+    def last_sweeps(self) -> int:
+        """Sweeps the last smooth call ran."""
+        k = ctypes.c_int32()
+        _check(self.L.ilu_last_sweeps(self.h, ctypes.byref(k)), "ilu_last_sweeps")
+        return k.value
 
     @property
     def tile(self):

@@ -98,6 +98,7 @@ struct ilu_handle_s {
     int kev_sweeps = 0;
     bool use_graph = true;               // replay fixed-count sweeps from a captured graph
     double tuned_ms = 0.0;               // autotuner: measured sweep time of the chosen block shape
+    int last_sweeps = 0;                 // sweeps the last ilu_smooth call ran
     hipStream_t cap = nullptr;           // private stream the sweep graph is captured on
     hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
 
@@ -533,7 +534,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         return ILU_ENOMEM;
     const Ctx c = h->ctx();
     h->npartial = res_partials(c);
-    if (h->partial.alloc((size_t)h->npartial * sizeof(double), st) || h->norms.alloc(4 * sizeof(double), st))
+    if (h->partial.alloc((size_t)h->npartial * sizeof(double), st) || h->norms.alloc(16 * sizeof(double), st))
         return ILU_ENOMEM;
     if (upload(h->order_fwd, topo_order(h->blocks, true), st) || upload(h->order_bwd, topo_order(h->blocks, false), st))
         return ILU_ENOMEM;
@@ -979,32 +980,53 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
         HIPCHK(hipGraphLaunch(h->gexec, st));
         ++done;
     }
-    for (int k = 0; !graph && k < nsweeps; ++k) {
-        HIPCHK(mark(k, 0));
-        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1,
-                        rel_tol > 0.0 ? h->partial.as<double>() : nullptr, st);
-        HIPCHK(mark(k, 1));
-        if (rel_tol > 0.0) {
-            launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 1, st);
-            rel = std::sqrt(host_norm(h, 1, st, &err)) / bn;
-            if (err) return ILU_EHIP;
-            if (rel <= rel_tol) {
-                converged = true;
-                break;
-            }
+    // eager sweeps.  With rel_tol > 0 they run in chunks of CHK: every sweep's
+    // residual kernel also reduces ||b - A x||^2 into its own slot, and after
+    // a chunk one read of those slots tells whether the tolerance was met; if
+    // so, the current x is checked directly (the residual need not fall
+    // monotonically) and the loop ends once it passes.
+    constexpr int CHK = 8;
+    bool final_known = false;
+    while (!graph && done < nsweeps) {
+        const int m = rel_tol > 0.0 ? std::min(CHK, nsweeps - done) : nsweeps - done;
+        for (int j = 0; j < m; ++j) {
+            const int k = done + j;
+            HIPCHK(mark(k, 0));
+            launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1,
+                            rel_tol > 0.0 ? h->partial.as<double>() : nullptr, st);
+            if (rel_tol > 0.0) launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 2 + j, st);
             HIPCHK(mark(k, 1));
+            sweep_fwd(h, c, st);
+            HIPCHK(mark(k, 2));
+            sweep_bwd(h, c, st);
+            HIPCHK(mark(k, 3));
         }
-        sweep_fwd(h, c, st);
-        HIPCHK(mark(k, 2));
-        sweep_bwd(h, c, st);
-        HIPCHK(mark(k, 3));
-        ++done;
+        done += m;
+        if (rel_tol > 0.0) {
+            double nv[CHK];
+            HIPCHK(hipMemcpyAsync(nv, h->norms.as<double>() + 2, m * sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool hit = false;
+            for (int j = 0; j < m; ++j) hit = hit || std::sqrt(nv[j]) / bn <= rel_tol;
+            if (hit) {
+                launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1, h->partial.as<double>(), st);
+                launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 1, st);
+                rel = std::sqrt(host_norm(h, 1, st, &err)) / bn;
+                if (err) return ILU_EHIP;
+                final_known = true;
+                if (rel <= rel_tol) {
+                    converged = true;
+                    break;
+                }
+            }
+        }
     }
     HIPCHK(hipEventRecord(h->ev[1], st));
     HIPCHK(hipGetLastError());
     h->have_timing = done > 0;
     h->kev_sweeps = graph ? 0 : h->kernel_timing ? done : (done > 0 ? 1 : 0);
-    if (want_norm && !converged) {
+    h->last_sweeps = done;
+    if (want_norm && !final_known) {
         launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1, h->partial.as<double>(), st);
         launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 1, st);
         rel = std::sqrt(host_norm(h, 1, st, &err)) / bn;
@@ -1083,6 +1105,12 @@ int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double* L_out, double*
     launch_export_surrogate(h->ctx(), h->variant == ILU_SURR_F32, tet, L_out, Dinv_out, st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_last_sweeps(ilu_handle_t h, int32_t* sweeps_out) {
+    if (!h || !sweeps_out) return ILU_EINVAL;
+    *sweeps_out = h->last_sweeps;
     return ILU_OK;
 }
 

@@ -306,3 +306,108 @@ def test_autotuned_tile(torch, pkg):
         assert torch.equal(xa, xf), (v, auto.tile)
         auto.close()
         fixed.close()
+
+
+# ------------------------------------------------ full size, bench configuration
+
+def _l9_setup():
+    wl = W.workload("jit_L9_exp")
+    t = wl.tets[0]
+    pts = O.random_interior(9, 1500, seed=1)
+    return wl, t, pts
+
+
+def _nbr(level, pts, dirs):
+    # lexicographic indices of pts + d for each d (-1: not interior)
+    return np.stack([O.index_of(level, pts + d) for d in dirs], axis=1)
+
+
+def _gather(torch, dev, idx):
+    # rows of a device tensor at host indices (-1 -> 0)
+    i = torch.tensor(np.maximum(idx, 0), device="cuda")
+    out = dev[i].cpu().numpy()
+    out[idx < 0] = 0.0
+    return out
+
+
+def _ldlt_apply_at(torch, level, pts, L_dev, D_dev, x_dev, diag_is_inverse=False):
+    # (L D L^T x)_p at the sample points, with L^p_d the lower factor in
+    # direction d (0 if p+d is not interior), by products:
+    #   y_q = x_q + sum_d L^{q-d}_d x_{q-d},  z_q = D_q y_q,  out_p = z_p + sum_d L^p_d z_{p+d}
+    low = O.DIRS[:7]
+    qs = np.concatenate([pts[:, None, :], pts[:, None, :] + low[None, :, :]], axis=1)  # p and p + d
+    qflat = qs.reshape(-1, 3)
+    iq = O.index_of(level, qflat)
+    up = _nbr(level, qflat, [-d for d in low])                  # q - d
+    Lup = np.stack([_gather(torch, L_dev[:, s], up[:, s]) for s in range(7)], axis=1)
+    xup = np.stack([_gather(torch, x_dev, up[:, s]) for s in range(7)], axis=1)
+    y = _gather(torch, x_dev, iq) + (Lup * xup).sum(axis=1)
+    Dq = _gather(torch, D_dev, iq)
+    if diag_is_inverse:
+        Dq = np.where(iq >= 0, 1.0 / np.where(Dq == 0, 1.0, Dq), 0.0)
+    z = np.where(iq >= 0, Dq * y, 0.0).reshape(len(pts), 8)
+    ip = O.index_of(level, pts)
+    Lp = _gather(torch, L_dev, ip)
+    return z[:, 0] + (Lp * z[:, 1:]).sum(axis=1)
+
+
+def test_full_size_level9_stored(torch, pkg):
+    # the benchmark workload at full size (22,108,415 points) in the launch
+    # configuration the benchmark times (autotuned tile, graph replay):
+    # stencil rows vs the oracle at sampled points, the ILU(0) definition
+    # (L D L^T)_{p,p+d} = A^p_d there with the oracle's A, and the first sweep
+    # from x = 0 solving L D L^T x = b (checked by products)
+    wl, t, pts = _l9_setup()
+    sm = pkg.Smoother([t], pkg.STORED_F64)
+    ip = O.index_of(9, pts)
+    A_or = O.stencil_at(t, pts)
+    A_dev = sm.stencil(0)
+    A_g = A_dev[torch.tensor(ip, device="cuda")].cpu().numpy()
+    del A_dev
+    assert np.abs(A_g - A_or).max() <= 1e-12 * np.abs(A_or).max()
+    L_dev, D_dev = sm.factors(0)
+    nb = _nbr(9, pts, O.DIRS)
+    lower = {tuple(O.DIRS[k]): k for k in range(7)}
+    Lp = _gather(torch, L_dev, ip)
+    Dp = _gather(torch, D_dev, ip)
+    for s in list(range(7)) + [7]:
+        d = O.DIRS[s]
+        q = nb[:, s]
+        ok = q >= 0
+        acc = np.where(ok, Dp, 0.0) if s == 7 else np.zeros(len(pts))
+        for dt in range(7):
+            e = tuple(O.DIRS[dt] - d)
+            if e == (0, 0, 0):
+                Lq = np.ones(len(pts))
+            elif e in lower:
+                Lq = _gather(torch, L_dev[:, lower[e]], q)
+            else:
+                continue
+            r = nb[:, dt]
+            m = ok & (r >= 0)
+            acc = acc + np.where(m, Lp[:, dt] * _gather(torch, D_dev, r) * Lq, 0.0)
+        want = np.where(ok, A_or[:, s], 0.0)
+        assert np.abs(acc - want).max() <= 1e-11 * np.abs(A_or).max(), O.DIR_NAMES[s]
+    b = torch.tensor(t.rhs(), device="cuda")
+    x = torch.zeros_like(b)
+    sm.smooth(x, b, 1)
+    Cx = _ldlt_apply_at(torch, 9, pts, L_dev, D_dev, x)
+    bp = b[torch.tensor(ip, device="cuda")].cpu().numpy()
+    assert np.abs(Cx - bp).max() <= 1e-11 * np.abs(bp).max()
+
+
+def test_full_size_level9_fp32_surrogate(torch, pkg):
+    # the benchmark's headline variant at full size in its launch
+    # configuration: one FP32 sweep from x = 0 solves L~ D~ L~^T x = b with the
+    # kernels' own surrogate weights, to FP32 accuracy, at sampled points
+    wl, t, pts = _l9_setup()
+    sm = pkg.Smoother([t], pkg.SURR_F32, degree=wl.degree, stride=wl.stride)
+    assert sm.sample_stride(0) == O.effective_stride(9, wl.degree, wl.stride)
+    Lw, Dinv = sm.surrogate_values(0)
+    b = torch.tensor(t.rhs(), device="cuda")
+    x = torch.zeros_like(b)
+    sm.smooth(x, b, 1)
+    Cx = _ldlt_apply_at(torch, 9, pts, Lw, Dinv, x, diag_is_inverse=True)
+    ip = O.index_of(9, pts)
+    bp = b[torch.tensor(ip, device="cuda")].cpu().numpy()
+    assert np.abs(Cx - bp).max() <= 1e-4 * np.abs(bp).max()

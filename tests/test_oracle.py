@@ -107,6 +107,34 @@ def test_row_sums_vanish_and_symmetry(coeff):
     assert np.all(P.A[:, 7] > 0)
 
 
+@pytest.mark.parametrize("level", [3, 4])
+def test_stencil_at_equals_assembly(level):
+    # point-by-point stencil rows (sum over the 24 incident micro-tets) equal
+    # the rows of the whole-lattice assembly, boundary neighbours dropped
+    t, P = _jittered(level, *W.KAPPA_EXP, seed=21)
+    A = O.stencil_at(t, O.interior_points(level))
+    want = np.where(P.col >= 0, P.A, 0.0)
+    assert np.abs(A - want).max() <= 1e-14 * np.abs(want).max()
+
+
+def test_stencil_at_closed_form_and_row_sums_at_level9():
+    # a lattice too large to assemble whole: deep interior points of the
+    # reference tet have the closed-form stencil; on a jittered tet with a
+    # variable coefficient the rows of points away from the boundary sum to 0
+    n = 512
+    ref = W.Tet(W.REFERENCE_TET, 9, W.COEFF_CONST, (1.0, 0, 0, 0), 0)
+    pts = np.array([[100, 100, 100], [3, 4, 5], [200, 150, 140], [1, 1, 509 - 300]], dtype=np.int32)
+    deep = pts[np.all(pts >= 2, axis=1) & (pts.sum(axis=1) <= n - 3)]
+    want = np.array([REFERENCE_STENCIL[nm] for nm in O.DIR_NAMES]) / (3 * n)
+    np.testing.assert_allclose(O.stencil_at(ref, deep), np.broadcast_to(want, (len(deep), 15)), rtol=0, atol=1e-15)
+    t = W.make_tet(5, 9, *W.KAPPA_EXP, jitter=0.15)
+    sample = O.random_interior(9, 400, seed=3)
+    away = sample[np.all(sample >= 2, axis=1) & (sample.sum(axis=1) <= n - 3)]
+    A = O.stencil_at(t, away)
+    assert np.abs(A.sum(axis=1)).max() <= 1e-13 * np.abs(A).max()
+    assert np.all(A[:, 7] > 0)
+
+
 def test_second_moment_identity():
     # P1 reproduces quadratics in the weak sense on a translation-invariant
     # lattice: J (sum_d A_d d d^T) J^T = -2 h |det J| I  (kappa = 1, any affine tet)
