@@ -12,16 +12,16 @@
 // own rows plus one halo column and one halo row holding rows of the
 // neighbouring blocks.
 //
-// Blocks hand boundary values to each other through an exchange buffer.  A
-// separate halo wave in every workgroup does all of this traffic, so the
-// compute waves never wait on another block's memory: after every
-// hyperplane it copies the block's outgoing edge values (last column and last
-// row in sweep direction) from LDS to the buffer, each with a 32-bit launch
-// tag in one 64-bit word (FP64 values: two words, one per half); it loads the
-// incoming entries D hyperplanes ahead and checks the tag right before the
-// value goes into the LDS grid; only a stale entry is polled again.  No block ever waits
-// for its own stores, and no progress counter sits between producer and
-// consumer.  The tag is a device counter that the reset kernel advances
+// Blocks hand boundary values to each other through an exchange buffer.  Two
+// extra waves in every workgroup do all of this traffic, so the compute waves
+// never wait on another block's memory.  After every hyperplane the outgoing
+// wave copies the block's edge values (last column and last row in sweep
+// direction) from LDS to the buffer, each with a 32-bit launch tag in one
+// 64-bit word (FP64 values: two words, one per half).  The incoming wave loads
+// the entries it needs D hyperplanes ahead and checks the tag right before the
+// value goes into the LDS grid; only a stale entry is polled again.  No block
+// ever waits for its own stores, and no progress counter sits between
+// producer and consumer.  The tag is a device counter that the reset kernel advances
 // before every sweep, so graph replays never see entries of earlier sweeps
 // (tags repeat after 2^32 sweeps).
 //
@@ -157,13 +157,16 @@ __device__ __forceinline__ T halo_take(const Halo& h, const uint64_t* xch, int n
 
 // ------------------------------------------------------------------ forward
 //
-// Workgroup = BV*BW compute threads (one per row) + one halo wave.  Halo-wave
-// lane i < BW+BV+1 owns incoming halo row i (column, row, corner) and lane
-// i < BW+BV outgoing entry i; the producer lane of each entry is the one
-// xch_out_lane names.  Both paths pass the same barriers.
+// Workgroup = BV*BW compute threads (one per row) + an incoming wave + an
+// outgoing wave.  Incoming lane i < BW+BV+1 owns halo row i (column, row,
+// corner); outgoing lane i < BW+BV owns exchange entry i, whose producer lane
+// is the one xch_out_lane names.  Loads and stores live in different waves
+// because one wave's memory counter completes in issue order: a wait for a
+// halo load would otherwise also wait for the slow device-coherent stores
+// issued before it.  All paths pass the same barriers.
 
 template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
-__global__ void __launch_bounds__(BV* BW + WAVE)
+__global__ void __launch_bounds__(BV* BW + 2 * WAVE)
     k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lf, const T* __restrict__ tab,
                const T* __restrict__ r, T* __restrict__ w, const int32_t* __restrict__ order,
@@ -187,9 +190,26 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
         const int b = order[k];
         const BlockDev B = blocks[b];
         const int tb = B.tb, te = B.te;
-        for (int i = l; i < 4 * GC; i += NT + WAVE) grid[i] = (T)0;
-        if (l >= NT) {
-            // ---------------- halo wave
+        for (int i = l; i < 4 * GC; i += NT + 2 * WAVE) grid[i] = (T)0;
+        if (l >= NT + WAVE) {
+            // ---------------- outgoing wave: copies the block's edge values of
+            // hyperplane t-1 (published by the last barrier) to the exchange
+            // buffer.  It only stores, so it never waits on memory in the loop.
+            const int hlane = l - NT - WAVE;
+            const bool out = hlane < NX;
+            int ovl = 0, owl = 0;
+            if (out) xch_out_lane(0, hlane, BV, BW, &ovl, &owl);
+            const int ocell = (owl + 1) * GW + (ovl + 1);
+            __syncthreads();
+            __syncthreads();
+            for (int t = tb; t <= te; ++t) {
+                if (out && t > tb)
+                    x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, t - 1, hlane), grid[((t - 1) & 3) * GC + ocell], tag);
+                lds_barrier();
+            }
+            if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, te, hlane), grid[(te & 3) * GC + ocell], tag);
+        } else if (l >= NT) {
+            // ---------------- incoming wave: loads and checks only
             const int hlane = l - NT;
             Halo hin;
             int kk = 0, j = 0;
@@ -206,10 +226,6 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
                     hin.j = j;
                 }
             }
-            const bool out = hlane < NX;
-            int ovl = 0, owl = 0;
-            if (out) xch_out_lane(0, hlane, BV, BW, &ovl, &owl);
-            const int ocell = (owl + 1) * GW + (ovl + 1);
             __syncthreads();
             XEnt<T> hx[D];
             if (hin.role) {
@@ -227,9 +243,6 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
                 for (int q = 0; q < D; ++q) {
                     const int t = T0 + q;
                     if (t > te) break;
-                    // outgoing values of hyperplane t-1 (published by the last barrier)
-                    if (out && t > tb)
-                        x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, t - 1, hlane), grid[((t - 1) & 3) * GC + ocell], tag);
                     if (hin.role) {
                         grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx[q], tag, flags);
                         halo_issue(hin, xch, NX, t + D, hx[q]);
@@ -237,7 +250,6 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
                     lds_barrier();
                 }
             }
-            if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, te, hlane), grid[(te & 3) * GC + ocell], tag);
         } else {
             // ---------------- compute waves
             const int vl = l % BV, wl = l / BV;
@@ -328,7 +340,7 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
 // ----------------------------------------------------------------- backward
 
 template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
-__global__ void __launch_bounds__(BV* BW + WAVE)
+__global__ void __launch_bounds__(BV* BW + 2 * WAVE)
     k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lb, const T* __restrict__ tab,
                const T* __restrict__ w, double* __restrict__ xs, const int32_t* __restrict__ order,
@@ -352,9 +364,24 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
         const int b = order[k];
         const BlockDev B = blocks[b];
         const int tb = B.tb, te = B.te;
-        for (int i = l; i < 4 * GC; i += NT + WAVE) grid[i] = (T)0;
-        if (l >= NT) {
-            // ---------------- halo wave (halo at column BV and row BW of the grid)
+        for (int i = l; i < 4 * GC; i += NT + 2 * WAVE) grid[i] = (T)0;
+        if (l >= NT + WAVE) {
+            // ---------------- outgoing wave (edge values of hyperplane t+1)
+            const int hlane = l - NT - WAVE;
+            const bool out = hlane < NX;
+            int ovl = 0, owl = 0;
+            if (out) xch_out_lane(1, hlane, BV, BW, &ovl, &owl);
+            const int ocell = owl * GW + ovl;
+            __syncthreads();
+            __syncthreads();
+            for (int t = te; t >= tb; --t) {
+                if (out && t < te)
+                    x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, t + 1, hlane), grid[((t + 1) & 3) * GC + ocell], tag);
+                lds_barrier();
+            }
+            if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, tb, hlane), grid[(tb & 3) * GC + ocell], tag);
+        } else if (l >= NT) {
+            // ---------------- incoming wave (halo at column BV and row BW of the grid)
             const int hlane = l - NT;
             Halo hin;
             int kk = 0, j = 0;
@@ -371,10 +398,6 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
                     hin.j = j;
                 }
             }
-            const bool out = hlane < NX;
-            int ovl = 0, owl = 0;
-            if (out) xch_out_lane(1, hlane, BV, BW, &ovl, &owl);
-            const int ocell = owl * GW + ovl;
             __syncthreads();
             XEnt<T> hx[D];
             if (hin.role) {
@@ -392,8 +415,6 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
                 for (int q = 0; q < D; ++q) {
                     const int t = T0 - q;
                     if (t < tb) break;
-                    if (out && t < te)
-                        x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, t + 1, hlane), grid[((t + 1) & 3) * GC + ocell], tag);
                     if (hin.role) {
                         grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx[q], tag, flags);
                         halo_issue(hin, xch, NX, t - D, hx[q]);
@@ -401,7 +422,6 @@ __global__ void __launch_bounds__(BV* BW + WAVE)
                     lds_barrier();
                 }
             }
-            if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, tb, hlane), grid[(tb & 3) * GC + ocell], tag);
         } else {
             // ---------------- compute waves
             const int vl = l % BV, wl = l / BV;
@@ -507,10 +527,14 @@ namespace {
 // Batch depth U (operands of the next U hyperplanes are loaded while the
 // current U run) and halo distance D.  Both batches of loads must fit the
 // 63-entry vector memory counter: stored factors load 8 (forward) or 10
-// (backward) values per hyperplane.
-constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 4;  // stored factors
-constexpr int U_S64 = 4, D_S64 = 4;              // FP64 surrogate
-constexpr int U_F32 = 8, D_F32 = 4;              // FP32 surrogate
+// (backward) values per hyperplane.  D = 1 (the entry of hyperplane t+1 is
+// loaded during hyperplane t) measured fastest: every extra hyperplane of
+// halo lead adds a hyperplane of lag per block hop on the critical path, which
+// costs more than the load latency it hides (D = 1, 2, 4, 8 at level 9:
+// forward sweep 0.64, 0.66, 0.69, 0.81 ms with 16 x 32 blocks).
+constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 1;  // stored factors
+constexpr int U_S64 = 4, D_S64 = 1;              // FP64 surrogate
+constexpr int U_F32 = 8, D_F32 = 1;              // FP32 surrogate
 
 template <int BV, int BW>
 struct Shape {
@@ -528,34 +552,34 @@ struct Shape {
         return (const void*)k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW>;
     }
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
-        k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+        k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, (const double*)c.r, (double*)c.w, f.order_fwd,
             f.xch, f.ticket, f.flags);
     }
     static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
-        k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+        k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, (const double*)c.w, x, f.order_bwd, f.xch,
             f.ticket, f.flags);
     }
     template <int NC>
     static void fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+            k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.r, (double*)c.w,
                 f.order_fwd, f.xch, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+            k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.r, (float*)c.w,
                 f.order_fwd, f.xch, f.ticket, f.flags);
     }
     template <int NC>
     static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
         if (variant == 1)
-            k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+            k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.w, x, f.order_bwd,
                 f.xch, f.ticket, f.flags);
         else
-            k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + WAVE, 0, st>>>(
+            k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.w, x, f.order_bwd,
                 f.xch, f.ticket, f.flags);
     }
@@ -586,8 +610,8 @@ int resident(int variant, int NC) {
 #undef ILU_PTRS
     }
     int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, BV * BW + WAVE, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, BV * BW + WAVE, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, BV * BW + 2 * WAVE, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, BV * BW + 2 * WAVE, 0) != hipSuccess)
         return 1;
     return a < b ? a : b;
 }
