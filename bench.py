@@ -34,7 +34,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 def kernel_bytes(variant: str):
     wb = 4 if variant == "surr_f32" else 8
     res = 8 + 8 + 64 + wb                    # x, b, A (8 weights), r
-    if variant == "stored_f64":
+    if variant in ("stored_f64", "stored_sgs"):
         fwd = 8 + 56 + 8                      # r, L (7), w
         bwd = 8 + 8 + 56 + 8 + 8              # w in, 1/D, L^T (7), x in, x out
     else:
@@ -45,13 +45,18 @@ def kernel_bytes(variant: str):
 
 def kernel_flops(variant: str, dg: int):
     res = 30                                  # 15 multiply-adds
-    if variant == "stored_f64":
+    if variant in ("stored_f64", "stored_sgs"):
         return {"residual": res, "forward": 14, "backward": 16}
     # Horner: dg multiply-adds per direction (7 forward, 8 backward) plus the sweep
     return {"residual": res, "forward": 14 + 14 * dg, "backward": 16 + 16 * dg}
 
 
-VARIANTS = {"stored_f64": 0, "surr_f64": 1, "surr_f32": 2}
+VARIANTS = {"stored_f64": 0, "surr_f64": 1, "surr_f32": 2, "stored_sgs": 3}
+STORED = ("stored_f64", "stored_sgs")
+DTYPES = {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
+          "stored_f64": "f64", "stored_sgs": "f64"}
+CONTRACTION_STEPS = 20
+CONTRACTION_SEED = 0x5EED
 KERNEL_NAMES = {"residual": "k_residual", "forward": "k_fwd_flow", "backward": "k_bwd_flow"}
 
 
@@ -81,9 +86,17 @@ def measured_traffic(workload: str, variant: str, kernel: str):
     return e["fetch_bytes"] + e["write_bytes"]
 
 
+def start_vector(torch, n):
+    """Seeded U[-1,1] start error of the contraction measurement."""
+    import workloads as W
+    return torch.tensor(W.SplitMix64(CONTRACTION_SEED).uniform_array(n, -1.0, 1.0), device="cuda")
+
+
 def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
+    """Times `steps` sweeps; also measures the smoother's contraction factor.
+    Returns (results, handle): the caller closes the handle."""
     import numpy as np
-    kw = {} if variant == "stored_f64" else dict(degree=wl.degree, stride=wl.stride)
+    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride)
     kw["tile"] = tile
     t0 = time.perf_counter()
     sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
@@ -111,19 +124,23 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     sm.smooth(x2, b, steps)
     torch.cuda.synchronize()
     _, f_ms, b_ms, r_ms = sm.timing()
+    sm.set_kernel_timing(False)
     n = sm.n_total
+    # asymptotic contraction: power iteration on I - C^{-1} A from a seeded start
+    x2.copy_(start_vector(torch, n))
+    rho, rho_res = sm.contraction(x2, CONTRACTION_STEPS)
     out = dict(variant=variant, n_dof=n, setup_s=setup_s, ms_per_step=ms / steps,
                loop_ms_per_step=loop_ms / steps, value=n * steps / (ms * 1e-3), relres_after=rel,
-               kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms), tile=list(sm.tile))
-    sm.close()
-    return out
+               kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms), tile=list(sm.tile),
+               contraction=dict(rho=rho, rho_res=rho_res, steps=CONTRACTION_STEPS))
+    return out, sm
 
 
 def run_to_tol(pkg, torch, wl, variant, tol, cap, tile=(0, 0)):
     """One ilu_smooth call from x = 0 until ||b - A x|| / ||b|| <= tol (FP64
     residual; for the FP32 variant this is its FP64 iterative refinement)."""
     import numpy as np
-    kw = {} if variant == "stored_f64" else dict(degree=wl.degree, stride=wl.stride)
+    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride)
     kw["tile"] = tile
     sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
     b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
@@ -142,6 +159,48 @@ def run_to_tol(pkg, torch, wl, variant, tol, cap, tile=(0, 0)):
     out = dict(variant=variant, n_dof=sm.n_total, sweeps=k, ms=ms, value=sm.n_total * k / (ms * 1e-3),
                relres_after=rel, converged=bool(ok), tile=list(sm.tile), x=x.cpu().numpy())
     sm.close()
+    return out
+
+
+def lattice_coords(level: int):
+    """(x, y, z) of the interior points in lexicographic order (z slowest)."""
+    import numpy as np
+    n = 1 << level
+    parts = []
+    for z in range(1, n - 2):
+        m = n - 1 - z                            # x + y <= m
+        cnt = np.arange(m - 1, 0, -1)            # y = 1..m-1 holds m - y points
+        y = np.repeat(np.arange(1, m, dtype=np.int16), cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        x = (np.arange(len(y)) - start + 1).astype(np.int16)
+        parts.append(np.stack([x, y, np.full(len(y), z, dtype=np.int16)], axis=1))
+    return np.concatenate(parts)
+
+
+LOWER = ((-1, 0, 0), (0, -1, 0), (1, -1, 0), (-1, 1, -1), (0, 1, -1), (0, 0, -1), (1, 0, -1))
+LOWER_NAMES = ("w", "s", "se", "bnw", "bn", "bc", "be")
+
+
+def surrogate_quality(torch, stored, surr, tet_level):
+    """Surrogate error per direction against the exact ILU(0) of the same tet
+    (first tet of the workload): relative discrete L2 error and max-abs error
+    of L_d over the points whose neighbour p + d is interior, and of 1/D over
+    all points.  Both operands come from the library (exact factors of the
+    stored handle, weights as the sweeps evaluate them)."""
+    Lx, Dx = stored.factors(0)
+    Ls, Ds = surr.surrogate_values(0)
+    xyz = torch.tensor(lattice_coords(tet_level), device="cuda").to(torch.int32)
+    n = 1 << tet_level
+    s = xyz.sum(dim=1)
+    out = {}
+    for d, (dx, dy, dz) in enumerate(LOWER):
+        m = ((xyz[:, 0] + dx >= 1) & (xyz[:, 1] + dy >= 1) & (xyz[:, 2] + dz >= 1) & (s + dx + dy + dz <= n - 1))
+        e = (Ls[:, d] - Lx[:, d])[m]
+        out[LOWER_NAMES[d]] = dict(rel_l2=float(e.norm() / Lx[:, d][m].norm()), max_abs=float(e.abs().max()))
+    di = 1.0 / Dx
+    e = Ds - di
+    out["c (1/D)"] = dict(rel_l2=float(e.norm() / di.norm()), max_abs=float(e.abs().max()))
+    del Lx, Dx, Ls, Ds, xyz
     return out
 
 
@@ -225,6 +284,10 @@ def main():
     ap.add_argument("--to-tol", type=float, default=0.0,
                     help="instead of fixed sweeps: time each variant's refinement to this relative residual")
     ap.add_argument("--max-sweeps", type=int, default=20000)
+    ap.add_argument("--pcg-tol", type=float, default=0.0,
+                    help="instead of fixed sweeps: time CG preconditioned by each variant to this relative residual")
+    ap.add_argument("--pcg-abs-tol", type=float, default=0.0, help="absolute residual target of --pcg-tol mode")
+    ap.add_argument("--max-iters", type=int, default=5000)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -239,12 +302,26 @@ def main():
     tile = (0, 0) if a.tile == "auto" else tuple(int(c) for c in a.tile.split("x"))
     if a.to_tol > 0:
         return main_to_tol(a, torch, pkg, wl, variants, tile)
-    results = {}
+    if a.pcg_tol > 0 or a.pcg_abs_tol > 0:
+        return main_pcg(a, torch, pkg, wl, variants, tile)
+    results, handles = {}, {}
     for v in variants:
-        results[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
-        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, tile %s, kernels %s" % (
+        results[v], handles[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
+        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, tile %s, kernels %s, contraction %.6f" % (
             v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],
-            "x".join(map(str, results[v]["tile"])), json.dumps(results[v]["kernel_ms"])), file=sys.stderr, flush=True)
+            "x".join(map(str, results[v]["tile"])), json.dumps(results[v]["kernel_ms"]),
+            results[v]["contraction"]["rho"]), file=sys.stderr, flush=True)
+        if v not in STORED and "stored_f64" not in variants:
+            handles[v].close()
+    quality = {v: {"contraction": r["contraction"]} for v, r in results.items()}
+    if "stored_f64" in handles:
+        for v in variants:
+            if v not in STORED:
+                quality[v]["surrogate_error_vs_exact_ilu"] = surrogate_quality(
+                    torch, handles["stored_f64"], handles[v], wl.tets[0].level)
+    for h in handles.values():
+        h.close()
+    torch.cuda.empty_cache()
     if a.copy_bytes:
         copy_calibration(torch, a.copy_bytes)
     head = variants[0]
@@ -260,8 +337,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
-                  "stored_f64": "f64"}[head],
+        "dtype": DTYPES[head],
         "data": "synthetic (seeded jittered macro-tetrahedra, seeded RHS)",
         "config": {"workload": wl.name, "variant": head, "n_tets": len(wl.tets),
                    "levels": sorted({t.level for t in wl.tets}), "n_dof": hr["n_dof"],
@@ -270,6 +346,7 @@ def main():
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "loop_ms_per_step", "relres_after", "setup_s",
                                             "kernel_ms", "tile")} for v, r in results.items()},
         "roofline": roofline(hr, head, wl.degree, wl.name),
+        "quality": quality,
     }
     if "stored_f64" in results and head != "stored_f64":
         line["speedup_vs_stored_f64"] = hr["value"] / results["stored_f64"]["value"]
@@ -298,8 +375,7 @@ def main_to_tol(a, torch, pkg, wl, variants, tile):
         "value": hr["value"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": hr["sweeps"], "warmup": 3,
         "ms_per_step": hr["ms"] / max(1, hr["sweeps"]), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
-                  "stored_f64": "f64"}[head],
+        "dtype": DTYPES[head],
         "data": "synthetic (seeded jittered macro-tetrahedra, seeded RHS)",
         "config": {"workload": wl.name, "variant": head, "n_tets": len(wl.tets), "n_dof": hr["n_dof"],
                    "levels": sorted({t.level for t in wl.tets}), "surrogate_degree": wl.degree,
@@ -309,6 +385,54 @@ def main_to_tol(a, torch, pkg, wl, variants, tile):
     }
     if ref is not None and head != "stored_f64":
         line["time_to_tol_speedup_vs_stored_f64"] = ref["ms"] / hr["ms"]
+    print(json.dumps(line))
+
+
+def run_pcg(pkg, torch, wl, variant, rel_tol, abs_tol, cap, tile=(0, 0)):
+    """CG preconditioned by one smoother variant, from x = 0, until the
+    recursively updated residual meets the tolerance; device time of the call."""
+    import numpy as np
+    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride)
+    kw["tile"] = tile
+    sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
+    b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
+    x = torch.zeros_like(b)
+    sm.pcg(x, b, 2, rel_tol=rel_tol, abs_tol=abs_tol)     # warm-up (captures the iteration graph)
+    x.zero_()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    k, res, ok = sm.pcg(x, b, cap, rel_tol=rel_tol, abs_tol=abs_tol)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    bn = float(b.norm())
+    out = dict(variant=variant, n_dof=sm.n_total, iterations=k, ms=ms, ms_per_iteration=ms / max(k, 1),
+               true_relres=res / bn, true_res=res, converged=bool(ok), tile=list(sm.tile))
+    sm.close()
+    return out
+
+
+def main_pcg(a, torch, pkg, wl, variants, tile):
+    res = {}
+    for v in variants:
+        res[v] = r = run_pcg(pkg, torch, wl, v, a.pcg_tol, a.pcg_abs_tol, a.max_iters, tile)
+        print("# pcg %s: %d iterations in %.1f ms (%.3f ms/it), true relres %.3e, %s" % (
+            v, r["iterations"], r["ms"], r["ms_per_iteration"], r["true_relres"],
+            "converged" if r["converged"] else "NOT converged"), file=sys.stderr, flush=True)
+    head = variants[0]
+    line = {
+        "metric": "PCG time to tolerance on 1 MI355X (preconditioner = smoother variant)",
+        "value": res[head]["ms"], "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+        "dtype": DTYPES[head], "data": "synthetic (seeded jittered macro-tetrahedra, seeded RHS)",
+        "config": {"workload": wl.name, "variant": head, "n_dof": res[head]["n_dof"], "rel_tol": a.pcg_tol,
+                   "abs_tol": a.pcg_abs_tol, "surrogate_degree": wl.degree, "parallelism": "single GPU"},
+        "pcg": res,
+    }
+    for ref in ("stored_f64", "stored_sgs"):
+        if ref in res and head != ref:
+            line["time_speedup_vs_" + ref] = res[ref]["ms"] / res[head]["ms"]
     print(json.dumps(line))
 
 

@@ -57,6 +57,11 @@ extern "C" {
 #define ILU_SURR_F64 1   /* surrogate weights evaluated on the fly, FP64 sweeps */
 #define ILU_SURR_F32 2   /* surrogate weights and both sweeps in FP32; residual and
                             update in FP64 (iterative refinement) */
+#define ILU_STORED_SGS 3 /* comparator: symmetric Gauss-Seidel (Sec. 2.1),
+                            C = (D_A + L_A) D_A^{-1} (D_A + L_A)^T with D_A, L_A the
+                            diagonal and strictly lower part of A, stored in the
+                            factor form L^p_d = A^p_d / A^{p+d}_c, D^p = A^p_c and
+                            swept like ILU_STORED_F64 */
 
 /* sweep schedules */
 #define ILU_SCHED_AUTO 0      /* persistent dataflow kernel */
@@ -71,7 +76,7 @@ typedef struct ilu_tet_desc {
 } ilu_tet_desc;
 
 typedef struct ilu_opts {
-    int32_t variant;        /* ILU_STORED_F64 / ILU_SURR_F64 / ILU_SURR_F32 */
+    int32_t variant;        /* ILU_STORED_F64 / ILU_SURR_F64 / ILU_SURR_F32 / ILU_STORED_SGS */
     int32_t degree[3];      /* surrogate degrees (dg_x, dg_y, dg_z), each in [0, 6] */
     int32_t sample_stride;  /* stride of S_d (power of two); halved until every
                                sample set is unisolvent; 0 = 4 */
@@ -114,6 +119,36 @@ int ilu_smooth(ilu_handle_t h, double *x, const double *b, int32_t nsweeps, doub
  * arrays in the layout above.  Stream-ordered. */
 int stencil_apply(ilu_handle_t h, const double *x, double *y, void *hip_stream);
 
+/* Preconditioned conjugate gradients for A x = b with the handle's C^{-1} as
+ * preconditioner: the ILU (stored or surrogate) applied directly as a CG
+ * preconditioner as in the CG experiment of Sec. 4.3, or with ILU_STORED_SGS
+ * the symmetric Gauss-Seidel comparator.  Applying C^{-1} is one forward and
+ * one backward substitution from zero (in FP32 for ILU_SURR_F32: the vectors,
+ * A p and the CG scalars stay FP64).  x (in: start, out: iterate) and b are
+ * FP64 device arrays in the layout above.  Stops at the first iteration k
+ * with ||r_k||_2 <= max(rel_tol ||b||_2, abs_tol) for the recursively updated
+ * residual r_k, or after maxit iterations.  Every step, the scalars included,
+ * runs on the device (one iteration is replayed from a captured graph unless
+ * graph replay is off); the host reads the state after every 8 iterations,
+ * and iterations after convergence leave x unchanged.  iters_out (host, may
+ * be NULL): iterations done; resnorm_out (host, may be NULL): the true
+ * residual ||b - A x||_2 of the returned x.  ILU_ENOTCONV if the tolerance
+ * is not met, ILU_EBREAKDOWN if p.q or r.z is not positive (x then holds
+ * the last iterate).  Synchronous on hip_stream. */
+int ilu_pcg(ilu_handle_t h, double *x, const double *b, int32_t maxit, double rel_tol, double abs_tol,
+            int32_t *iters_out, double *resnorm_out, void *hip_stream);
+
+/* Asymptotic contraction factor of the smoother by power iteration (the rate
+ * definition of the numerical results in Sec. 4.3, applied to one smoothing
+ * step): with b = 0 a step maps x to (I - C^{-1} A) x.  Starting from x (FP64
+ * device array in the layout above, not zero), nsteps steps are applied, each
+ * followed by scaling to unit 2-norm.  rho_out (host): ||x_k||_2 / ||x_{k-1}||_2
+ * of the last step; rho_res_out (host, may be NULL): (||A x_k||_2 /
+ * ||A x_0||_2)^(1/k) of the unscaled iteration.  On return x holds the last
+ * scaled iterate.  Synchronous on hip_stream. */
+int ilu_contraction(ilu_handle_t h, double *x, int32_t nsteps, double *rho_out, double *rho_res_out,
+                    void *hip_stream);
+
 /* Offset and interior-point count of tetrahedron `tet` in the vectors. */
 int ilu_layout(ilu_handle_t h, int32_t tet, int64_t *offset, int64_t *count_interior);
 
@@ -135,7 +170,8 @@ const char *ilu_last_error(void);
  * neighbour lies on the macro boundary are 0. */
 int ilu_get_stencil(ilu_handle_t h, int32_t tet, double *A_out, void *hip_stream);
 
-/* Exact ILU(0) factors of tetrahedron `tet` (only for ILU_STORED_F64):
+/* Exact ILU(0) factors of tetrahedron `tet` (only for ILU_STORED_F64; the
+ * symmetric Gauss-Seidel factors for ILU_STORED_SGS):
  * L_out device FP64 [N][7] (directions w,s,se,bnw,bn,bc,be; 0 where the
  * neighbour is on the boundary), D_out device FP64 [N]. */
 int ilu_get_factors(ilu_handle_t h, int32_t tet, double *L_out, double *D_out, void *hip_stream);

@@ -16,6 +16,10 @@ Functions and the passage they follow:
   sample_set, fit_surrogate    Sec. 4.1 sample sets S_d and LSQ fit
   eval_surrogate               Sec. 4.1 surrogate polynomials
   asymptotic_stencil           Sec. 3 Gauss-Seidel iteration of the stencil equations
+  contraction_factor           Sec. 4.3 asymptotic rate by power iteration, applied to
+                               the smoother's error propagation I - C^{-1} A
+  Problem.sgs_factors          Sec. 2.1 symmetric Gauss-Seidel preconditioner in L D L^T form
+  pcg                          Sec. 4.3 CG experiment: CG preconditioned by C^{-1}
 """
 from __future__ import annotations
 
@@ -225,6 +229,58 @@ class Problem:
         return x, rel
 
 
+    def sgs_factors(self):
+        """Symmetric Gauss-Seidel (Sec. 2.1): C = (D_A + L_A) D_A^{-1} (D_A + L_A)^T
+        with D_A, L_A the diagonal and strictly lower part of A, written as
+        unit-lower L times D times L^T: L^p_d = A^p_d / A^{p+d}_c, D^p = A^p_c.
+        Returns (L (N,7), D (N,)) in the layout of ilu0."""
+        L = np.zeros((self.N, NLOW))
+        for d in range(NLOW):
+            j = self.col[:, d]
+            m = j >= 0
+            L[m, d] = self.A[m, d] / self.A[j[m], CENTRE]
+        return L, self.A[:, CENTRE].copy()
+
+    def precond(self, Lw, Dinv, f32: bool = False):
+        """z = C^{-1} r as one smoothing step from zero with right-hand side r
+        (Alg. 2; FP32 substitutions after rounding r when f32)."""
+        if f32:
+            L32, D32 = np.asarray(Lw, dtype=np.float32), np.asarray(Dinv, dtype=np.float32)
+            return lambda r: self.smooth_stencil_f32(L32, D32, r, None, 1)[0]
+        return lambda r: self.smooth_stencil(Lw, Dinv, r, None, 1)[0]
+
+
+def pcg(problem: "Problem", precond, b, x0=None, maxit: int = 1000, rel_tol: float = 0.0, abs_tol: float = 0.0):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel) for A x = b with
+    z = precond(r) ~ C^{-1} r, the use of the ILU as a CG preconditioner in
+    Sec. 4.3.  Stops at the first k with ||r_k|| <= max(rel_tol ||b||, abs_tol)
+    for the recursively updated residual.  Returns (x, iterations, ||r_k|| per
+    iteration starting with k = 0, converged)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    tol = max(rel_tol * np.linalg.norm(b), abs_tol)
+    r = b - problem.apply(x)
+    hist = [np.linalg.norm(r)]
+    if hist[-1] <= tol:
+        return x, 0, hist, True
+    z = precond(r)
+    p = z.copy()
+    rz = r @ z
+    for k in range(1, maxit + 1):
+        q = problem.apply(p)
+        alpha = rz / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        hist.append(np.linalg.norm(r))
+        if hist[-1] <= tol:
+            return x, k, hist, True
+        z = precond(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, maxit, hist, False
+
+
 def ilu0_csr_inplace(rowptr, colind, val):
     """Generic IKJ ILU(0) on any CSR matrix with sorted columns (in place)."""
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
@@ -376,3 +432,29 @@ def asymptotic_stencil(Ad, iters: int = 20000, tol: float = 1e-15):
         if np.max(np.abs(L - Lold)) < tol and abs(D - Dold) < tol * abs(D):
             break
     return L, D
+
+
+# ------------------------------------------------------------- contraction
+
+def contraction_factor(problem: "Problem", step, x0, steps: int = 20):
+    """Asymptotic contraction of one smoother by power iteration (the rate
+    definition of the numerical results in Sec. 4.3, applied to the smoothing
+    step itself): with b = 0 a step maps the error e to (I - C^{-1} A) e.
+    Start from x0, apply `steps` steps, normalising after each.
+
+    `step(y)` must return one smoothing step of y with zero right-hand side.
+    Returns (rho, rho_res): rho = ||x_k||_2 / ||x_{k-1}||_2 of the last step,
+    rho_res = (||A x_k||_2 / ||A x_0||_2)^(1/k) of the unnormalised iteration."""
+    y = np.array(x0, dtype=np.float64)
+    y /= np.linalg.norm(y)
+    ra = np.linalg.norm(problem.apply(y))
+    rho, logsum = float("nan"), 0.0
+    for _ in range(steps):
+        z = step(y)
+        nz = np.linalg.norm(z)
+        rz = np.linalg.norm(problem.apply(z))
+        rho = nz                     # ||y|| = 1
+        logsum += np.log(rz / ra)
+        y = z / nz
+        ra = rz / nz
+    return rho, float(np.exp(logsum / steps))

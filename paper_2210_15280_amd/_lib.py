@@ -9,7 +9,7 @@ from typing import Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 HEADER = os.path.join(HERE, "..", "include", "ilu.h")
 
-STORED_F64, SURR_F64, SURR_F32 = 0, 1, 2
+STORED_F64, SURR_F64, SURR_F32, STORED_SGS = 0, 1, 2, 3
 SCHED_AUTO, SCHED_PLANE, SCHED_DATAFLOW = 0, 1, 2
 COEFF_CONST, COEFF_SINPROD, COEFF_EXPSINCOS, COEFF_POLY = 0, 1, 2, 3
 
@@ -53,6 +53,8 @@ def lib():
                                           ctypes.POINTER(P)]
         L.ilu_smooth.argtypes = [P, P, P, I32, D, ctypes.POINTER(D), P]
         L.stencil_apply.argtypes = [P, P, P, P]
+        L.ilu_pcg.argtypes = [P, P, P, I32, D, D, ctypes.POINTER(I32), ctypes.POINTER(D), P]
+        L.ilu_contraction.argtypes = [P, P, I32, ctypes.POINTER(D), ctypes.POINTER(D), P]
         L.ilu_layout.argtypes = [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)]
         L.ilu_destroy.argtypes = [P]
         L.ilu_strerror.argtypes = [ctypes.c_int]
@@ -161,6 +163,25 @@ class Smoother:
             return rel.value, False
         _check(rc, "ilu_smooth")
         return rel.value, True
+
+    def pcg(self, x, b, maxit: int, rel_tol: float = 0.0, abs_tol: float = 0.0, stream=None):
+        """CG on A x = b preconditioned by this smoother's C; x is the start and
+        the result.  Returns (iterations, true residual norm, converged)."""
+        it, res = ctypes.c_int32(0), ctypes.c_double(-1.0)
+        rc = self.L.ilu_pcg(self.h, self._vec(x), self._vec(b), int(maxit), float(rel_tol), float(abs_tol),
+                            ctypes.byref(it), ctypes.byref(res), self._stream(stream))
+        if rc == -7:  # ILU_ENOTCONV
+            return it.value, res.value, False
+        _check(rc, "ilu_pcg")
+        return it.value, res.value, True
+
+    def contraction(self, x, nsteps: int = 20, stream=None):
+        """Power-iteration contraction factor from start vector x (overwritten
+        with the last normalised iterate).  Returns (rho, rho_res)."""
+        rho, rr = ctypes.c_double(), ctypes.c_double()
+        _check(self.L.ilu_contraction(self.h, self._vec(x), int(nsteps), ctypes.byref(rho), ctypes.byref(rr),
+                                      self._stream(stream)), "ilu_contraction")
+        return rho.value, rr.value
 
     def apply(self, x, stream=None):
         y = self.torch.empty_like(x)

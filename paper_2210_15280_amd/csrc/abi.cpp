@@ -17,6 +17,7 @@
 #include "ctx.h"
 #include "setup_kernels.h"
 #include "sweep_kernels.h"
+#include "krylov_kernels.h"
 
 using namespace ilu;
 
@@ -71,7 +72,8 @@ int64_t choose3_h(int64_t k) { return k < 3 ? 0 : k * (k - 1) * (k - 2) / 6; }
 
 struct ilu_handle_s {
     int ntets = 0;
-    int variant = 0;
+    int variant = 0;     // kernel variant: ILU_STORED_F64, ILU_SURR_F64 or ILU_SURR_F32
+    bool sgs = false;    // stored factors are the symmetric Gauss-Seidel ones
     int schedule = 0;
     int deg[3] = {0, 0, 0};
     int NC = 0, K = 0;
@@ -101,6 +103,8 @@ struct ilu_handle_s {
     int last_sweeps = 0;                 // sweeps the last ilu_smooth call ran
     hipStream_t cap = nullptr;           // private stream the sweep graph is captured on
     hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
+    DevBuf cg_r, cg_z, cg_p, cg_q, cg_sc;  // PCG vectors (stream layout) and scalars
+    hipGraphExec_t cg_exec = nullptr;    // one PCG iteration
 
     Ctx ctx() const {
         Ctx c;
@@ -138,6 +142,7 @@ struct ilu_handle_s {
     }
     ~ilu_handle_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
         if (cap) (void)hipStreamDestroy(cap);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -404,7 +409,8 @@ int build_tables(ilu_handle_t h, hipStream_t st) {
 // Host-only preparation: validated tetrahedron records, sample layout, block tables.
 int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_handle_t h, int64_t* nsamples) {
     h->ntets = ntets;
-    h->variant = opts->variant;
+    h->sgs = opts->variant == ILU_STORED_SGS;
+    h->variant = h->sgs ? ILU_STORED_F64 : opts->variant;
     h->schedule = opts->schedule == ILU_SCHED_PLANE ? ILU_SCHED_PLANE : ILU_SCHED_DATAFLOW;
     const bool surr = h->variant != ILU_STORED_F64;
     for (int k = 0; k < 3; ++k) h->deg[k] = surr ? opts->degree[k] : 0;
@@ -471,7 +477,7 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
 }
 
 void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
-void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
+void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target = nullptr);
 
 // Full setup of one handle.  With `coef_in` (surrogate variants only) the
 // least-squares fit is skipped and these coefficients are used: the fit does
@@ -495,8 +501,11 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         const Ctx c = h->ctx();
-        for (int t = h->tmin; t <= h->tmax; ++t)
-            launch_factor_plane(c, t, h->Lf.as<double>(), h->Df.as<double>(), h->flags.as<int>(), st);
+        if (h->sgs)
+            launch_sgs_factors(c, h->Lf.as<double>(), h->Df.as<double>(), h->flags.as<int>(), st);
+        else
+            for (int t = h->tmin; t <= h->tmax; ++t)
+                launch_factor_plane(c, t, h->Lf.as<double>(), h->Df.as<double>(), h->flags.as<int>(), st);
         HIPCHK(hipGetLastError());
         if (int e = read_flags(h, st, fl)) return e;
         if (fl[0]) return ILU_EBREAKDOWN;
@@ -812,14 +821,59 @@ void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
     }
 }
 
-void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st) {
+// Backward substitution; the correction is added to `target` (default: the
+// iterate x of the smoother).
+void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target) {
+    double* x = target ? target : h->xs.as<double>();
     if (h->schedule == ILU_SCHED_PLANE) {
-        for (int t = h->tmax; t >= h->tmin; --t) launch_bwd_plane(c, h->variant, t, h->xs.as<double>(), st);
+        for (int t = h->tmax; t >= h->tmin; --t) launch_bwd_plane(c, h->variant, t, x, st);
     } else {
         const Flow f = h->flow();
         launch_flow_reset(f, st);
-        launch_bwd_flow(c, f, h->variant, h->xs.as<double>(), st);
+        launch_bwd_flow(c, f, h->variant, x, st);
     }
+}
+
+// One PCG iteration, entirely on the device (scalars in cg_sc):
+//   q = A p;  alpha = (r.z) / (p.q);  x += alpha p;  r -= alpha q;
+//   z = C^{-1} r (forward and backward substitution from zero);
+//   beta = (r.z)_new / (r.z);  p = z + beta p.
+// Once the tolerance is met the scalar kernels freeze x, r and p, so extra
+// iterations change nothing.  Kernel nodes only: it can be captured.
+void cg_iteration(ilu_handle_t h, const Ctx& c, hipStream_t st) {
+    double* sc = h->cg_sc.as<double>();
+    double* part = h->partial.as<double>();
+    double *p = h->cg_p.as<double>(), *q = h->cg_q.as<double>(), *r = h->cg_r.as<double>(),
+           *z = h->cg_z.as<double>();
+    launch_residual(c, p, nullptr, q, false, 0, nullptr, st);
+    launch_dot(c, p, q, part, st);
+    launch_reduce(part, h->npartial, sc, CG_PQ, st);
+    launch_cg_scalar(sc, CG_STEP_ALPHA, 0.0, 0.0, st);
+    launch_cg_update(c, h->variant == ILU_SURR_F32, h->xs.as<double>(), p, r, q, z, h->r.p, sc, part, st);
+    launch_reduce(part, h->npartial, sc, CG_RR, st);
+    launch_cg_scalar(sc, CG_CHECK, 0.0, 0.0, st);
+    sweep_fwd(h, c, st);
+    sweep_bwd(h, c, st, z);
+    launch_dot(c, r, z, part, st);
+    launch_reduce(part, h->npartial, sc, CG_RZNEW, st);
+    launch_cg_scalar(sc, CG_STEP_BETA, 0.0, 0.0, st);
+    launch_cg_direction(c, p, z, sc, st);
+}
+
+int capture_cg(ilu_handle_t h, const Ctx& c) {
+    if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    cg_iteration(h, c, h->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
+    const hipError_t e2 = hipGraphInstantiate(&h->cg_exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        h->cg_exec = nullptr;
+        return hip_fail(e2, "hipGraphInstantiate", __LINE__);
+    }
+    return ILU_OK;
 }
 
 // Capture one sweep (residual, forward and backward substitution over every
@@ -856,11 +910,11 @@ double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
 
 namespace {
 int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
-    if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_SURR_F32) return ILU_EINVAL;
+    if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_STORED_SGS) return ILU_EINVAL;
     for (int k = 0; k < 2; ++k)
         if (opts->reserved[k]) return ILU_EINVAL;
     if ((opts->tile[0] || opts->tile[1]) && !flow_shape_supported(opts->tile[0], opts->tile[1])) return ILU_EINVAL;
-    if (opts->variant != ILU_STORED_F64) {
+    if (opts->variant == ILU_SURR_F64 || opts->variant == ILU_SURR_F32) {
         for (int k = 0; k < 3; ++k)
             if (opts->degree[k] < 0 || opts->degree[k] > 6) return ILU_EINVAL;
         if (opts->sample_stride < 0 || (opts->sample_stride & (opts->sample_stride - 1))) return ILU_EINVAL;
@@ -1054,6 +1108,133 @@ int stencil_apply(ilu_handle_t h, const double* x, double* y, void* hip_stream) 
     launch_residual(c, h->xs.as<double>(), nullptr, h->bs.as<double>(), false, 0, nullptr, st);
     launch_permute(c, 0, 1, h->bs.as<double>(), y, h->S, 1, -1, st);
     HIPCHK(hipGetLastError());
+    return ILU_OK;
+}
+
+int ilu_pcg(ilu_handle_t h, double* x, const double* b, int32_t maxit, double rel_tol, double abs_tol,
+            int32_t* iters_out, double* resnorm_out, void* hip_stream) {
+    if (!h || !x || !b || maxit < 0 || !(rel_tol >= 0.0) || !(abs_tol >= 0.0)) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Ctx c = h->ctx();
+    const size_t vb = (size_t)h->S * sizeof(double);
+    if (!h->cg_sc.p) {
+        if (h->cg_r.alloc(vb, st) || h->cg_z.alloc(vb, st) || h->cg_p.alloc(vb, st) || h->cg_q.alloc(vb, st) ||
+            h->cg_sc.alloc(CG_NSLOT * sizeof(double), st))
+            return ILU_ENOMEM;
+    }
+    double* sc = h->cg_sc.as<double>();
+    double* part = h->partial.as<double>();
+    double *r = h->cg_r.as<double>(), *z = h->cg_z.as<double>(), *p = h->cg_p.as<double>();
+    launch_permute(c, 1, 1, x, h->xs.as<double>(), h->S, 1, -1, st);
+    launch_permute(c, 1, 1, b, h->bs.as<double>(), h->S, 1, -1, st);
+    HIPCHK(hipMemsetAsync(p, 0, vb, st));
+    HIPCHK(hipMemsetAsync(h->cg_q.p, 0, vb, st));
+    launch_sumsq(c, h->bs.as<double>(), part, st);
+    launch_reduce(part, h->npartial, sc, CG_BB, st);
+    launch_cg_scalar(sc, CG_SETUP, rel_tol, abs_tol, st);
+    // r = b - A x, z = C^{-1} r, p = z
+    launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), r, false, 1, nullptr, st);
+    launch_cg_update(c, h->variant == ILU_SURR_F32, h->xs.as<double>(), p, r, h->cg_q.as<double>(), z, h->r.p, sc,
+                     part, st);
+    launch_reduce(part, h->npartial, sc, CG_RR, st);
+    sweep_fwd(h, c, st);
+    sweep_bwd(h, c, st, z);
+    launch_dot(c, r, z, part, st);
+    launch_reduce(part, h->npartial, sc, CG_RZNEW, st);
+    launch_cg_scalar(sc, CG_INIT, 0.0, 0.0, st);
+    launch_cg_direction(c, p, z, sc, st);
+    HIPCHK(hipGetLastError());
+    const bool graph = h->use_graph && !h->kernel_timing && maxit > 0;
+    if (graph && !h->cg_exec)
+        if (int e = capture_cg(h, c)) return e;
+    // the host looks at the device state after every CHK iterations
+    constexpr int CHK = 8;
+    double state[CG_NSLOT];
+    int issued = 0;
+    for (;;) {
+        HIPCHK(hipMemcpyAsync(state, sc, sizeof(state), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (state[CG_DONE] != 0.0 || issued >= maxit) break;
+        const int m = std::min(CHK, maxit - issued);
+        for (int j = 0; j < m; ++j) {
+            if (graph) HIPCHK(hipGraphLaunch(h->cg_exec, st));
+            else cg_iteration(h, c, st);
+        }
+        HIPCHK(hipGetLastError());
+        issued += m;
+    }
+    if (iters_out) *iters_out = (int32_t)state[CG_ITERS];
+    if (resnorm_out) {
+        // true residual of the returned iterate (q is free here)
+        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->cg_q.as<double>(), false, 1, part, st);
+        launch_reduce(part, h->npartial, h->norms.as<double>(), 1, st);
+        int err = 0;
+        *resnorm_out = std::sqrt(host_norm(h, 1, st, &err));
+        if (err) return ILU_EHIP;
+    }
+    launch_permute(c, 0, 1, h->xs.as<double>(), x, h->S, 1, -1, st);
+    HIPCHK(hipGetLastError());
+    int32_t fl[4];
+    if (int e = read_flags(h, st, fl)) return e;
+    if (h->schedule != ILU_SCHED_PLANE && fl[2]) return ILU_EHIP;  // a dataflow wait exceeded its bound
+    if (state[CG_BREAK] != 0.0) return ILU_EBREAKDOWN;
+    if (state[CG_DONE] == 0.0) return ILU_ENOTCONV;
+    return ILU_OK;
+}
+
+int ilu_contraction(ilu_handle_t h, double* x, int32_t nsteps, double* rho_out, double* rho_res_out,
+                    void* hip_stream) {
+    if (!h || !x || nsteps < 1 || !rho_out) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Ctx c = h->ctx();
+    const bool f32 = h->variant == ILU_SURR_F32;
+    double* nr = h->norms.as<double>();
+    double* part = h->partial.as<double>();
+    double* xs = h->xs.as<double>();
+    launch_permute(c, 1, 1, x, xs, h->S, 1, -1, st);
+    HIPCHK(hipMemsetAsync(h->bs.p, 0, h->bs.bytes, st));  // b = 0: a step maps e to (I - C^{-1} A) e
+    launch_sumsq(c, xs, part, st);
+    launch_reduce(part, h->npartial, nr, 3, st);
+    int err = 0;
+    const double n0 = host_norm(h, 3, st, &err);
+    if (err) return ILU_EHIP;
+    if (!(n0 > 0.0) || !std::isfinite(n0)) return ILU_EINVAL;
+    launch_scale_rsqrt(c, xs, nr, 3, st);
+    double rho = 0.0, logsum = 0.0, ra0 = 0.0;
+    int k = 0;
+    for (; k < nsteps; ++k) {
+        // ||A y||^2 of the normalised iterate comes with the step's residual
+        launch_residual(c, xs, h->bs.as<double>(), h->r.p, f32, 1, part, st);
+        launch_reduce(part, h->npartial, nr, 4, st);
+        sweep_fwd(h, c, st);
+        sweep_bwd(h, c, st);
+        launch_sumsq(c, xs, part, st);
+        launch_reduce(part, h->npartial, nr, 3, st);
+        launch_scale_rsqrt(c, xs, nr, 3, st);
+        double v[2];
+        HIPCHK(hipMemcpyAsync(v, nr + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (k == 0) ra0 = std::sqrt(v[1]);
+        rho = std::sqrt(v[0]);
+        if (!(rho > 0.0)) break;  // the step removed the error completely
+        logsum += std::log(rho);
+    }
+    double rho_res = 0.0;
+    if (rho > 0.0 && ra0 > 0.0) {
+        // ||A x_K|| / ||A x_0|| = (||A y_K|| / ||A y_0||) prod rho_k
+        launch_residual(c, xs, h->bs.as<double>(), h->r.p, f32, 1, part, st);
+        launch_reduce(part, h->npartial, nr, 4, st);
+        const double raK = std::sqrt(host_norm(h, 4, st, &err));
+        if (err) return ILU_EHIP;
+        rho_res = raK > 0.0 ? std::exp((std::log(raK / ra0) + logsum) / nsteps) : 0.0;
+    }
+    *rho_out = rho;
+    if (rho_res_out) *rho_res_out = rho_res;
+    launch_permute(c, 0, 1, xs, x, h->S, 1, -1, st);
+    HIPCHK(hipGetLastError());
+    int32_t fl[4];
+    if (int e = read_flags(h, st, fl)) return e;
+    if (h->schedule != ILU_SCHED_PLANE && fl[2]) return ILU_EHIP;
     return ILU_OK;
 }
 

@@ -31,6 +31,25 @@ __device__ __forceinline__ void decode_group(int groups, int& b, int& lane) {
     lane = (int)(blockIdx.x % groups) * WAVE + (int)(threadIdx.x & (WAVE - 1));
 }
 
+// Point-parallel work items of the residual, norm and vector kernels: workgroup
+// (x, y) runs lanes [64 (x % groups), +64) of block x / groups over the y-th
+// chunk of RES_T hyperplanes, so the grid sweeps one band of hyperplanes of
+// every block at a time.  (Remapping the items so that each XCD gets a
+// contiguous range of blocks measured 10-20% slower.)
+struct Item {
+    int blk, chunk, lane;
+    int64_t id;
+    bool live;
+};
+__device__ __forceinline__ Item res_item(int groups, int nblocks) {
+    Item it;
+    decode_group(groups, it.blk, it.lane);
+    it.chunk = (int)blockIdx.y;
+    it.live = it.blk < nblocks;
+    it.id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    return it;
+}
+
 __device__ __forceinline__ bool interior(int n, int x, int y, int z) {
     return x >= 1 && y >= 1 && z >= 1 && x + y + z <= n - 1;
 }

@@ -10,25 +10,6 @@ namespace ilu {
 
 // ---------------------------------------------------------------- residual
 
-// Point-parallel work items of the residual and norm kernels: workgroup
-// (x, y) runs lanes [64 (x % groups), +64) of block x / groups over the y-th
-// chunk of RES_T hyperplanes, so the grid sweeps one band of hyperplanes of
-// every block at a time.  (Remapping the items so that each XCD gets a
-// contiguous range of blocks measured 10-20% slower.)
-struct Item {
-    int blk, chunk, lane;
-    int64_t id;
-    bool live;
-};
-__device__ __forceinline__ Item res_item(int groups, int nblocks) {
-    Item it;
-    decode_group(groups, it.blk, it.lane);
-    it.chunk = (int)blockIdx.y;
-    it.live = it.blk < nblocks;
-    it.id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    return it;
-}
-
 template <typename RT, bool SUB>
 __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                                   const LaneDev* __restrict__ lanes, int lpb, int groups, int nblocks,

@@ -395,3 +395,130 @@ def test_fit_is_basis_independent_and_error_falls_with_degree():
         errs.append(rel.mean())
     # higher degree, smaller overall error (Sec. 4.2, discrete L2 error study)
     assert errs[-1] < errs[0]
+
+
+def test_surrogate_error_counts_only_interior_neighbours():
+    # a known perturbation on the points whose neighbour p + d is interior gives
+    # the closed-form error; perturbing the other points changes nothing
+    t, P = _jittered(4, *W.KAPPA_SIN)
+    L, U, D = P.ilu0()
+    inner = P.col[:, :7] >= 0
+    eps = 1e-3
+    Lw = L + eps * inner + 7.0 * ~inner
+    Dinv = 1.0 / D * (1 + eps)
+    rel, mx = O.surrogate_error(4, L, D, Lw, Dinv)
+    for d in range(7):
+        m = inner[:, d]
+        assert rel[d] == pytest.approx(eps * np.sqrt(m.sum()) / np.linalg.norm(L[m, d]), rel=1e-12)
+        assert mx[d] == pytest.approx(eps, rel=1e-9)
+    assert rel[7] == pytest.approx(eps, rel=1e-12)
+
+
+# ---------------------------------------------------------------- contraction
+
+
+def _dense_lower(P, L):
+    Lm, _ = _factor_matrices(P, L, np.ones(P.N))
+    return Lm.toarray()
+
+
+def test_contraction_factor_is_spectral_radius_of_ilu_smoother():
+    # power iteration on I - C^{-1} A with C = L D L^T from ILU(0) converges to
+    # its spectral radius, computed here by a dense eigen-solver
+    t, P = _jittered(3, *W.KAPPA_SIN, seed=7)
+    L, U, D = P.ilu0()
+    Lm = _dense_lower(P, L)
+    C = Lm @ np.diag(D) @ Lm.T
+    E = np.eye(P.N) - np.linalg.solve(C, P.csr().toarray())
+    radius = np.abs(np.linalg.eigvals(E)).max()
+    zero = np.zeros(P.N)
+    x0 = W.SplitMix64(11).uniform_array(P.N, -1.0, 1.0)
+    rho, rho_res = O.contraction_factor(P, lambda y: P.smooth_stencil(L, 1.0 / D, zero, y, 1)[0], x0, 100)
+    assert rho == pytest.approx(radius, rel=1e-10)
+    assert 0.9 * radius < rho_res <= radius * (1 + 1e-9)
+    assert 0.0 < radius < 0.2
+
+
+def test_contraction_factor_of_damped_jacobi_and_exact_solve():
+    t, P = _jittered(3, *W.KAPPA_SIN, seed=7)
+    A = P.csr().toarray()
+    zero = np.zeros(P.N)
+    x0 = W.SplitMix64(11).uniform_array(P.N, -1.0, 1.0)
+    # L = 0: the sweep is a Jacobi step; halve it for a unique dominant eigenvalue
+    dinv = 1.0 / P.A[:, 7]
+    jac = lambda y: y + 0.5 * (P.smooth_stencil(np.zeros((P.N, 7)), dinv, zero, y, 1)[0] - y)
+    radius = np.abs(np.linalg.eigvals(np.eye(P.N) - 0.5 * dinv[:, None] * A)).max()
+    rho, _ = O.contraction_factor(P, jac, x0, 200)
+    assert rho == pytest.approx(radius, rel=1e-8)
+    # an exact solve removes the error in one step
+    rho, _ = O.contraction_factor(P, lambda y: y - np.linalg.solve(A, A @ y), x0, 1)
+    assert rho < 1e-13
+
+
+# ---------------------------------------------------------- PCG and the SGS comparator
+
+
+def test_sgs_factors_define_symmetric_gauss_seidel():
+    # L D L^T built from the stencil factors equals (D_A + L_A) D_A^-1 (D_A + L_A)^T
+    # built from the assembled matrix (Sec. 2.1)
+    t, P = _jittered(4, *W.KAPPA_EXP)
+    L, D = P.sgs_factors()
+    Lm, Dm = _factor_matrices(P, L, D)
+    C = (Lm @ Dm @ Lm.T).toarray()
+    A = P.csr().toarray()
+    DL = np.tril(A)
+    C2 = DL @ np.diag(1.0 / np.diag(A)) @ DL.T
+    np.testing.assert_allclose(C, C2, rtol=0, atol=1e-13 * np.abs(A).max())
+
+
+@pytest.mark.parametrize("which", ["ilu", "sgs", "ilu_f32"])
+def test_pcg_matches_scipy_cg(which):
+    # same preconditioner handed to scipy's CG: equal iteration counts and iterates
+    import scipy.sparse.linalg as sla
+    t, P = _jittered(4, *W.KAPPA_SIN, seed=7)
+    if which == "sgs":
+        L, D = P.sgs_factors()
+    else:
+        L, U, D = P.ilu0()
+    M = P.precond(L, 1.0 / D, f32=which == "ilu_f32")
+    b = t.rhs()
+    x, k, hist, ok = O.pcg(P, M, b, maxit=300, rel_tol=1e-10)
+    assert ok and hist[-1] <= 1e-10 * np.linalg.norm(b) < hist[-2]
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+    A = P.csr()
+    xs, info = sla.cg(A, b, rtol=1e-10, atol=0.0, maxiter=300, M=sla.LinearOperator(A.shape, matvec=M), callback=cb)
+    assert info == 0 and count[0] == k
+    np.testing.assert_allclose(x, xs, rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def test_pcg_special_cases():
+    t, P = _jittered(3, *W.KAPPA_SIN, seed=7)
+    A = P.csr().toarray()
+    b = t.rhs()
+    # the exact inverse as preconditioner: one iteration
+    x, k, _, ok = O.pcg(P, lambda r: np.linalg.solve(A, r), b, maxit=5, rel_tol=1e-12)
+    assert ok and k == 1
+    np.testing.assert_allclose(A @ x, b, atol=1e-12)
+    # plain CG on N unknowns terminates after at most N steps (exact arithmetic; a
+    # few more with rounding)
+    x, k, _, ok = O.pcg(P, lambda r: r.copy(), b, maxit=10 * P.N, rel_tol=1e-10)
+    assert ok and k <= P.N + 3
+    # b = 0 from x = 0: nothing to do
+    x, k, _, ok = O.pcg(P, lambda r: r.copy(), np.zeros(P.N), maxit=5, rel_tol=1e-10)
+    assert ok and k == 0 and not x.any()
+
+
+def test_ilu_preconditioner_beats_sgs_and_plain_cg():
+    # the ordering reported with the CG experiment of Sec. 4.3: the ILU
+    # preconditioner needs fewer CG iterations than symmetric Gauss-Seidel
+    t, P = _jittered(5, *W.KAPPA_SIN, seed=7)
+    b = t.rhs()
+    L, U, D = P.ilu0()
+    Ls, Ds = P.sgs_factors()
+    k_ilu = O.pcg(P, P.precond(L, 1.0 / D), b, maxit=500, rel_tol=1e-8)[1]
+    k_sgs = O.pcg(P, P.precond(Ls, 1.0 / Ds), b, maxit=500, rel_tol=1e-8)[1]
+    k_cg = O.pcg(P, lambda r: r.copy(), b, maxit=500, rel_tol=1e-8)[1]
+    assert k_ilu < k_sgs < k_cg
