@@ -12,14 +12,15 @@
 // own rows plus one halo column and one halo row holding rows of the
 // neighbouring blocks.
 //
-// Blocks hand boundary values to each other through an exchange buffer.  Two
-// extra waves in every workgroup do all of this traffic, so the compute waves
+// Blocks hand boundary values to each other through an exchange buffer.
+// Extra waves in every workgroup do all of this traffic, so the compute waves
 // never wait on another block's memory.  After every hyperplane the outgoing
 // wave copies the block's edge values (last column and last row in sweep
 // direction) from LDS to the buffer, each with a 32-bit launch tag in one
-// 64-bit word (FP64 values: two words, one per half).  The incoming wave loads
-// the entries it needs D hyperplanes ahead and checks the tag right before the
-// value goes into the LDS grid; only a stale entry is polled again.  No block
+// 64-bit word (FP64 values: two words, one per half).  D incoming waves take
+// turns by hyperplane: each loads the entries of its next hyperplane D ahead
+// and checks the tag right before the value goes into the LDS grid; only a
+// stale entry is polled again.  No block
 // ever waits for its own stores, and no progress counter sits between
 // producer and consumer.  The tag is a device counter that the reset kernel advances
 // before every sweep, so graph replays never see entries of earlier sweeps
@@ -157,7 +158,7 @@ __device__ __forceinline__ T halo_take(const Halo& h, const uint64_t* xch, int n
 
 // ------------------------------------------------------------------ forward
 //
-// Workgroup = BV*BW compute threads (one per row) + an incoming wave + an
+// Workgroup = BV*BW compute threads (one per row) + D incoming waves + an
 // outgoing wave.  Incoming lane i < BW+BV+1 owns halo row i (column, row,
 // corner); outgoing lane i < BW+BV owns exchange entry i, whose producer lane
 // is the one xch_out_lane names.  Loads and stores live in different waves
@@ -166,7 +167,7 @@ __device__ __forceinline__ T halo_take(const Halo& h, const uint64_t* xch, int n
 // issued before it.  All paths pass the same barriers.
 
 template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
-__global__ void __launch_bounds__(BV* BW + 2 * WAVE)
+__global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
     k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lf, const T* __restrict__ tab,
                const T* __restrict__ r, T* __restrict__ w, const int32_t* __restrict__ order,
@@ -190,12 +191,12 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
         const int b = order[k];
         const BlockDev B = blocks[b];
         const int tb = B.tb, te = B.te;
-        for (int i = l; i < 4 * GC; i += NT + 2 * WAVE) grid[i] = (T)0;
-        if (l >= NT + WAVE) {
+        for (int i = l; i < 4 * GC; i += NT + (D + 1) * WAVE) grid[i] = (T)0;
+        if (l >= NT + D * WAVE) {
             // ---------------- outgoing wave: copies the block's edge values of
             // hyperplane t-1 (published by the last barrier) to the exchange
             // buffer.  It only stores, so it never waits on memory in the loop.
-            const int hlane = l - NT - WAVE;
+            const int hlane = l - NT - D * WAVE;
             const bool out = hlane < NX;
             int ovl = 0, owl = 0;
             if (out) xch_out_lane(0, hlane, BV, BW, &ovl, &owl);
@@ -209,8 +210,11 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
             }
             if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, te, hlane), grid[(te & 3) * GC + ocell], tag);
         } else if (l >= NT) {
-            // ---------------- incoming wave: loads and checks only
-            const int hlane = l - NT;
+            // ---------------- incoming waves: loads and checks only.  Wave iw serves
+            // the hyperplanes t with (t - tb) % D == iw and loads the entry of its next
+            // one (t + D) right after taking t, so each wave has one load in flight and
+            // a wait for it never waits for another hyperplane's load.
+            const int hlane = (l - NT) % WAVE, iw = (l - NT) / WAVE;
             Halo hin;
             int kk = 0, j = 0;
             if (xch_halo_role(0, hlane, BV, BW, &kk, &j)) {
@@ -227,15 +231,16 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
                 }
             }
             __syncthreads();
-            XEnt<T> hx[D];
+            XEnt<T> hx;
             if (hin.role) {
-                for (int s = tb - 3; s < tb; ++s) {
-                    XEnt<T> e;
-                    halo_issue(hin, xch, NX, s, e);
-                    grid[(s & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, s, e, tag, flags);
+                if (iw == 0) {
+                    for (int s = tb - 3; s < tb; ++s) {
+                        XEnt<T> e;
+                        halo_issue(hin, xch, NX, s, e);
+                        grid[(s & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, s, e, tag, flags);
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < D; ++q) halo_issue(hin, xch, NX, tb + q, hx[q]);
+                halo_issue(hin, xch, NX, tb + iw, hx);
             }
             __syncthreads();
             for (int T0 = tb; T0 <= te; T0 += D) {
@@ -243,9 +248,9 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
                 for (int q = 0; q < D; ++q) {
                     const int t = T0 + q;
                     if (t > te) break;
-                    if (hin.role) {
-                        grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx[q], tag, flags);
-                        halo_issue(hin, xch, NX, t + D, hx[q]);
+                    if (hin.role && q == iw) {
+                        grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx, tag, flags);
+                        halo_issue(hin, xch, NX, t + D, hx);
                     }
                     lds_barrier();
                 }
@@ -340,7 +345,7 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
 // ----------------------------------------------------------------- backward
 
 template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
-__global__ void __launch_bounds__(BV* BW + 2 * WAVE)
+__global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
     k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lb, const T* __restrict__ tab,
                const T* __restrict__ w, double* __restrict__ xs, const int32_t* __restrict__ order,
@@ -364,10 +369,10 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
         const int b = order[k];
         const BlockDev B = blocks[b];
         const int tb = B.tb, te = B.te;
-        for (int i = l; i < 4 * GC; i += NT + 2 * WAVE) grid[i] = (T)0;
-        if (l >= NT + WAVE) {
+        for (int i = l; i < 4 * GC; i += NT + (D + 1) * WAVE) grid[i] = (T)0;
+        if (l >= NT + D * WAVE) {
             // ---------------- outgoing wave (edge values of hyperplane t+1)
-            const int hlane = l - NT - WAVE;
+            const int hlane = l - NT - D * WAVE;
             const bool out = hlane < NX;
             int ovl = 0, owl = 0;
             if (out) xch_out_lane(1, hlane, BV, BW, &ovl, &owl);
@@ -381,8 +386,9 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
             }
             if (out) x_put(xch + xch_word(B.xoff, B.tlo, NX, XW, tb, hlane), grid[(tb & 3) * GC + ocell], tag);
         } else if (l >= NT) {
-            // ---------------- incoming wave (halo at column BV and row BW of the grid)
-            const int hlane = l - NT;
+            // ---------------- incoming waves (halo at column BV and row BW of the grid);
+            // wave iw serves the hyperplanes t with (te - t) % D == iw
+            const int hlane = (l - NT) % WAVE, iw = (l - NT) / WAVE;
             Halo hin;
             int kk = 0, j = 0;
             if (xch_halo_role(1, hlane, BV, BW, &kk, &j)) {
@@ -399,15 +405,16 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
                 }
             }
             __syncthreads();
-            XEnt<T> hx[D];
+            XEnt<T> hx;
             if (hin.role) {
-                for (int s = te + 3; s > te; --s) {
-                    XEnt<T> e;
-                    halo_issue(hin, xch, NX, s, e);
-                    grid[(s & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, s, e, tag, flags);
+                if (iw == 0) {
+                    for (int s = te + 3; s > te; --s) {
+                        XEnt<T> e;
+                        halo_issue(hin, xch, NX, s, e);
+                        grid[(s & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, s, e, tag, flags);
+                    }
                 }
-#pragma unroll
-                for (int q = 0; q < D; ++q) halo_issue(hin, xch, NX, te - q, hx[q]);
+                halo_issue(hin, xch, NX, te - iw, hx);
             }
             __syncthreads();
             for (int T0 = te; T0 >= tb; T0 -= D) {
@@ -415,9 +422,9 @@ __global__ void __launch_bounds__(BV* BW + 2 * WAVE)
                 for (int q = 0; q < D; ++q) {
                     const int t = T0 - q;
                     if (t < tb) break;
-                    if (hin.role) {
-                        grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx[q], tag, flags);
-                        halo_issue(hin, xch, NX, t - D, hx[q]);
+                    if (hin.role && q == iw) {
+                        grid[(t & 3) * GC + hin.cell] = halo_take<T>(hin, xch, NX, t, hx, tag, flags);
+                        halo_issue(hin, xch, NX, t - D, hx);
                     }
                     lds_barrier();
                 }
@@ -525,16 +532,23 @@ __global__ void k_flow_reset(int32_t* __restrict__ ticket) {
 namespace {
 
 // Batch depth U (operands of the next U hyperplanes are loaded while the
-// current U run) and halo distance D.  Both batches of loads must fit the
-// 63-entry vector memory counter: stored factors load 8 (forward) or 10
-// (backward) values per hyperplane.  D = 1 (the entry of hyperplane t+1 is
-// loaded during hyperplane t) measured fastest: every extra hyperplane of
-// halo lead adds a hyperplane of lag per block hop on the critical path, which
-// costs more than the load latency it hides (D = 1, 2, 4, 8 at level 9:
-// forward sweep 0.64, 0.66, 0.69, 0.81 ms with 16 x 32 blocks).
-constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 1;  // stored factors
-constexpr int U_S64 = 4, D_S64 = 1;              // FP64 surrogate
-constexpr int U_F32 = 8, D_F32 = 1;              // FP32 surrogate
+// current U run) and halo lead D = number of incoming waves.  Both batches of
+// loads must fit the 63-entry vector memory counter: stored factors load 8
+// (forward) or 10 (backward) values per hyperplane.
+//
+// With one incoming wave the entry of hyperplane t+1 is loaded during
+// hyperplane t and every hyperplane waits one exchange round trip (a
+// device-coherent load, ~0.45 us): the stale-entry poll loop makes the
+// compiler wait for all of a wave's outstanding loads, so a deeper lead in one
+// wave hid nothing.  D waves with one load in flight each hide the round trip
+// over D hyperplanes.  Level 9, FP32 surrogate, 16 x 16 blocks: forward /
+// backward 0.674 / 0.687 ms with D = 1, 0.487 / 0.555 with D = 2, 0.507 /
+// 0.563 with D = 3 (D = 3 is slower on the small tetrahedra of a batch).
+// Making a block wait until its producers are several hyperplanes ahead
+// before it starts only added lag per block hop, at every D tried.
+constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 2;  // stored factors
+constexpr int U_S64 = 4, D_S64 = 2;              // FP64 surrogate
+constexpr int U_F32 = 8, D_F32 = 2;              // FP32 surrogate
 
 template <int BV, int BW>
 struct Shape {
@@ -552,34 +566,34 @@ struct Shape {
         return (const void*)k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW>;
     }
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
-        k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
+        k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, (const double*)c.r, (double*)c.w, f.order_fwd,
             f.xch, f.ticket, f.flags);
     }
     static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
-        k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
+        k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, (const double*)c.w, x, f.order_bwd, f.xch,
             f.ticket, f.flags);
     }
     template <int NC>
     static void fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
+            k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.r, (double*)c.w,
                 f.order_fwd, f.xch, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
+            k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.r, (float*)c.w,
                 f.order_fwd, f.xch, f.ticket, f.flags);
     }
     template <int NC>
     static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
         if (variant == 1)
-            k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
+            k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.w, x, f.order_bwd,
                 f.xch, f.ticket, f.flags);
         else
-            k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + 2 * WAVE, 0, st>>>(
+            k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.w, x, f.order_bwd,
                 f.xch, f.ticket, f.flags);
     }
@@ -609,9 +623,10 @@ int resident(int variant, int NC) {
         ILU_NC_SWITCH(NC, ILU_PTRS)
 #undef ILU_PTRS
     }
+    const int nthreads = BV * BW + (1 + (variant == 0 ? D_F64 : variant == 1 ? D_S64 : D_F32)) * WAVE;
     int a = 0, b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, BV * BW + 2 * WAVE, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, BV * BW + 2 * WAVE, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, nthreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, nthreads, 0) != hipSuccess)
         return 1;
     return a < b ? a : b;
 }
