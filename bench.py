@@ -43,8 +43,9 @@ def kernel_bytes(variant: str):
     return {"residual": res, "forward": fwd, "backward": bwd}
 
 
-def kernel_flops(variant: str, dg: int):
+def kernel_flops(variant: str, dg):
     res = 30                                  # 15 multiply-adds
+    dg = dg if isinstance(dg, int) else dg[0]  # Horner runs over x only
     if variant in ("stored_f64", "stored_sgs"):
         return {"residual": res, "forward": 14, "backward": 16}
     # Horner: dg multiply-adds per direction (7 forward, 8 backward) plus the sweep
@@ -288,6 +289,7 @@ def main():
                     help="instead of fixed sweeps: time CG preconditioned by each variant to this relative residual")
     ap.add_argument("--pcg-abs-tol", type=float, default=0.0, help="absolute residual target of --pcg-tol mode")
     ap.add_argument("--max-iters", type=int, default=5000)
+    ap.add_argument("--degree", default="", help="surrogate degrees dx,dy,dz instead of the workload's")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -298,6 +300,10 @@ def main():
     import workloads as W
     pkg.lib()
     wl = W.workload(a.workload)
+    if a.degree:
+        import dataclasses
+        dg = tuple(int(c) for c in a.degree.split(","))
+        wl = dataclasses.replace(wl, degree=dg[0] if len(dg) == 1 else dg)
     variants = a.variants.split(",")
     tile = (0, 0) if a.tile == "auto" else tuple(int(c) for c in a.tile.split("x"))
     if a.to_tol > 0:

@@ -20,6 +20,8 @@ Functions and the passage they follow:
                                the smoother's error propagation I - C^{-1} A
   Problem.sgs_factors          Sec. 2.1 symmetric Gauss-Seidel preconditioner in L D L^T form
   pcg                          Sec. 4.3 CG experiment: CG preconditioned by C^{-1}
+  lfa_orientation              Sec. 3 (strategy on macro-elements): LFA smoothing factor of
+                               the asymptotic ILU stencil for each vertex permutation
 """
 from __future__ import annotations
 
@@ -458,3 +460,66 @@ def contraction_factor(problem: "Problem", step, x0, steps: int = 20):
         y = z / nz
         ra = rz / nz
     return rho, float(np.exp(logsum / steps))
+
+
+# ------------------------------------------------------------------ LFA
+
+def constant_stencil(verts) -> np.ndarray:
+    """The 15 stencil weights A_d (listing order of D) for kappa = 1 at an
+    interior point whose neighbours are all interior (level 4, point (4,4,4)):
+    with an affine macro map and a constant coefficient every such point has
+    the same stencil (Sec. 3, strategy on macro-elements)."""
+    class _T:
+        pass
+    t = _T()
+    t.verts, t.level, t.coeff_kind, t.coeff_params = verts, 4, 0, (1.0, 0.0, 0.0, 0.0)
+    return stencil_at(t, [[4, 4, 4]])[0]
+
+
+def lfa_frequencies(samples: int = 16) -> np.ndarray:
+    """Theta_osc = (-pi, pi)^3 minus (-pi/2, pi/2)^3 sampled on a uniform grid
+    of `samples` cell centres per direction (reading of the sampling rule):
+    theta_j = -pi + (2 j + 1) pi / samples, kept if some |theta_i| >= pi/2."""
+    th = -np.pi + (2 * np.arange(samples) + 1) * np.pi / samples
+    T = np.stack(np.meshgrid(th, th, th, indexing="ij"), -1).reshape(-1, 3)
+    return T[np.abs(T).max(axis=1) >= np.pi / 2]
+
+
+def smoothing_factor(A, L, D, thetas) -> float:
+    """mu = max over thetas of |(L D conj(L) - A) / (L D conj(L))| with the
+    symbols L(theta) = 1 + sum_{d in D_l} L_d e^{i d.theta}, D(theta) = D and
+    A(theta) = sum_{d in D} A_d e^{i d.theta} (Sec. 3)."""
+    Ls = 1.0 + sum(L[d] * np.exp(1j * (thetas @ DIRS[d])) for d in range(NLOW))
+    As = sum(A[d] * np.exp(1j * (thetas @ DIRS[d])) for d in range(15))
+    C = Ls * D * np.conj(Ls)
+    return float(np.abs((C - As) / C).max())
+
+
+def permutations():
+    """The 24 vertex permutations s = (s1 s2 s3 s4) in lexicographic order."""
+    import itertools
+    return [tuple(p) for p in itertools.permutations((1, 2, 3, 4))]
+
+
+def permute_vertices(verts, s):
+    """Reading of the permutation notation: original vertex i becomes vertex
+    s_i of the permuted tetrahedron."""
+    v = np.asarray(verts, dtype=np.float64).reshape(4, 3)
+    out = np.empty_like(v)
+    for i, si in enumerate(s):
+        out[si - 1] = v[i]
+    return out
+
+
+def lfa_orientation(verts, samples: int = 16):
+    """Smoothing factor mu of the asymptotic ILU stencil (LFA) for each of the
+    24 vertex permutations of one macro-tetrahedron, and the index of the
+    smallest (Sec. 3, strategy on macro-elements).  Returns (mu (24,), best)."""
+    th = lfa_frequencies(samples)
+    mu = []
+    for s in permutations():
+        A = constant_stencil(permute_vertices(verts, s))
+        L, D = asymptotic_stencil(A)
+        mu.append(smoothing_factor(A, L, D, th))
+    mu = np.array(mu)
+    return mu, int(np.argmin(mu))

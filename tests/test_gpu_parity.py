@@ -187,6 +187,38 @@ def test_surrogate_f32_mixed_parity(torch, pkg, sched):
     assert rel == pytest.approx(rr[-1], rel=1e-3)
 
 
+@pytest.mark.parametrize("deg", [(0, 0, 4), (1, 2, 4), (3, 1, 0)])
+def test_anisotropic_degree_parity(torch, pkg, deg):
+    # anisotropic tensor degrees (dg_x, dg_y, dg_z): the GPU fit against the
+    # oracle's (1e-7, the basis conditioning), then FP64 and FP32 sweeps with
+    # the oracle's coefficients (1e-11 and 2e-5, as for isotropic degrees)
+    level = 6
+    t = W.make_tet(16, level, *W.KAPPA_EXP, jitter=0.15)
+    P = O.Problem.from_tet(t)
+    L, U, D = P.ilu0()
+    s_eff = O.effective_stride(level, deg, 4)
+    c = O.fit_surrogate(level, L, D, deg, s_eff)
+    Lo, Do = O.eval_surrogate(level, c, deg)
+    sm = pkg.Smoother([t], pkg.SURR_F64, degree=deg, stride=4, tile=(8, 8))
+    assert sm.sample_stride(0) == s_eff
+    Lg, Dg = sm.surrogate_values(0)
+    assert _rel(Lg.cpu().numpy(), Lo) < 1e-7
+    assert _rel(Dg.cpu().numpy(), Do) < 1e-7
+    sm.set_surrogate(0, c)
+    b = t.rhs()
+    bd = torch.tensor(b, device="cuda")
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    sm.smooth(x, bd, 6)
+    want, _ = P.smooth_stencil(Lo, Do, b, nsweeps=6)
+    assert _rel(x.cpu().numpy(), want) < 1e-11
+    sm32 = pkg.Smoother([t], pkg.SURR_F32, degree=deg, stride=4, tile=(16, 16))
+    sm32.set_surrogate(0, c)
+    x.zero_()
+    sm32.smooth(x, bd, 8)
+    want32, _ = P.smooth_stencil_f32(Lo.astype(np.float32), Do.astype(np.float32), b, nsweeps=8)
+    assert _rel(x.cpu().numpy(), want32) < 2e-5
+
+
 def test_iterative_refinement_reaches_tolerance(torch, pkg):
     t = W.make_tet(4, 4, *W.KAPPA_SIN, jitter=0.15)
     P = O.Problem.from_tet(t)

@@ -355,6 +355,39 @@ def test_unisolvence_rule_matches_rank(level, stride, deg):
     assert O.effective_stride(7, 4, 4) == 4
 
 
+@pytest.mark.parametrize("deg", [(0, 0, 4), (1, 2, 4), (3, 1, 0), (0, 2, 0)])
+@pytest.mark.parametrize("level,stride", [(4, 1), (5, 2), (5, 4), (6, 4)])
+def test_unisolvence_rule_matches_rank_anisotropic(level, stride, deg):
+    # tensor degrees (dg_x, dg_y, dg_z): a lattice simplex of side M is
+    # unisolvent exactly when M >= dg_x + dg_y + dg_z (checked by rank)
+    pts = O.interior_points(level).astype(float) / (1 << level)
+    for t in list(range(7)) + [7]:
+        idx = O.sample_set(level, t, stride)
+        if len(idx) == 0:
+            continue
+        V = O.legendre_tensor_matrix(pts[idx], deg)
+        full = np.linalg.matrix_rank(V) == V.shape[1]
+        assert full == (O.sample_side(level, O.DIRS[t], stride) >= sum(deg))
+
+
+def test_anisotropic_tensor_polynomials_are_recovered_exactly():
+    # samples of a polynomial in P_{1,2,4} (monomials x^i y^j z^k, i <= 1, j <= 2,
+    # k <= 4) are reproduced by the fit, and the fit of a lower tensor space
+    # (0, 0, 4) cannot reproduce its x-dependence
+    level, s = 6, 2
+    pts = O.interior_points(level).astype(float) / (1 << level)
+    x, y, z = pts.T
+    f = 0.3 + x * (1 - y) ** 2 * z ** 4 - 2.0 * y * z ** 3 + 0.5 * x * y
+    L = np.tile(f[:, None], (1, 7))
+    D = 1.0 / (1.0 + f ** 2)
+    c = O.fit_surrogate(level, L, D, (1, 2, 4), s)
+    Lw, Dinv = O.eval_surrogate(level, c, (1, 2, 4))
+    np.testing.assert_allclose(Lw[:, 0], f, atol=1e-11)
+    c0 = O.fit_surrogate(level, L, D, (0, 0, 4), s)
+    Lw0, _ = O.eval_surrogate(level, c0, (0, 0, 4))
+    assert np.abs(Lw0[:, 0] - f).max() > 1e-2
+
+
 def test_polynomial_samples_are_recovered_exactly():
     level, deg, s = 6, 3, 2
     pts = O.interior_points(level).astype(float) / (1 << level)
@@ -522,3 +555,75 @@ def test_ilu_preconditioner_beats_sgs_and_plain_cg():
     k_sgs = O.pcg(P, P.precond(Ls, 1.0 / Ds), b, maxit=500, rel_tol=1e-8)[1]
     k_cg = O.pcg(P, lambda r: r.copy(), b, maxit=500, rel_tol=1e-8)[1]
     assert k_ilu < k_sgs < k_cg
+
+
+# ------------------------------------------------------------------ LFA (Sec. 3)
+
+
+def _stencil_product(L, D):
+    """Offsets and values of L D L^T for constant stencils (L_c = 1)."""
+    low = [tuple(O.DIRS[d]) for d in range(7)] + [(0, 0, 0)]
+    val = list(L) + [1.0]
+    out = {}
+    for a, la in zip(low, val):
+        for b, lb in zip(low, val):
+            off = tuple(np.subtract(a, b))
+            out[off] = out.get(off, 0.0) + la * D * lb
+    return out
+
+
+def test_asymptotic_stencil_reproduces_A_on_the_pattern():
+    # the fixed point of the stencil equations: (L D L^T)_d = A_d on the 15
+    # pattern offsets, plus exactly 12 fill-in offsets (Sec. 3)
+    t = W.make_tet(21, 4, W.COEFF_CONST, (1.0,), jitter=0.15)
+    A = O.constant_stencil(t.verts)
+    L, D = O.asymptotic_stencil(A)
+    prod = _stencil_product(L, D)
+    for d in range(15):
+        assert prod.pop(tuple(O.DIRS[d])) == pytest.approx(A[d], abs=1e-12 * np.abs(A).max())
+    assert len([v for v in prod.values() if abs(v) > 1e-14]) == 12
+    # so the LFA error symbol D |L|^2 - A is the symbol of the fill-in alone
+    th = np.random.default_rng(3).uniform(-np.pi, np.pi, (50, 3))
+    Ls = 1 + sum(L[d] * np.exp(1j * th @ O.DIRS[d]) for d in range(7))
+    As = sum(A[d] * np.exp(1j * th @ O.DIRS[d]) for d in range(15))
+    fill = sum(v * np.exp(1j * th @ np.array(off)) for off, v in prod.items())
+    np.testing.assert_allclose(D * np.abs(Ls) ** 2 - As, fill, atol=1e-12 * np.abs(A).max())
+
+
+def test_smoothing_factor_is_invariant_under_similarity():
+    # mu depends on the shape and vertex order only: translation, uniform
+    # scaling and rotation leave it unchanged
+    v = np.array(W.make_tet(22, 4, W.COEFF_CONST, (1.0,), jitter=0.15).verts)
+    mu, best = O.lfa_orientation(v)
+    c, s = np.cos(0.7), np.sin(0.7)
+    R = np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]]) @ np.array([[1, 0, 0], [0, c, s], [0, -s, c]])
+    mu2, best2 = O.lfa_orientation(3.5 * v @ R.T + np.array([1.0, -2.0, 0.5]))
+    np.testing.assert_allclose(mu2, mu, rtol=1e-9)
+    assert best2 == best and 0.0 < mu[best] < 1.0
+    # a finer frequency grid moves the sampled supremum only a little
+    th = O.lfa_frequencies(48)
+    A = O.constant_stencil(O.permute_vertices(v, O.permutations()[best]))
+    L, D = O.asymptotic_stencil(A)
+    assert abs(O.smoothing_factor(A, L, D, th) - mu[best]) < 0.05
+
+
+def test_lfa_orientation_matches_printed_choices():
+    # Cap and Spade (Table SM1): among the permutations the paper lists, the
+    # smallest smoothing factor is at the one its heuristic selected (bold).
+    # Spindle: the LFA prefers (1 4 2 3), which the paper's multigrid rates
+    # also favour (0.35 vs 0.39 for its bold (1 3 2 4)); recorded, not asserted.
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "orientation_shapes.json")))
+    perms = ["".join(map(str, p)) for p in O.permutations()]
+    for name in ("Cap", "Spade"):
+        sh = g["shapes"][name]
+        mu, best = O.lfa_orientation(sh["vertices"])
+        listed = {p: mu[perms.index(p)] for p in sh["rho_ilu"]}
+        assert min(listed, key=listed.get) == sh["bold"], (name, listed)
+        # and the best listed permutation also has the best printed rate
+        assert min(sh["rho_ilu"], key=sh["rho_ilu"].get) == sh["bold"]
+    sh = g["shapes"]["Spindle"]
+    mu, best = O.lfa_orientation(sh["vertices"])
+    listed = {p: mu[perms.index(p)] for p in sh["rho_ilu"]}
+    assert min(listed, key=listed.get) == min(sh["rho_ilu"], key=sh["rho_ilu"].get) == "1423"
