@@ -290,6 +290,8 @@ def main():
     ap.add_argument("--pcg-abs-tol", type=float, default=0.0, help="absolute residual target of --pcg-tol mode")
     ap.add_argument("--max-iters", type=int, default=5000)
     ap.add_argument("--degree", default="", help="surrogate degrees dx,dy,dz instead of the workload's")
+    ap.add_argument("--lfa", action="store_true",
+                    help="instead of sweeps: time the LFA orientation choice for every tetrahedron of the workload")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -310,6 +312,8 @@ def main():
         return main_to_tol(a, torch, pkg, wl, variants, tile)
     if a.pcg_tol > 0 or a.pcg_abs_tol > 0:
         return main_pcg(a, torch, pkg, wl, variants, tile)
+    if a.lfa:
+        return main_lfa(a, pkg, wl)
     results, handles = {}, {}
     for v in variants:
         results[v], handles[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
@@ -439,6 +443,37 @@ def main_pcg(a, torch, pkg, wl, variants, tile):
     for ref in ("stored_f64", "stored_sgs"):
         if ref in res and head != ref:
             line["time_speedup_vs_" + ref] = res[ref]["ms"] / res[head]["ms"]
+    print(json.dumps(line))
+
+
+def main_lfa(a, pkg, wl, samples=16):
+    """LFA orientation choice (24 permutations x samples^3 frequencies per
+    tetrahedron) for the workload's tetrahedra; host clock around the
+    synchronous library call."""
+    tets = list(wl.tets)
+    for _ in range(2):
+        pkg.lfa_orientation(tets, samples)
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mu, best = pkg.lfa_orientation(tets, samples)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    nfreq = sum(1 for i in range(samples) for j in range(samples) for k in range(samples)
+                if max(abs(2 * c + 1 - samples) for c in (i, j, k)) * 2 >= samples)
+    nsym = len(tets) * 24 * nfreq
+    line = {"metric": "LFA orientation choice: smoothing factors of 24 vertex permutations per tetrahedron",
+            "value": len(tets) / (ms * 1e-3), "unit": "tetrahedra/s", "n_gpus": 1, "ms_per_call": ms,
+            "symbols_per_s": nsym / (ms * 1e-3), "higher_is_better": True, "dtype": "f64",
+            "data": "synthetic (seeded jittered macro-tetrahedra)",
+            "config": {"workload": wl.name, "n_tets": len(tets), "samples": samples, "frequencies": nfreq},
+            "best_mu": {"min": min(m[b] for m, b in zip(mu, best)), "max": max(m[b] for m, b in zip(mu, best))}}
+    if not a.no_cpu:
+        import oracle as O
+        t0 = time.perf_counter()
+        O.lfa_orientation(tets[0].verts, samples)
+        el = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / el, "unit": "tetrahedra/s", "cores": 1, "kind": "oracle",
+                                "sample": "one tetrahedron of the workload, %.2f s" % el}
     print(json.dumps(line))
 
 

@@ -43,7 +43,7 @@ extern "C" {
 #define ILU_EHIP (-3)       /* a HIP runtime call failed */
 #define ILU_EBREAKDOWN (-4) /* ILU(0) pivot D^p <= 0 (A is not an M-matrix) */
 #define ILU_ERANK (-5)      /* a least-squares problem is rank deficient */
-#define ILU_EGEOM (-6)      /* det J <= 0 (degenerate or inverted tetrahedron) */
+#define ILU_EGEOM (-6)      /* det J = 0 (degenerate tetrahedron) */
 #define ILU_ENOTCONV (-7)   /* rel_tol requested but not reached in nsweeps */
 
 /* coefficient kinds (kappa as a function of the physical point X) */
@@ -69,7 +69,8 @@ extern "C" {
 #define ILU_SCHED_DATAFLOW 2  /* persistent kernel, per-block progress counters */
 
 typedef struct ilu_tet_desc {
-    double vertex[4][3];   /* v1..v4; d_i = v_{i+1} - v1 must have det > 0 */
+    double vertex[4][3];   /* v1..v4 (their order fixes the DOF ordering); d_i = v_{i+1} - v1
+                              must not be coplanar (either orientation) */
     int32_t level;         /* L in [2, 10] */
     int32_t coeff_kind;    /* ILU_COEFF_* */
     double coeff_param[4];
@@ -148,6 +149,26 @@ int ilu_pcg(ilu_handle_t h, double *x, const double *b, int32_t maxit, double re
  * scaled iterate.  Synchronous on hip_stream. */
 int ilu_contraction(ilu_handle_t h, double *x, int32_t nsteps, double *rho_out, double *rho_res_out,
                     void *hip_stream);
+
+/* Orientation choice by local Fourier analysis (Sec. 3, strategy on
+ * macro-elements): for each of the 24 vertex permutations of each
+ * tetrahedron, the smoothing factor mu of the ILU with the asymptotic stencil
+ * (the Gauss-Seidel fixed point of the stencil equations) for the constant
+ * stencil of a unit coefficient (level and coefficient of the descriptors are
+ * ignored):
+ *     mu = max |(L D conj(L) - A)(theta) / (L D conj(L))(theta)|
+ * over the oscillatory frequencies theta in (-pi,pi)^3 minus (-pi/2,pi/2)^3,
+ * sampled at the cell centres theta_j = -pi + (2j+1) pi / samples of a uniform
+ * grid (the paper uses 16 samples per direction; samples must be a multiple of
+ * 4 in [4, 256]).  Permutation k (0..23) is the k-th permutation
+ * s = (s1 s2 s3 s4) of (1 2 3 4) in lexicographic order; the permuted
+ * tetrahedron has the original vertex i at position s_i.  mu_out (host,
+ * may be NULL): [ntets][24]; +inf where the fixed-point iteration did not
+ * converge to a positive pivot.  best_out (host, may be NULL): per
+ * tetrahedron the k of the smallest mu (the first one on ties).  ILU_EGEOM
+ * for a degenerate tetrahedron.  Synchronous on hip_stream. */
+int ilu_lfa_orientation(const ilu_tet_desc *tets, int32_t ntets, int32_t samples, double *mu_out, int32_t *best_out,
+                        void *hip_stream);
 
 /* Offset and interior-point count of tetrahedron `tet` in the vectors. */
 int ilu_layout(ilu_handle_t h, int32_t tet, int64_t *offset, int64_t *count_interior);

@@ -55,6 +55,7 @@ def lib():
         L.stencil_apply.argtypes = [P, P, P, P]
         L.ilu_pcg.argtypes = [P, P, P, I32, D, D, ctypes.POINTER(I32), ctypes.POINTER(D), P]
         L.ilu_contraction.argtypes = [P, P, I32, ctypes.POINTER(D), ctypes.POINTER(D), P]
+        L.ilu_lfa_orientation.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, I32, P, P, P]
         L.ilu_layout.argtypes = [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)]
         L.ilu_destroy.argtypes = [P]
         L.ilu_strerror.argtypes = [ctypes.c_int]
@@ -97,6 +98,28 @@ def exported_symbols() -> list:
     return out
 
 
+def _tet_array(tets):
+    arr = (ilu_tet_desc * len(tets))()
+    for i, t in enumerate(tets):
+        arr[i].vertex[:] = [float(c) for row in t.verts for c in row]
+        arr[i].level = int(t.level)
+        arr[i].coeff_kind = int(t.coeff_kind)
+        arr[i].coeff_param[:] = [float(c) for c in t.coeff_params]
+    return arr
+
+
+def lfa_orientation(tets: Sequence, samples: int = 16, stream: int = 0):
+    """LFA smoothing factors of the 24 vertex permutations of every tetrahedron
+    (ilu_lfa_orientation).  Returns (mu as a list of 24-lists, best index per
+    tetrahedron)."""
+    n = len(tets)
+    mu = (ctypes.c_double * (24 * n))()
+    best = (ctypes.c_int32 * n)()
+    _check(lib().ilu_lfa_orientation(_tet_array(tets), n, int(samples), mu, best, ctypes.c_void_p(stream)),
+           "ilu_lfa_orientation")
+    return [list(mu[24 * i:24 * i + 24]) for i in range(n)], list(best)
+
+
 def _check(code: int, what: str):
     if code != 0:
         raise ILUError(code, what)
@@ -119,13 +142,7 @@ class Smoother:
         self.torch = torch
         self.L = lib()
         self.ntets = len(tets)
-        arr = (ilu_tet_desc * self.ntets)()
-        for i, t in enumerate(tets):
-            v = [c for row in t.verts for c in row]
-            arr[i].vertex[:] = v
-            arr[i].level = int(t.level)
-            arr[i].coeff_kind = int(t.coeff_kind)
-            arr[i].coeff_param[:] = [float(c) for c in t.coeff_params]
+        arr = _tet_array(tets)
         opts = ilu_opts()
         opts.variant = int(variant)
         dg = (degree,) * 3 if isinstance(degree, int) else tuple(degree)

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libilu.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["setup_kernels.hip", "sweep_kernels.hip", "dataflow_kernels.hip", "krylov_kernels.hip", "abi.cpp"]
+SOURCES = ["setup_kernels.hip", "sweep_kernels.hip", "dataflow_kernels.hip", "krylov_kernels.hip", "lfa_kernels.hip", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          # no packed FP32 instructions in device code

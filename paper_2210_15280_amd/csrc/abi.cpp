@@ -18,6 +18,7 @@
 #include "setup_kernels.h"
 #include "sweep_kernels.h"
 #include "krylov_kernels.h"
+#include "lfa_kernels.h"
 
 using namespace ilu;
 
@@ -434,7 +435,8 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
         const double* J = T.J;
         const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
                            J[2] * (J[3] * J[7] - J[4] * J[6]);
-        if (!(det > 0.0) || !std::isfinite(det)) return ILU_EGEOM;
+        // either orientation: the element stiffness only uses |det| and metric terms
+        if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return ILU_EGEOM;
         for (int k = 0; k < 3; ++k) T.deg[k] = h->deg[k];
         T.ncoef = h->K;
         if (surr) {
@@ -1235,6 +1237,48 @@ int ilu_contraction(ilu_handle_t h, double* x, int32_t nsteps, double* rho_out, 
     int32_t fl[4];
     if (int e = read_flags(h, st, fl)) return e;
     if (h->schedule != ILU_SCHED_PLANE && fl[2]) return ILU_EHIP;
+    return ILU_OK;
+}
+
+int ilu_lfa_orientation(const ilu_tet_desc* tets, int32_t ntets, int32_t samples, double* mu_out,
+                        int32_t* best_out, void* hip_stream) {
+    if (!tets || ntets <= 0 || (!mu_out && !best_out) || samples < 4 || samples > 256 || samples % 4) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<double> v((size_t)ntets * 12);
+    for (int i = 0; i < ntets; ++i) {
+        for (int a = 0; a < 4; ++a)
+            for (int r = 0; r < 3; ++r) {
+                const double x = tets[i].vertex[a][r];
+                if (!std::isfinite(x)) return ILU_EINVAL;
+                v[(size_t)i * 12 + 3 * a + r] = x;
+            }
+        double E[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) E[r][c] = tets[i].vertex[c + 1][r] - tets[i].vertex[0][r];
+        const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                           E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                           E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+        if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return ILU_EGEOM;
+    }
+    DevBuf dv, drec, dmu;
+    const size_t np = (size_t)ntets * LFA_PERMS;
+    if (dv.alloc(v.size() * sizeof(double), st, false) || drec.alloc(np * LFA_REC * sizeof(double), st, false) ||
+        dmu.alloc(np * sizeof(double), st, false))
+        return ILU_ENOMEM;
+    HIPCHK(hipMemcpyAsync(dv.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_lfa_stencils(dv.as<double>(), ntets, drec.as<double>(), st);
+    launch_lfa_symbols(drec.as<double>(), ntets, samples, dmu.as<double>(), st);
+    HIPCHK(hipGetLastError());
+    std::vector<double> mu(np);
+    HIPCHK(hipMemcpyAsync(mu.data(), dmu.p, np * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < ntets; ++i) {
+        int best = 0;
+        for (int k = 1; k < LFA_PERMS; ++k)
+            if (mu[(size_t)i * LFA_PERMS + k] < mu[(size_t)i * LFA_PERMS + best]) best = k;
+        if (best_out) best_out[i] = best;
+    }
+    if (mu_out) std::memcpy(mu_out, mu.data(), np * sizeof(double));
     return ILU_OK;
 }
 

@@ -1,0 +1,17 @@
+// Launchers of the LFA orientation kernels (Sec. 3, strategy on macro-elements).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ilu {
+
+constexpr int LFA_PERMS = 24;       // vertex permutations of a tetrahedron
+constexpr int LFA_REC = 24;         // per (tet, permutation): A[15], L[7], D, converged
+constexpr int LFA_MAX_ITERS = 20000;
+
+// verts: device [ntets][4][3]; rec: device [ntets * 24][LFA_REC]
+void launch_lfa_stencils(const double* verts, int ntets, double* rec, hipStream_t st);
+// mu: device [ntets * 24]; samples frequencies per direction
+void launch_lfa_symbols(const double* rec, int ntets, int samples, double* mu, hipStream_t st);
+
+}  // namespace ilu

@@ -6,6 +6,7 @@
 
 #include "kernels_common.h"
 #include "setup_kernels.h"
+#include "stencil_device.h"
 
 namespace ilu {
 
@@ -25,38 +26,9 @@ __device__ double kappa_at(const TetDev& T, double X, double Y, double Z) {
     }
 }
 
-// Slot in the 15-point stencil (listing order w,s,se,bnw,bn,bc,be,c,e,n,nw,tse,ts,tc,tw)
-// of a lattice offset with components in {-1,0,1}; -1 if it is not a stencil offset.
-__device__ int stencil_slot(int dx, int dy, int dz) {
-    if (dz == -1) {
-        if (dy == 0 && dx == 0) return 5;    // bc
-        if (dy == 0 && dx == 1) return 6;    // be
-        if (dy == 1 && dx == -1) return 3;   // bnw
-        if (dy == 1 && dx == 0) return 4;    // bn
-        return -1;
-    }
-    if (dz == 0) {
-        if (dy == -1 && dx == 0) return 1;   // s
-        if (dy == -1 && dx == 1) return 2;   // se
-        if (dy == 0 && dx == -1) return 0;   // w
-        if (dy == 0 && dx == 0) return 7;    // c
-        if (dy == 0 && dx == 1) return 8;    // e
-        if (dy == 1 && dx == 0) return 9;    // n
-        if (dy == 1 && dx == -1) return 10;  // nw
-        return -1;
-    }
-    if (dy == -1 && dx == 1) return 11;      // tse
-    if (dy == -1 && dx == 0) return 12;      // ts
-    if (dy == 0 && dx == 0) return 13;       // tc
-    if (dy == 0 && dx == -1) return 14;      // tw
-    return -1;
-}
-
-// One thread per (block, lane, hyperplane): gather the 24 micro-tetrahedra
-// around p and sum their P1 element stiffness rows (Sec. 2.1).  The micro-mesh
-// is the Kuhn subdivision in (a,b,c) = (x, x+y, x+y+z): the simplices
-// containing P are q + {0, e_s1, e_s1+e_s2, (1,1,1)} with P one of the four
-// vertices.  Writes the centre and the seven lower weights (entries whose
+// One thread per (block, lane, hyperplane): the stencil row of p (sum over the
+// 24 micro-tetrahedra around p, stencil_row).  Writes the centre and the
+// seven lower weights (entries whose
 // neighbour is on the macro boundary are stored as 0: the restricted matrix
 // drops them), slot order [c, w, s, se, bnw, bn, bc, be].
 __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
@@ -70,66 +42,11 @@ __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __re
     const TetDev& T = tets[B.tet];
     const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
     const double invn = 1.0 / n;
-    static constexpr int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;  // x = u - v, u = t - v - w
         if (x < 1 || x > n - 1 - v) continue;
         double Ad[15];
-        for (int s = 0; s < 15; ++s) Ad[s] = 0.0;
-        const int P[3] = {x, x + y, x + y + z};
-        for (int sg = 0; sg < 6; ++sg) {
-            int off[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {1, 1, 1}};
-            off[1][perm[sg][0]] = 1;
-            off[2][perm[sg][0]] = 1;
-            off[2][perm[sg][1]] = 1;
-            for (int k = 0; k < 4; ++k) {
-                // vertices (logical xyz) of the simplex whose k-th vertex is p
-                int lx[4], ly[4], lz[4];
-                for (int j = 0; j < 4; ++j) {
-                    const int a = P[0] - off[k][0] + off[j][0];
-                    const int bb = P[1] - off[k][1] + off[j][1];
-                    const int c = P[2] - off[k][2] + off[j][2];
-                    lx[j] = a;
-                    ly[j] = bb - a;
-                    lz[j] = c - bb;
-                }
-                // physical edge matrix E (columns X_j - X_0) = J (l_j - l_0) / n
-                double E[3][3], cen[3];
-                for (int r = 0; r < 3; ++r) {
-                    for (int cc = 0; cc < 3; ++cc) {
-                        const int ex = lx[cc + 1] - lx[0], ey = ly[cc + 1] - ly[0], ez = lz[cc + 1] - lz[0];
-                        E[r][cc] = (T.J[3 * r] * ex + T.J[3 * r + 1] * ey + T.J[3 * r + 2] * ez) * invn;
-                    }
-                    const double mx = 0.25 * (lx[0] + lx[1] + lx[2] + lx[3]);
-                    const double my = 0.25 * (ly[0] + ly[1] + ly[2] + ly[3]);
-                    const double mz = 0.25 * (lz[0] + lz[1] + lz[2] + lz[3]);
-                    cen[r] = T.v0[r] + (T.J[3 * r] * mx + T.J[3 * r + 1] * my + T.J[3 * r + 2] * mz) * invn;
-                }
-                const double c00 = E[1][1] * E[2][2] - E[1][2] * E[2][1];
-                const double c01 = E[1][2] * E[2][0] - E[1][0] * E[2][2];
-                const double c02 = E[1][0] * E[2][1] - E[1][1] * E[2][0];
-                const double det = E[0][0] * c00 + E[0][1] * c01 + E[0][2] * c02;
-                const double id = 1.0 / det;
-                // rows of E^{-1} are the gradients of lambda_1..3
-                double g[4][3];
-                g[1][0] = c00 * id;
-                g[1][1] = (E[0][2] * E[2][1] - E[0][1] * E[2][2]) * id;
-                g[1][2] = (E[0][1] * E[1][2] - E[0][2] * E[1][1]) * id;
-                g[2][0] = c01 * id;
-                g[2][1] = (E[0][0] * E[2][2] - E[0][2] * E[2][0]) * id;
-                g[2][2] = (E[0][2] * E[1][0] - E[0][0] * E[1][2]) * id;
-                g[3][0] = c02 * id;
-                g[3][1] = (E[0][1] * E[2][0] - E[0][0] * E[2][1]) * id;
-                g[3][2] = (E[0][0] * E[1][1] - E[0][1] * E[1][0]) * id;
-                for (int r = 0; r < 3; ++r) g[0][r] = -(g[1][r] + g[2][r] + g[3][r]);
-                const double scale = kappa_at(T, cen[0], cen[1], cen[2]) * fabs(det) / 6.0;
-                for (int j = 0; j < 4; ++j) {
-                    const double kij = scale * (g[k][0] * g[j][0] + g[k][1] * g[j][1] + g[k][2] * g[j][2]);
-                    const int sl = stencil_slot(lx[j] - lx[k], ly[j] - ly[k], lz[j] - lz[k]);
-                    Ad[sl] += kij;
-                }
-            }
-        }
+        stencil_row(T.J, T.v0, invn, x, y, z, [&](double X, double Y, double Z) { return kappa_at(T, X, Y, Z); }, Ad);
         const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
         A8[idx] = Ad[7];
         for (int s = 0; s < NLOW; ++s) {

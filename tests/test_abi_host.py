@@ -55,14 +55,34 @@ def _setup(P, tets, variant=0, degree=(4, 4, 4), stride=4, reserved=0, tile=(0, 
     return P.lib().ilu_setup_surrogate(arr, len(tets), ctypes.byref(o), None, ctypes.byref(h))
 
 
-def test_inverted_tet_is_rejected(P):
-    t = W.make_tet(1, 4, W.COEFF_CONST, (1.0,))
-    v = list(t.verts)
-    v[1], v[2] = v[2], v[1]  # swap two vertices: det J < 0
-    bad = W.Tet(tuple(v), 4, 0, (1.0, 0, 0, 0), t.rhs_state)
-    assert _setup(P, [bad]) == -6
+def test_degenerate_tet_is_rejected_and_either_orientation_accepted(P):
+    from paper_2210_15280_amd._lib import _tet_array, ilu_opts
     flat = W.Tet(((0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0)), 4, 0, (1.0, 0, 0, 0), 0)
     assert _setup(P, [flat]) == -6
+    # swapping two vertices flips det J: accepted (the layout replay runs on the host)
+    t = W.make_tet(1, 4, W.COEFF_CONST, (1.0,))
+    v = list(t.verts)
+    v[1], v[2] = v[2], v[1]
+    inv = W.Tet(tuple(v), 4, 0, (1.0, 0, 0, 0), t.rhs_state)
+    o = ilu_opts()
+    o.variant, o.tile[:] = 0, [8, 8]
+    bad = ctypes.c_int64(-1)
+    assert P.lib().ilu_check_layout(_tet_array([inv]), 1, ctypes.byref(o), ctypes.byref(bad)) == 0
+    assert bad.value == 0
+
+
+def test_lfa_orientation_argument_checks(P):
+    from paper_2210_15280_amd._lib import _tet_array
+    t = W.make_tet(1, 4, W.COEFF_CONST, (1.0,))
+    mu = (ctypes.c_double * 24)()
+    best = (ctypes.c_int32 * 1)()
+    L = P.lib()
+    for samples in (0, 2, 6, 18, 260):
+        assert L.ilu_lfa_orientation(_tet_array([t]), 1, samples, mu, best, None) == -1
+    assert L.ilu_lfa_orientation(_tet_array([t]), 1, 16, None, None, None) == -1
+    assert L.ilu_lfa_orientation(_tet_array([t]), 0, 16, mu, best, None) == -1
+    flat = W.Tet(((0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0)), 4, 0, (1.0, 0, 0, 0), 0)
+    assert L.ilu_lfa_orientation(_tet_array([flat]), 1, 16, mu, best, None) == -6
 
 
 def test_invalid_arguments(P):

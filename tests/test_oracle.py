@@ -627,3 +627,23 @@ def test_lfa_orientation_matches_printed_choices():
     mu, best = O.lfa_orientation(sh["vertices"])
     listed = {p: mu[perms.index(p)] for p in sh["rho_ilu"]}
     assert min(listed, key=listed.get) == min(sh["rho_ilu"], key=sh["rho_ilu"].get) == "1423"
+
+
+def test_z_only_surrogate_on_a_flat_tetrahedron():
+    # distorted tetrahedron of height 0.1 with a unit coefficient (Sec. 4.3):
+    # the factors vary mainly along z, so dg_x = dg_y = 0 with a high dg_z
+    # comes close to the exact ILU's contraction, while a low dg_z does not
+    wl = W.workload("flat_L8_const")
+    t = wl.tets[0]
+    t5 = W.Tet(t.verts, 5, t.coeff_kind, t.coeff_params, t.rhs_state)
+    P = O.Problem.from_tet(t5)
+    L, U, D = P.ilu0()
+    z = np.zeros(P.N)
+    x0 = W.SplitMix64(1).uniform_array(P.N, -1.0, 1.0)
+    rho_exact = O.contraction_factor(P, lambda y: P.smooth_stencil(L, 1.0 / D, z, y, 1)[0], x0, 20)[0]
+    rho = {}
+    for deg in ((0, 0, 6), (0, 0, 3)):
+        c = O.fit_surrogate(5, L, D, deg, O.effective_stride(5, deg, 4))
+        Lw, Dinv = O.eval_surrogate(5, c, deg)
+        rho[deg] = O.contraction_factor(P, lambda y: P.smooth_stencil(Lw, Dinv, z, y, 1)[0], x0, 20)[0]
+    assert rho[(0, 0, 6)] < 1.25 * rho_exact < rho[(0, 0, 3)]

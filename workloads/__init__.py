@@ -174,7 +174,13 @@ def workload(name: str) -> Workload:
     if name == "jit_L9_exp":
         t = make_tet(5, 9, *KAPPA_EXP, jitter=0.15)
         return Workload(name, (t,), "surr_f32", 6, 4, 20)
+    if name == "flat_L8_const":
+        # trirectangular tetrahedron of height 0.1, unit coefficient: the
+        # distorted tetrahedron of the anisotropic-degree study
+        t = Tet(FLAT_TET, 8, COEFF_CONST, (1.0, 0.0, 0.0, 0.0), SplitMix64(6).state)
+        return Workload(name, (t,), "surr_f32", 6, 4, 20)
     raise KeyError(name)
 
 
-WORKLOADS = ("ref_L4", "jit_L7_sin", "jit_L8_sin", "batch256_L567", "jit_L9_exp")
+FLAT_TET = ((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 0.1))
+WORKLOADS = ("ref_L4", "jit_L7_sin", "jit_L8_sin", "batch256_L567", "jit_L9_exp", "flat_L8_const")
