@@ -15,6 +15,7 @@ Functions and the passage they follow:
   smooth_stencil(_f32)         Alg. 2 (variant V2), FP64 / FP32-mixed
   sample_set, fit_surrogate    Sec. 4.1 sample sets S_d and LSQ fit
   eval_surrogate               Sec. 4.1 surrogate polynomials
+  fit/eval_operator_surrogate  Sec. 4.3 surrogate for the operator A itself
   asymptotic_stencil           Sec. 3 Gauss-Seidel iteration of the stencil equations
   contraction_factor           Sec. 4.3 asymptotic rate by power iteration, applied to
                                the smoother's error propagation I - C^{-1} A
@@ -168,10 +169,14 @@ class Problem:
     def from_tet(cls, tet):
         return cls(tet.verts, tet.level, tet.coeff_kind, tet.coeff_params)
 
-    def apply(self, x):
+    def _op(self, A):
+        return self.A if A is None else np.ascontiguousarray(A, dtype=np.float64).reshape(self.N, 15)
+
+    def apply(self, x, A=None):
+        """y = A x (or with the stencil array A given in the same layout, e.g. a surrogate operator)."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         y = np.zeros(self.N)
-        _L().oracle_apply(self.N, _ptr(self.A), _ptr(self.col), _ptr(x), _ptr(y))
+        _L().oracle_apply(self.N, _ptr(self._op(A)), _ptr(self.col), _ptr(x), _ptr(y))
         return y
 
     def csr(self):
@@ -208,22 +213,23 @@ class Problem:
                                _ptr(x), int(nsweeps), _ptr(rel))
         return x, rel
 
-    def smooth_stencil(self, Lw, Dinv, b, x0=None, nsweeps=1):
-        """Alg. 2 (V2) with per-point weights Lw (N,7) and Dinv (N,).  Returns (x, relres)."""
+    def smooth_stencil(self, Lw, Dinv, b, x0=None, nsweeps=1, A=None):
+        """Alg. 2 (V2) with per-point weights Lw (N,7) and Dinv (N,); the residual
+        uses A (default: the assembled operator).  Returns (x, relres)."""
         x = np.zeros(self.N) if x0 is None else np.array(x0, dtype=np.float64)
         rel = np.zeros(nsweeps + 1)
-        _L().oracle_smooth_stencil(self.N, _ptr(self.A), _ptr(self.col),
+        _L().oracle_smooth_stencil(self.N, _ptr(self._op(A)), _ptr(self.col),
                                    _ptr(np.ascontiguousarray(Lw, dtype=np.float64)),
                                    _ptr(np.ascontiguousarray(Dinv, dtype=np.float64)),
                                    _ptr(np.ascontiguousarray(b, dtype=np.float64)), _ptr(x), int(nsweeps),
                                    _ptr(rel))
         return x, rel
 
-    def smooth_stencil_f32(self, Lw, Dinv, b, x0=None, nsweeps=1):
+    def smooth_stencil_f32(self, Lw, Dinv, b, x0=None, nsweeps=1, A=None):
         """Alg. 2 with FP64 residual, FP32 weights and substitutions, FP64 update."""
         x = np.zeros(self.N) if x0 is None else np.array(x0, dtype=np.float64)
         rel = np.zeros(nsweeps + 1)
-        _L().oracle_smooth_stencil_f32(self.N, _ptr(self.A), _ptr(self.col),
+        _L().oracle_smooth_stencil_f32(self.N, _ptr(self._op(A)), _ptr(self.col),
                                        _ptr(np.ascontiguousarray(Lw, dtype=np.float32)),
                                        _ptr(np.ascontiguousarray(Dinv, dtype=np.float32)),
                                        _ptr(np.ascontiguousarray(b, dtype=np.float64)), _ptr(x), int(nsweeps),
@@ -387,6 +393,39 @@ def eval_surrogate(level: int, coeffs: np.ndarray, degree, basis: str = "legendr
     mat = legendre_tensor_matrix if basis == "legendre" else monomial_tensor_matrix
     vals = mat(pts, degree) @ coeffs.T
     return np.ascontiguousarray(vals[:, :NLOW]), np.ascontiguousarray(vals[:, NLOW])
+
+
+def fit_operator_surrogate(level: int, A: np.ndarray, degree, stride: int, basis: str = "legendre"):
+    """Surrogate for the operator (Sec. 4.3 approximates A by surrogate
+    polynomials as well): one polynomial per d in D_l fit to A^p_d and one
+    for c fit to A^p_c, on the sample sets S_d of the ILU fit (p + d interior,
+    so the dropped boundary entries are never samples).  A is the (N,15)
+    stencil array.  Returns coeffs (8, K): rows 0..6 = D_l, 7 = c."""
+    pts = interior_points(level).astype(np.float64) / (1 << level)
+    mat = legendre_tensor_matrix if basis == "legendre" else monomial_tensor_matrix
+    out = []
+    for t in list(range(NLOW)) + [CENTRE]:
+        idx = sample_set(level, t, stride)
+        out.append(lsq(mat(pts[idx], degree), A[idx, t]))
+    return np.array(out)
+
+
+def eval_operator_surrogate(level: int, coeffs: np.ndarray, degree, basis: str = "legendre") -> np.ndarray:
+    """The surrogate stencil in the (N,15) layout: lower weights and the
+    centre from their polynomials at p, and the upper weight of direction
+    -d_k as the lower polynomial k at p - d_k (A^p_{-d} = A^{p-d}_d, so the
+    surrogate operator stays symmetric).  Entries whose neighbour is not
+    interior multiply nothing."""
+    pts = interior_points(level).astype(np.float64)
+    n = 1 << level
+    mat = legendre_tensor_matrix if basis == "legendre" else monomial_tensor_matrix
+    out = np.zeros((len(pts), 15))
+    vals = mat(pts / n, degree) @ coeffs.T
+    out[:, :NLOW] = vals[:, :NLOW]
+    out[:, CENTRE] = vals[:, NLOW]
+    for k in range(NLOW):
+        out[:, 8 + k] = mat((pts - DIRS[k]) / n, degree) @ coeffs[k]
+    return out
 
 
 def surrogate_error(level: int, L, D, Lw, Dinv):

@@ -647,3 +647,44 @@ def test_z_only_surrogate_on_a_flat_tetrahedron():
         Lw, Dinv = O.eval_surrogate(5, c, deg)
         rho[deg] = O.contraction_factor(P, lambda y: P.smooth_stencil(Lw, Dinv, z, y, 1)[0], x0, 20)[0]
     assert rho[(0, 0, 6)] < 1.25 * rho_exact < rho[(0, 0, 3)]
+
+
+# --------------------------------------------------------- surrogate operator
+
+
+@pytest.mark.parametrize("coeff,deg", [((W.COEFF_CONST, (1.0,)), 0), ((W.COEFF_POLY, (1.0, 10.0, 2.0, 0.0)), 2)])
+def test_operator_surrogate_is_exact_for_polynomial_stencils(coeff, deg):
+    # kappa = 1 (constant stencil) and kappa = 1 + 10 (x^2 + y^2 + z^2) (the
+    # paper's kappa_2) on an affine tetrahedron give stencil entries that are
+    # polynomials of degree deg in the lattice point, so the fit reproduces A
+    # on the pattern and smoothing with the surrogate operator equals smoothing
+    # with A
+    t = W.make_tet(23, 5, coeff[0], coeff[1], jitter=0.15)
+    P = O.Problem.from_tet(t)
+    s = O.effective_stride(5, deg, 4)
+    c = O.fit_operator_surrogate(5, P.A, deg, s)
+    At = O.eval_operator_surrogate(5, c, deg)
+    m = P.col >= 0
+    assert np.abs(At[m] - P.A[m]).max() <= 1e-9 * np.abs(P.A).max()
+    L, U, D = P.ilu0()
+    b = t.rhs()
+    x1, _ = P.smooth_stencil(L, 1.0 / D, b, nsweeps=3)
+    x2, _ = P.smooth_stencil(L, 1.0 / D, b, nsweeps=3, A=At)
+    np.testing.assert_allclose(x2, x1, rtol=0, atol=1e-8 * np.abs(x1).max())
+
+
+def test_operator_surrogate_is_symmetric_and_close():
+    # variable coefficient: the surrogate is symmetric by construction
+    # (upper weights are the lower polynomials at p - d) and within the fit
+    # error of A; its row sums vanish only approximately
+    t = W.make_tet(24, 5, *W.KAPPA_EXP, jitter=0.15)
+    P = O.Problem.from_tet(t)
+    c = O.fit_operator_surrogate(5, P.A, 3, O.effective_stride(5, 3, 4))
+    At = O.eval_operator_surrogate(5, c, 3)
+    m = P.col >= 0
+    for s in range(7):
+        j = P.col[:, 8 + s]
+        ok = j >= 0
+        np.testing.assert_allclose(At[ok, 8 + s], At[j[ok], s], rtol=0, atol=1e-12 * np.abs(P.A).max())
+    rel = np.abs(At[m] - P.A[m]).max() / np.abs(P.A).max()
+    assert 1e-8 < rel < 5e-2
