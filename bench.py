@@ -32,8 +32,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # kernel; stencil weights: 8 unique FP64 values per point, the other 7 are the
 # neighbours' by symmetry).  w: FP64 (8 B) or FP32 (4 B).
 def kernel_bytes(variant: str):
-    wb = 4 if variant == "surr_f32" else 8
+    wb = 4 if variant.startswith("surr_f32") else 8
     res = 8 + 8 + 64 + wb                    # x, b, A (8 weights), r
+    if variant.endswith("_sa"):
+        res = 8 + 8 + wb                      # x, b, r (the operator is evaluated, not loaded)
     if variant in ("stored_f64", "stored_sgs"):
         fwd = 8 + 56 + 8                      # r, L (7), w
         bwd = 8 + 8 + 56 + 8 + 8              # w in, 1/D, L^T (7), x in, x out
@@ -52,10 +54,20 @@ def kernel_flops(variant: str, dg):
     return {"residual": res, "forward": 14 + 14 * dg, "backward": 16 + 16 * dg}
 
 
-VARIANTS = {"stored_f64": 0, "surr_f64": 1, "surr_f32": 2, "stored_sgs": 3}
+# variant name -> (library variant, operator mode); *_sa: surrogate operator in the residual
+VARIANTS = {"stored_f64": (0, 0), "surr_f64": (1, 0), "surr_f32": (2, 0), "stored_sgs": (3, 0),
+            "surr_f64_sa": (1, 1), "surr_f32_sa": (2, 1)}
 STORED = ("stored_f64", "stored_sgs")
 DTYPES = {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
-          "stored_f64": "f64", "stored_sgs": "f64"}
+          "stored_f64": "f64", "stored_sgs": "f64",
+          "surr_f32_sa": "f32 (sweeps, surrogate evaluation) + f64 (residual with f32-evaluated surrogate operator, update)",
+          "surr_f64_sa": "f64 (surrogate operator)"}
+
+
+def make_smoother(pkg, wl, variant, tile):
+    v, a_mode = VARIANTS[variant]
+    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride, a_mode=a_mode)
+    return pkg.Smoother(list(wl.tets), v, tile=tile, **kw)
 CONTRACTION_STEPS = 20
 CONTRACTION_SEED = 0x5EED
 KERNEL_NAMES = {"residual": "k_residual", "forward": "k_fwd_flow", "backward": "k_bwd_flow"}
@@ -97,10 +109,8 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     """Times `steps` sweeps; also measures the smoother's contraction factor.
     Returns (results, handle): the caller closes the handle."""
     import numpy as np
-    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride)
-    kw["tile"] = tile
     t0 = time.perf_counter()
-    sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
+    sm = make_smoother(pkg, wl, variant, tile)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
@@ -141,9 +151,7 @@ def run_to_tol(pkg, torch, wl, variant, tol, cap, tile=(0, 0)):
     """One ilu_smooth call from x = 0 until ||b - A x|| / ||b|| <= tol (FP64
     residual; for the FP32 variant this is its FP64 iterative refinement)."""
     import numpy as np
-    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride)
-    kw["tile"] = tile
-    sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
+    sm = make_smoother(pkg, wl, variant, tile)
     b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
     x = torch.zeros_like(b)
     sm.smooth(x, b, 3)
@@ -402,9 +410,7 @@ def run_pcg(pkg, torch, wl, variant, rel_tol, abs_tol, cap, tile=(0, 0)):
     """CG preconditioned by one smoother variant, from x = 0, until the
     recursively updated residual meets the tolerance; device time of the call."""
     import numpy as np
-    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride)
-    kw["tile"] = tile
-    sm = pkg.Smoother(list(wl.tets), VARIANTS[variant], **kw)
+    sm = make_smoother(pkg, wl, variant, tile)
     b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
     x = torch.zeros_like(b)
     sm.pcg(x, b, 2, rel_tol=rel_tol, abs_tol=abs_tol)     # warm-up (captures the iteration graph)

@@ -63,6 +63,19 @@ extern "C" {
                             factor form L^p_d = A^p_d / A^{p+d}_c, D^p = A^p_c and
                             swept like ILU_STORED_F64 */
 
+/* operator in the residual b - A x */
+#define ILU_A_EXACT 0     /* the assembled FP64 stencil (8 values per point in HBM) */
+#define ILU_A_SURROGATE 1 /* surrogate polynomials for A as well (Sec. 4.3): the lower
+                             weights fitted on the sample sets S_d with the same
+                             degrees, the upper weights evaluated as the lower
+                             polynomials at p - d (symmetric), the centre as minus the
+                             sum of the 14 neighbour weights (the rows of the
+                             unrestricted A sum to zero), so r = b - sum_d A~_d
+                             (x_{p+d} - x_p); Horner per point in FP32 for ILU_SURR_F32,
+                             FP64 otherwise, FP64 accumulation.  Surrogate variants
+                             only; the degree must resolve the coefficient, or the
+                             iteration with A~ may diverge. */
+
 /* sweep schedules */
 #define ILU_SCHED_AUTO 0      /* persistent dataflow kernel */
 #define ILU_SCHED_PLANE 1     /* one launch per hyperplane (reference schedule) */
@@ -88,7 +101,8 @@ typedef struct ilu_opts {
                                with every shape (least-squares fit once), times a few
                                sweeps of each on the device and keeps the fastest
                                (hyperplane schedule: chosen from the levels) */
-    int32_t reserved[2];    /* must be 0 */
+    int32_t a_mode;         /* ILU_A_EXACT or ILU_A_SURROGATE */
+    int32_t reserved;       /* must be 0 */
 } ilu_opts;
 
 typedef struct ilu_handle_s *ilu_handle_t;
@@ -117,7 +131,8 @@ int ilu_smooth(ilu_handle_t h, double *x, const double *b, int32_t nsweeps, doub
                void *hip_stream);
 
 /* y = A x on the interior points (Sec. 2.1 stencil matvec), FP64 device
- * arrays in the layout above.  Stream-ordered. */
+ * arrays in the layout above; with ILU_A_SURROGATE the surrogate operator the
+ * smoother's residual uses.  Stream-ordered. */
 int stencil_apply(ilu_handle_t h, const double *x, double *y, void *hip_stream);
 
 /* Preconditioned conjugate gradients for A x = b with the handle's C^{-1} as
@@ -204,6 +219,14 @@ int ilu_get_factors(ilu_handle_t h, int32_t tet, double *L_out, double *D_out, v
  * ilu_set_surrogate replaces them (and rebuilds the evaluation tables). */
 int ilu_get_surrogate(ilu_handle_t h, int32_t tet, double *coeffs_out);
 int ilu_set_surrogate(ilu_handle_t h, int32_t tet, const double *coeffs, void *hip_stream);
+
+/* Surrogate coefficients of the operator (handles built with
+ * ILU_A_SURROGATE), host FP64 [8][K] in the layout of ilu_get_surrogate: row
+ * r < 7 fits A_d for the lower direction r; row 7 fits the centre A_c, which
+ * the operator does not use (its centre follows from the row sums).
+ * ilu_set_surrogate_a replaces them (and rebuilds the operator tables). */
+int ilu_get_surrogate_a(ilu_handle_t h, int32_t tet, double *coeffs_out);
+int ilu_set_surrogate_a(ilu_handle_t h, int32_t tet, const double *coeffs, void *hip_stream);
 
 /* Surrogate weights as the sweeps evaluate them, lexicographic order:
  * L_out device FP64 [N][7], Dinv_out device FP64 [N] (FP32 variants are

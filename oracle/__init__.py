@@ -411,20 +411,25 @@ def fit_operator_surrogate(level: int, A: np.ndarray, degree, stride: int, basis
 
 
 def eval_operator_surrogate(level: int, coeffs: np.ndarray, degree, basis: str = "legendre") -> np.ndarray:
-    """The surrogate stencil in the (N,15) layout: lower weights and the
-    centre from their polynomials at p, and the upper weight of direction
-    -d_k as the lower polynomial k at p - d_k (A^p_{-d} = A^{p-d}_d, so the
-    surrogate operator stays symmetric).  Entries whose neighbour is not
-    interior multiply nothing."""
+    """The surrogate stencil in the (N,15) layout: lower weights from their
+    polynomials at p, the upper weight of direction -d_k as the lower
+    polynomial k at p - d_k (A^p_{-d} = A^{p-d}_d, so the surrogate stays
+    symmetric), and the centre from the zero row sums of the unrestricted
+    operator, A_c = -(sum of the 14 neighbour weights), because
+    a(phi_p, 1) = 0 for every coefficient (Sec. 2.1).  The fitted centre
+    polynomial (row 7) is not used: a fitted centre breaks the row sums by
+    the fit error, which is far larger than the O(h^3) smallest eigenvalues
+    of A and makes the iteration diverge at fine levels.  Entries whose
+    neighbour is not interior multiply nothing (they still enter the centre)."""
     pts = interior_points(level).astype(np.float64)
     n = 1 << level
     mat = legendre_tensor_matrix if basis == "legendre" else monomial_tensor_matrix
     out = np.zeros((len(pts), 15))
     vals = mat(pts / n, degree) @ coeffs.T
     out[:, :NLOW] = vals[:, :NLOW]
-    out[:, CENTRE] = vals[:, NLOW]
     for k in range(NLOW):
         out[:, 8 + k] = mat((pts - DIRS[k]) / n, degree) @ coeffs[k]
+    out[:, CENTRE] = -(out[:, :NLOW].sum(axis=1) + out[:, 8:].sum(axis=1))
     return out
 
 

@@ -11,6 +11,7 @@ HEADER = os.path.join(HERE, "..", "include", "ilu.h")
 
 STORED_F64, SURR_F64, SURR_F32, STORED_SGS = 0, 1, 2, 3
 SCHED_AUTO, SCHED_PLANE, SCHED_DATAFLOW = 0, 1, 2
+A_EXACT, A_SURROGATE = 0, 1
 COEFF_CONST, COEFF_SINPROD, COEFF_EXPSINCOS, COEFF_POLY = 0, 1, 2, 3
 
 
@@ -25,7 +26,8 @@ class ilu_tet_desc(ctypes.Structure):
 
 class ilu_opts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("degree", ctypes.c_int32 * 3), ("sample_stride", ctypes.c_int32),
-                ("schedule", ctypes.c_int32), ("tile", ctypes.c_int32 * 2), ("reserved", ctypes.c_int32 * 2)]
+                ("schedule", ctypes.c_int32), ("tile", ctypes.c_int32 * 2), ("a_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ILUError(RuntimeError):
@@ -66,6 +68,8 @@ def lib():
         L.ilu_get_factors.argtypes = [P, I32, P, P, P]
         L.ilu_get_surrogate.argtypes = [P, I32, P]
         L.ilu_set_surrogate.argtypes = [P, I32, P, P]
+        L.ilu_get_surrogate_a.argtypes = [P, I32, P]
+        L.ilu_set_surrogate_a.argtypes = [P, I32, P, P]
         L.ilu_get_surrogate_values.argtypes = [P, I32, P, P, P]
         L.ilu_sample_stride.argtypes = [P, I32, ctypes.POINTER(I32)]
         L.ilu_tile.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
@@ -137,7 +141,7 @@ class Smoother:
     in lexicographic order, concatenated (see ``offsets``)."""
 
     def __init__(self, tets: Sequence, variant: int = STORED_F64, degree=4, stride: int = 4,
-                 schedule: int = SCHED_AUTO, tile=(0, 0), stream=None):
+                 schedule: int = SCHED_AUTO, tile=(0, 0), a_mode: int = A_EXACT, stream=None):
         import torch
         self.torch = torch
         self.L = lib()
@@ -150,6 +154,7 @@ class Smoother:
         opts.sample_stride = int(stride)
         opts.schedule = int(schedule)
         opts.tile[:] = [int(tile[0]), int(tile[1])]
+        opts.a_mode = int(a_mode)
         self.variant = variant
         self.degree = dg
         self.h = ctypes.c_void_p()
@@ -231,6 +236,18 @@ class Smoother:
         c = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(8, self.ncoef())
         _check(self.L.ilu_set_surrogate(self.h, tet, c.ctypes.data_as(ctypes.c_void_p), self._stream(None)),
                "ilu_set_surrogate")
+
+    def surrogate_a(self, tet: int = 0):
+        import numpy as np
+        c = np.zeros((8, self.ncoef()))
+        _check(self.L.ilu_get_surrogate_a(self.h, tet, c.ctypes.data_as(ctypes.c_void_p)), "ilu_get_surrogate_a")
+        return c
+
+    def set_surrogate_a(self, tet: int, coeffs):
+        import numpy as np
+        c = np.ascontiguousarray(coeffs, dtype=np.float64).reshape(8, self.ncoef())
+        _check(self.L.ilu_set_surrogate_a(self.h, tet, c.ctypes.data_as(ctypes.c_void_p), self._stream(None)),
+               "ilu_set_surrogate_a")
 
     def surrogate_values(self, tet: int = 0):
         L = self.torch.zeros((self.counts[tet], 7), dtype=self.torch.float64, device="cuda")

@@ -105,6 +105,9 @@ struct ilu_handle_s {
     hipStream_t cap = nullptr;           // private stream the sweep graph is captured on
     hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
     DevBuf cg_r, cg_z, cg_p, cg_q, cg_sc;  // PCG vectors (stream layout) and scalars
+    int a_mode = ILU_A_EXACT;            // operator of the residual
+    DevBuf coefA_d, tabA64, tabA32;      // surrogate operator: coefficients and row tables
+    std::vector<double> coefA_h;
     hipGraphExec_t cg_exec = nullptr;    // one PCG iteration
 
     Ctx ctx() const {
@@ -129,6 +132,10 @@ struct ilu_handle_s {
         c.NC = NC;
         c.r = r.p;
         c.w = w.p;
+        if (a_mode == ILU_A_SURROGATE) {
+            if (variant == ILU_SURR_F32) c.tabA32 = tabA32.as<float>();
+            else c.tabA64 = tabA64.as<double>();
+        }
         return c;
     }
     Flow flow() const {
@@ -323,7 +330,7 @@ int read_flags(ilu_handle_t h, hipStream_t st, int32_t out[4]) {
 
 // Least squares for every (tet, fitted direction): TSQR with Householder
 // chunks, then back substitution (all on the device).
-int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st) {
+int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coef_out) {
     const int K = h->K, m = K + 1;
     const int chunk = 4 * m;
     const Ctx c = h->ctx();
@@ -387,31 +394,36 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st) {
         sj[p].out_off = (int64_t)p * m;
     }
     if (upload(jobs_d, sj, st)) return ILU_ENOMEM;
-    if (h->coef_d.alloc((size_t)np * K * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    launch_qr_solve(jobs_d.as<QrJob>(), np, m, finalR.as<double>(), h->coef_d.as<double>(), h->flags.as<int>(), st);
+    if (coef_out.alloc((size_t)np * K * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    launch_qr_solve(jobs_d.as<QrJob>(), np, m, finalR.as<double>(), coef_out.as<double>(), h->flags.as<int>(), st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
 }
 
-int build_tables(ilu_handle_t h, hipStream_t st) {
+// Per-row evaluation tables of one set of 8 fitted polynomials (the ILU
+// factors into tab64/tab32, or the operator into tabA64/tabA32); the FP32 copy
+// only for the mixed variant.
+int build_tables_from(ilu_handle_t h, hipStream_t st, const DevBuf& coef, DevBuf& t64, DevBuf& t32) {
     const int nslots = (int)h->blocks.size() * h->bv * h->bw;
     const size_t rec = 2 + 15 * (size_t)h->NC;
-    if (h->tab64.alloc(nslots * rec * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    if (h->variant == ILU_SURR_F32 && h->tab32.alloc(nslots * rec * sizeof(float), st) != hipSuccess)
-        return ILU_ENOMEM;
+    if (t64.alloc(nslots * rec * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    if (h->variant == ILU_SURR_F32 && t32.alloc(nslots * rec * sizeof(float), st) != hipSuccess) return ILU_ENOMEM;
     const Ctx c = h->ctx();
-    launch_row_tables(c, nslots, h->coef_d.as<double>(), h->NC, h->tab64.as<double>(),
-                      h->variant == ILU_SURR_F32 ? h->tab32.as<float>() : nullptr, st);
+    launch_row_tables(c, nslots, coef.as<double>(), h->NC, t64.as<double>(),
+                      h->variant == ILU_SURR_F32 ? t32.as<float>() : nullptr, st);
     HIPCHK(hipGetLastError());
     return ILU_OK;
 }
+
+int build_tables(ilu_handle_t h, hipStream_t st) { return build_tables_from(h, st, h->coef_d, h->tab64, h->tab32); }
 
 // Host-only preparation: validated tetrahedron records, sample layout, block tables.
 int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_handle_t h, int64_t* nsamples) {
     h->ntets = ntets;
     h->sgs = opts->variant == ILU_STORED_SGS;
     h->variant = h->sgs ? ILU_STORED_F64 : opts->variant;
+    h->a_mode = opts->a_mode;
     h->schedule = opts->schedule == ILU_SCHED_PLANE ? ILU_SCHED_PLANE : ILU_SCHED_DATAFLOW;
     const bool surr = h->variant != ILU_STORED_F64;
     for (int k = 0; k < 3; ++k) h->deg[k] = surr ? opts->degree[k] : 0;
@@ -485,7 +497,7 @@ void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target = nu
 // least-squares fit is skipped and these coefficients are used: the fit does
 // not depend on the block shape, so the tile autotuner fits once.
 int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t h,
-               const std::vector<double>* coef_in = nullptr) {
+               const std::vector<double>* coef_in = nullptr, const std::vector<double>* coefA_in = nullptr) {
     int64_t soff = 0;
     if (int e = prepare(tets, ntets, opts, h, &soff)) return e;
     const bool surr = h->variant != ILU_STORED_F64;
@@ -527,7 +539,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         if (samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         launch_gather_samples(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), samples.as<double>(), st);
         HIPCHK(hipGetLastError());
-        if (int e = solve_lsq(h, samples, st)) return e;
+        if (int e = solve_lsq(h, samples, st, h->coef_d)) return e;
         if (int e = read_flags(h, st, fl)) return e;
         if (fl[1]) return ILU_ERANK;
         h->coef_h.resize((size_t)ntets * NFIT * h->K);
@@ -537,6 +549,28 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         // the exact factors are only needed during setup for the surrogate variants
         h->Lf.release();
         h->Df.release();
+    }
+    // surrogate operator: the centre and lower stencil weights sampled on the
+    // same sets and fitted like the factors (or injected by the autotuner)
+    if (h->a_mode == ILU_A_SURROGATE) {
+        if (coefA_in) {
+            h->coefA_h = *coefA_in;
+            if (h->coefA_d.alloc(h->coefA_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
+            HIPCHK(hipMemcpyAsync(h->coefA_d.p, h->coefA_h.data(), h->coefA_h.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+        } else {
+            DevBuf samples;
+            if (samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+            launch_gather_a_samples(h->ctx(), samples.as<double>(), st);
+            HIPCHK(hipGetLastError());
+            if (int e = solve_lsq(h, samples, st, h->coefA_d)) return e;
+            if (int e = read_flags(h, st, fl)) return e;
+            if (fl[1]) return ILU_ERANK;
+            h->coefA_h.resize((size_t)ntets * NFIT * h->K);
+            HIPCHK(hipMemcpyAsync(h->coefA_h.data(), h->coefA_d.p, h->coefA_h.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+        }
+        if (int e = build_tables_from(h, st, h->coefA_d, h->tabA64, h->tabA32)) return e;
     }
     // sweep buffers
     const size_t es = h->variant == ILU_SURR_F32 ? sizeof(float) : sizeof(double);
@@ -590,7 +624,8 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
     ilu_handle_t best = nullptr;
     double best_ms = 0.0;
     const std::vector<double>* coef = nullptr;
-    std::vector<double> coef_keep;
+    const std::vector<double>* coefA = nullptr;
+    std::vector<double> coef_keep, coefA_keep;
     for (const auto& sh : shapes) {
         if (opts->variant == ILU_SURR_F64 && opts->degree[0] >= 3 && sh[1] == 32) continue;
         ilu_opts o = *opts;
@@ -601,7 +636,7 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
             delete best;
             return ILU_ENOMEM;
         }
-        int rc = setup_impl(tets, ntets, &o, st, h, coef);
+        int rc = setup_impl(tets, ntets, &o, st, h, coef, coefA);
         double ms = 0.0;
         if (rc == ILU_OK) rc = time_sweep(h, st, 3, &ms);
         if (rc != ILU_OK) {
@@ -613,6 +648,10 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
         if (h->variant != ILU_STORED_F64 && !coef) {
             coef_keep = h->coef_h;
             coef = &coef_keep;
+            if (h->a_mode == ILU_A_SURROGATE) {
+                coefA_keep = h->coefA_h;
+                coefA = &coefA_keep;
+            }
         }
         if (!best || ms < best_ms) {
             delete best;
@@ -901,6 +940,18 @@ int capture_sweep(ilu_handle_t h, const Ctx& c) {
     return ILU_OK;
 }
 
+// Forget the captured graphs (they are recaptured on the next call): their
+// kernel nodes hold buffer addresses that a table rebuild replaces.
+int drop_graphs(ilu_handle_t h, hipStream_t st) {
+    (void)st;
+    HIPCHK(hipDeviceSynchronize());  // a replay may be in flight on any stream
+    if (h->gexec) HIPCHK(hipGraphExecDestroy(h->gexec));
+    if (h->cg_exec) HIPCHK(hipGraphExecDestroy(h->cg_exec));
+    h->gexec = nullptr;
+    h->cg_exec = nullptr;
+    return ILU_OK;
+}
+
 double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
     double v = 0.0;
     *err = hipMemcpyAsync(&v, h->norms.as<double>() + slot, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -913,8 +964,10 @@ double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
 namespace {
 int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
     if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_STORED_SGS) return ILU_EINVAL;
-    for (int k = 0; k < 2; ++k)
-        if (opts->reserved[k]) return ILU_EINVAL;
+    if (opts->reserved) return ILU_EINVAL;
+    if (opts->a_mode != ILU_A_EXACT && opts->a_mode != ILU_A_SURROGATE) return ILU_EINVAL;
+    if (opts->a_mode == ILU_A_SURROGATE && opts->variant != ILU_SURR_F64 && opts->variant != ILU_SURR_F32)
+        return ILU_EINVAL;
     if ((opts->tile[0] || opts->tile[1]) && !flow_shape_supported(opts->tile[0], opts->tile[1])) return ILU_EINVAL;
     if (opts->variant == ILU_SURR_F64 || opts->variant == ILU_SURR_F32) {
         for (int k = 0; k < 3; ++k)
@@ -1319,7 +1372,26 @@ int ilu_set_surrogate(ilu_handle_t h, int32_t tet, const double* coeffs, void* h
     std::memcpy(h->coef_h.data() + (size_t)tet * NFIT * h->K, coeffs, (size_t)NFIT * h->K * sizeof(double));
     HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double), hipMemcpyHostToDevice,
                           st));
+    if (int e = drop_graphs(h, st)) return e;  // captured launches hold the old table pointers
     if (int e = build_tables(h, st)) return e;
+    HIPCHK(hipStreamSynchronize(st));
+    return ILU_OK;
+}
+
+int ilu_get_surrogate_a(ilu_handle_t h, int32_t tet, double* coeffs_out) {
+    if (!h || !coeffs_out || tet < 0 || tet >= h->ntets || h->a_mode != ILU_A_SURROGATE) return ILU_EINVAL;
+    std::memcpy(coeffs_out, h->coefA_h.data() + (size_t)tet * NFIT * h->K, (size_t)NFIT * h->K * sizeof(double));
+    return ILU_OK;
+}
+
+int ilu_set_surrogate_a(ilu_handle_t h, int32_t tet, const double* coeffs, void* hip_stream) {
+    if (!h || !coeffs || tet < 0 || tet >= h->ntets || h->a_mode != ILU_A_SURROGATE) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::memcpy(h->coefA_h.data() + (size_t)tet * NFIT * h->K, coeffs, (size_t)NFIT * h->K * sizeof(double));
+    HIPCHK(hipMemcpyAsync(h->coefA_d.p, h->coefA_h.data(), h->coefA_h.size() * sizeof(double),
+                          hipMemcpyHostToDevice, st));
+    if (int e = drop_graphs(h, st)) return e;
+    if (int e = build_tables_from(h, st, h->coefA_d, h->tabA64, h->tabA32)) return e;
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
 }

@@ -28,6 +28,10 @@ struct Ctx {
     int NC = 0;                   // dg_x + 1
     void* r = nullptr;            // residual stream (FP64, or FP32 for the mixed variant)
     void* w = nullptr;            // substitution stream (same type as r)
+    // surrogate operator (null: the residual uses the assembled A8): per-row
+    // records [xm, 1/hw, lower 7*NC, centre NC, upper 7*NC], FP32 for the mixed variant
+    const double* tabA64 = nullptr;
+    const float* tabA32 = nullptr;
 };
 
 }  // namespace ilu

@@ -18,6 +18,8 @@ void launch_assemble(const Ctx& c, double* A8, double* Afull, hipStream_t st);
 void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags, hipStream_t st);
 void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st);
 void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st);
+// samples of the assembled stencil (centre and lower weights) on the same sample sets
+void launch_gather_a_samples(const Ctx& c, double* samples, hipStream_t st);
 void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
                       const double* samples, const double* in, double* out, double* scratch, int grid, int nchunks,
                       hipStream_t st);

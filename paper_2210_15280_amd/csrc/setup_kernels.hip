@@ -164,7 +164,8 @@ __device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz) 
 
 __global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                  const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S, const double* __restrict__ Lf,
-                                 const double* __restrict__ Df, double* __restrict__ samples) {
+                                 const double* __restrict__ Df, const double* __restrict__ A8,
+                                 double* __restrict__ samples) {
     int b, lane;
     decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
@@ -183,7 +184,9 @@ __global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev
             if (!interior(n, x + dx, y + dy, z + dz)) continue;
             const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
             const int64_t si = simplex_index(T.samp_M[f], kx, ky, kz);
-            samples[T.samp_off[f] + si] = f < NLOW ? Lf[(int64_t)f * S + idx] : 1.0 / Df[idx];
+            // ILU fit: L^p_d and 1/D^p; operator fit (A8 given): A^p_d and A^p_c
+            samples[T.samp_off[f] + si] = A8 ? (f < NLOW ? A8[(int64_t)(1 + f) * S + idx] : A8[idx])
+                                             : (f < NLOW ? Lf[(int64_t)f * S + idx] : 1.0 / Df[idx]);
         }
     }
 }
@@ -462,7 +465,13 @@ void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* 
 }
 
 void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st) {
-    k_gather_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df, samples);
+    k_gather_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df,
+                                                           nullptr, samples);
+}
+
+void launch_gather_a_samples(const Ctx& c, double* samples, hipStream_t st) {
+    k_gather_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, nullptr,
+                                                           nullptr, c.A8, samples);
 }
 
 void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,

@@ -79,6 +79,89 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
     if (threadIdx.x == 0 && partial) partial[it.id] = red[0];
 }
 
+// Residual with the surrogate operator (Sec. 4.3 approximates A by surrogate
+// polynomials too): the neighbour weights come from the row's table -- the
+// seven lower weights at p, the seven upper weights as the lower polynomials
+// at p - d -- evaluated by Horner in the table's precision TT, and the centre
+// is minus their sum (the full rows of A sum to zero, a(phi_p, 1) = 0), so
+//     r = b - sum_{d != c} A~_d (x_{p+d} - x_p)
+// in FP64.  A fitted centre would break the row sums by the fit error, which
+// exceeds the O(h^3) smallest eigenvalues of A at fine levels.  Per point it
+// loads x at p and its 14 neighbours and b, and no stencil weights.  One
+// point per thread and iteration.
+template <int NC, typename TT>
+__device__ __forceinline__ TT horner_c(const TT* c, TT eta) {
+    TT acc = c[NC - 1];
+#pragma unroll
+    for (int i = NC - 2; i >= 0; --i) acc = acc * eta + c[i];
+    return acc;
+}
+
+template <typename RT, typename TT, int NC, bool SUB>
+__global__ void __launch_bounds__(256) k_residual_sa(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                                     const LaneDev* __restrict__ lanes, int lpb, int groups,
+                                                     int nblocks, const TT* __restrict__ tab,
+                                                     const double* __restrict__ x, const double* __restrict__ b,
+                                                     RT* __restrict__ r, double* __restrict__ partial) {
+    __shared__ double red[256];
+    const Item it = res_item(groups, nblocks);
+    const int sub = threadIdx.x >> 6;
+    double acc2 = 0.0;
+    const int64_t slot = (int64_t)(it.live ? it.blk : 0) * lpb + (it.live ? it.lane : 0);
+    const BlockDev& B = blocks[it.live ? it.blk : 0];
+    const LaneDev& Ln = lanes[slot];
+    const int t0 = B.tb + it.chunk * RES_T;
+    if (it.live && t0 <= B.te) {
+        const int n = tets[B.tet].n, v = Ln.v, w = Ln.w;
+        const bool valid = v != 0;
+        const int64_t rs = Ln.rp[R_SELF];
+        int64_t rpl[NLOW], rpu[NLOW];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s) {
+            rpl[s] = Ln.rp[low_row(s)] + (int64_t)lpb * low_dt(s);
+            rpu[s] = Ln.rp[up_row(s)] + (int64_t)lpb * up_dt(s);
+        }
+        // row record [xm, 1/hw, lower 7*NC, centre NC (unused), upper 7*NC] (zeros for unused lanes)
+        const TT* tr = tab + slot * (2 + 15 * NC);
+        const TT xm = tr[0], ihw = tr[1];
+        TT c[15 * NC];
+#pragma unroll
+        for (int i = 0; i < 15 * NC; ++i) c[i] = tr[2 + i];
+        const int t1 = min(B.te, t0 + RES_T - 1);
+        for (int t = t0 + sub; t <= t1; t += 4) {
+            const int xx = t - 2 * v - w;
+            const bool act = valid && xx >= 1 && xx <= n - 1 - v;
+            // inactive points read the zero region, as in the assembled residual
+            const int64_t off = act ? (int64_t)lpb * t : 0;
+            const int64_t idx = act ? rs + off : 0;
+            double xl[NLOW], xu[NLOW];
+            const double xc = x[idx];
+#pragma unroll
+            for (int s = 0; s < NLOW; ++s) {
+                xl[s] = x[act ? rpl[s] + off : 0];
+                xu[s] = x[act ? rpu[s] + off : 0];
+            }
+            const double bv = SUB ? b[idx] : 0.0;
+            const TT eta = ((TT)xx - xm) * ihw;
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < NLOW; ++s)
+                acc += (double)horner_c<NC>(c + s * NC, eta) * (xl[s] - xc) +
+                       (double)horner_c<NC>(c + (8 + s) * NC, eta) * (xu[s] - xc);
+            const double rv = act ? (SUB ? bv - acc : acc) : 0.0;
+            r[rs + (int64_t)lpb * t] = (RT)rv;
+            acc2 += rv * rv;
+        }
+    }
+    red[threadIdx.x] = acc2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && partial) partial[it.id] = red[0];
+}
+
 // sum of squares of a stream vector restricted to active points (for ||b||)
 __global__ void __launch_bounds__(256) k_sumsq(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                                const LaneDev* __restrict__ lanes, int lpb, int groups, int nblocks,
@@ -254,8 +337,38 @@ void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, dou
 
 int64_t res_partials(const Ctx& c) { return (int64_t)c.nblocks * c.groups * c.res_chunks; }
 
+namespace {
+template <typename TT, int NC>
+void launch_residual_sa(const Ctx& c, const TT* tab, const double* x, const double* b, void* r, bool f32, int subtract,
+                        double* partial, hipStream_t st) {
+    const dim3 grid((unsigned)(c.nblocks * c.groups), (unsigned)c.res_chunks);
+#define ILU_RSA_ARGS c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.nblocks, tab, x, b
+    if (f32 && subtract) k_residual_sa<float, TT, NC, true><<<grid, 256, 0, st>>>(ILU_RSA_ARGS, (float*)r, partial);
+    else if (f32) k_residual_sa<float, TT, NC, false><<<grid, 256, 0, st>>>(ILU_RSA_ARGS, (float*)r, partial);
+    else if (subtract) k_residual_sa<double, TT, NC, true><<<grid, 256, 0, st>>>(ILU_RSA_ARGS, (double*)r, partial);
+    else k_residual_sa<double, TT, NC, false><<<grid, 256, 0, st>>>(ILU_RSA_ARGS, (double*)r, partial);
+#undef ILU_RSA_ARGS
+}
+
+template <typename TT>
+void launch_residual_sa_nc(const Ctx& c, const TT* tab, const double* x, const double* b, void* r, bool f32,
+                           int subtract, double* partial, hipStream_t st) {
+    switch (c.NC) {
+    case 1: launch_residual_sa<TT, 1>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    case 2: launch_residual_sa<TT, 2>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    case 3: launch_residual_sa<TT, 3>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    case 4: launch_residual_sa<TT, 4>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    case 5: launch_residual_sa<TT, 5>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    case 6: launch_residual_sa<TT, 6>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    default: launch_residual_sa<TT, 7>(c, tab, x, b, r, f32, subtract, partial, st); break;
+    }
+}
+}  // namespace
+
 void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
                      hipStream_t st) {
+    if (c.tabA32) return launch_residual_sa_nc<float>(c, c.tabA32, x, b, r, f32, subtract, partial, st);
+    if (c.tabA64) return launch_residual_sa_nc<double>(c, c.tabA64, x, b, r, f32, subtract, partial, st);
     const dim3 grid((unsigned)(c.nblocks * c.groups), (unsigned)c.res_chunks);
 #define ILU_RES_ARGS c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.nblocks, c.S, c.A8, x, b
     if (f32 && subtract) k_residual<float, true><<<grid, 256, 0, st>>>(ILU_RES_ARGS, (float*)r, partial);

@@ -49,7 +49,7 @@ def _setup(P, tets, variant=0, degree=(4, 4, 4), stride=4, reserved=0, tile=(0, 
     o.variant = variant
     o.degree[:] = list(degree)
     o.sample_stride = stride
-    o.reserved[0] = reserved
+    o.reserved = reserved
     o.tile[:] = list(tile)
     h = ctypes.c_void_p()
     return P.lib().ilu_setup_surrogate(arr, len(tets), ctypes.byref(o), None, ctypes.byref(h))

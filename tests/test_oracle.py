@@ -675,8 +675,9 @@ def test_operator_surrogate_is_exact_for_polynomial_stencils(coeff, deg):
 
 def test_operator_surrogate_is_symmetric_and_close():
     # variable coefficient: the surrogate is symmetric by construction
-    # (upper weights are the lower polynomials at p - d) and within the fit
-    # error of A; its row sums vanish only approximately
+    # (upper weights are the lower polynomials at p - d), its full rows sum to
+    # zero like A's (the centre is minus the neighbour weights), and it is
+    # within the fit error of A
     t = W.make_tet(24, 5, *W.KAPPA_EXP, jitter=0.15)
     P = O.Problem.from_tet(t)
     c = O.fit_operator_surrogate(5, P.A, 3, O.effective_stride(5, 3, 4))
@@ -686,6 +687,7 @@ def test_operator_surrogate_is_symmetric_and_close():
         j = P.col[:, 8 + s]
         ok = j >= 0
         np.testing.assert_allclose(At[ok, 8 + s], At[j[ok], s], rtol=0, atol=1e-12 * np.abs(P.A).max())
+    np.testing.assert_allclose(At.sum(axis=1), 0.0, atol=1e-12 * np.abs(P.A).max())
     # the discrete L2 error of the fitted entries falls with the degree
     errs = []
     for deg in (1, 4):
@@ -693,3 +695,20 @@ def test_operator_surrogate_is_symmetric_and_close():
         At = O.eval_operator_surrogate(5, c, deg)
         errs.append(np.linalg.norm(At[m] - P.A[m]) / np.linalg.norm(P.A[m]))
     assert 1e-8 < errs[1] < errs[0]
+
+
+def test_operator_surrogate_keeps_the_smoother_contracting():
+    # with the centre from the row sums, the surrogate operator at a
+    # sufficient degree leaves the smoother's contraction that of A
+    t = W.make_tet(5, 6, *W.KAPPA_EXP, jitter=0.15)
+    P = O.Problem.from_tet(t)
+    L, U, D = P.ilu0()
+    deg = 6
+    s = O.effective_stride(6, deg, 4)
+    Lw, Dinv = O.eval_surrogate(6, O.fit_surrogate(6, L, D, deg, s), deg)
+    At = O.eval_operator_surrogate(6, O.fit_operator_surrogate(6, P.A, deg, s), deg)
+    z = np.zeros(P.N)
+    x0 = W.SplitMix64(1).uniform_array(P.N, -1.0, 1.0)
+    rho_a = O.contraction_factor(P, lambda y: P.smooth_stencil(Lw, Dinv, z, y, 1)[0], x0, 40)[0]
+    rho_s = O.contraction_factor(P, lambda y: P.smooth_stencil(Lw, Dinv, z, y, 1, A=At)[0], x0, 40)[0]
+    assert rho_s == pytest.approx(rho_a, rel=1e-3) and rho_s < 1.0
