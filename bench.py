@@ -54,19 +54,23 @@ def kernel_flops(variant: str, dg):
     return {"residual": res, "forward": 14 + 14 * dg, "backward": 16 + 16 * dg}
 
 
-# variant name -> (library variant, operator mode); *_sa: surrogate operator in the residual
-VARIANTS = {"stored_f64": (0, 0), "surr_f64": (1, 0), "surr_f32": (2, 0), "stored_sgs": (3, 0),
-            "surr_f64_sa": (1, 1), "surr_f32_sa": (2, 1)}
+# variant name -> (library variant, operator of the residual, boundary variant);
+# *_sa: surrogate operator in the residual; *_v1: stored exact factors at the
+# boundary points (their O(h^-2) bytes are left out of the per-point traffic)
+VARIANTS = {"stored_f64": (0, 0, 0), "surr_f64": (1, 0, 0), "surr_f32": (2, 0, 0), "stored_sgs": (3, 0, 0),
+            "surr_f64_sa": (1, 1, 0), "surr_f32_sa": (2, 1, 0), "surr_f64_v1": (1, 0, 1), "surr_f32_v1": (2, 0, 1)}
 STORED = ("stored_f64", "stored_sgs")
 DTYPES = {"surr_f32": "f32 (sweeps, surrogate evaluation) + f64 (residual, update)", "surr_f64": "f64",
           "stored_f64": "f64", "stored_sgs": "f64",
           "surr_f32_sa": "f32 (sweeps, surrogate evaluation) + f64 (residual with f32-evaluated surrogate operator, update)",
-          "surr_f64_sa": "f64 (surrogate operator)"}
+          "surr_f64_sa": "f64 (surrogate operator)",
+          "surr_f32_v1": "f32 (sweeps, surrogate evaluation, stored boundary factors) + f64 (residual, update)",
+          "surr_f64_v1": "f64 (stored boundary factors)"}
 
 
 def make_smoother(pkg, wl, variant, tile):
-    v, a_mode = VARIANTS[variant]
-    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride, a_mode=a_mode)
+    v, a_mode, boundary = VARIANTS[variant]
+    kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride, a_mode=a_mode, boundary=boundary)
     return pkg.Smoother(list(wl.tets), v, tile=tile, **kw)
 CONTRACTION_STEPS = 20
 CONTRACTION_SEED = 0x5EED

@@ -14,7 +14,7 @@
  * where C is either the exact ILU(0) (stored factors) or its surrogate: one
  * polynomial per lower stencil direction for L and one for 1/D, fitted by
  * least squares on the sample sets S_d (Sec. 4.1), evaluated on the fly
- * (Alg. 2, boundary variant V2).
+ * (Alg. 2), with the boundary variant V2 or V1 (ilu_opts.boundary).
  *
  * Vectors at this interface: FP64 device arrays, interior points of each
  * tetrahedron in lexicographic order (z slowest, then y, then x; x,y,z >= 1,
@@ -76,6 +76,18 @@ extern "C" {
                              only; the degree must resolve the coefficient, or the
                              iteration with A~ may diverge. */
 
+/* boundary stencils of the surrogate variants (Sec. 4.1) */
+#define ILU_BOUNDARY_V2 0 /* surrogates everywhere; weights whose neighbour is not interior
+                             are zeroed in the substitutions */
+#define ILU_BOUNDARY_V1 1 /* the exact factors L^p_d and 1/D^p of the boundary points (the
+                             O(h^-2) interior points with a stencil neighbour on the macro
+                             boundary: min(x,y,z) = 1 or x+y+z = n-1) are stored in compact
+                             arrays and used wherever the substitutions need a factor of
+                             such a point: L^p_d in the forward substitution at p, 1/D^p
+                             and L^p_d (as the weight of p + d) in the backward one.  The
+                             surrogate is used everywhere else.  Surrogate variants only;
+                             the setup runs the exact factorisation once more for it. */
+
 /* sweep schedules */
 #define ILU_SCHED_AUTO 0      /* persistent dataflow kernel */
 #define ILU_SCHED_PLANE 1     /* one launch per hyperplane (reference schedule) */
@@ -102,7 +114,7 @@ typedef struct ilu_opts {
                                sweeps of each on the device and keeps the fastest
                                (hyperplane schedule: chosen from the levels) */
     int32_t a_mode;         /* ILU_A_EXACT or ILU_A_SURROGATE */
-    int32_t reserved;       /* must be 0 */
+    int32_t boundary;       /* ILU_BOUNDARY_V2 or ILU_BOUNDARY_V1 (surrogate variants) */
 } ilu_opts;
 
 typedef struct ilu_handle_s *ilu_handle_t;
@@ -230,7 +242,8 @@ int ilu_set_surrogate_a(ilu_handle_t h, int32_t tet, const double *coeffs, void 
 
 /* Surrogate weights as the sweeps evaluate them, lexicographic order:
  * L_out device FP64 [N][7], Dinv_out device FP64 [N] (FP32 variants are
- * widened). */
+ * widened; with ILU_BOUNDARY_V1 the stored exact factors at the boundary
+ * points). */
 int ilu_get_surrogate_values(ilu_handle_t h, int32_t tet, double *L_out, double *Dinv_out, void *hip_stream);
 
 /* Effective sample stride chosen for tetrahedron `tet` (surrogate variants). */

@@ -13,6 +13,8 @@ Functions and the passage they follow:
   ilu0_stencil                 Sec. 3 stencil equations / Alg. 1
   smooth                       Sec. 2.1 Richardson smoother with C = L D L^T
   smooth_stencil(_f32)         Alg. 2 (variant V2), FP64 / FP32-mixed
+  Problem.boundary_points,     Sec. 4.1 boundary variant V1: boundary points and their
+    Problem.v1_weights         stored exact factors in place of the surrogate
   sample_set, fit_surrogate    Sec. 4.1 sample sets S_d and LSQ fit
   eval_surrogate               Sec. 4.1 surrogate polynomials
   fit/eval_operator_surrogate  Sec. 4.3 surrogate for the operator A itself
@@ -236,6 +238,25 @@ class Problem:
                                        _ptr(rel))
         return x, rel
 
+
+    def boundary_points(self):
+        """Mask (N,) of the boundary points of Sec. 4.1: interior points with at
+        least one of the 14 stencil neighbours on the macro boundary."""
+        return np.any(np.delete(self.col, CENTRE, axis=1) < 0, axis=1)
+
+    def v1_weights(self, Lw, Dinv, L, D):
+        """Boundary variant V1 (Sec. 4.1, the substitution algorithm with the
+        boundary layer): the exact factors L^p_d and 1/D^p of every boundary
+        point p replace its surrogate values.  The forward substitution at p
+        reads L^p_d, the backward substitution reads 1/D^p at p and L^p_d at
+        p + d, so replacing the per-point weights covers every use.  Returns
+        (Lw1 (N,7), Dinv1 (N,))."""
+        m = self.boundary_points()
+        Lw1 = np.array(Lw, dtype=np.float64)
+        Dinv1 = np.array(Dinv, dtype=np.float64)
+        Lw1[m] = L[m]
+        Dinv1[m] = 1.0 / D[m]
+        return Lw1, Dinv1
 
     def sgs_factors(self):
         """Symmetric Gauss-Seidel (Sec. 2.1): C = (D_A + L_A) D_A^{-1} (D_A + L_A)^T

@@ -12,6 +12,7 @@ HEADER = os.path.join(HERE, "..", "include", "ilu.h")
 STORED_F64, SURR_F64, SURR_F32, STORED_SGS = 0, 1, 2, 3
 SCHED_AUTO, SCHED_PLANE, SCHED_DATAFLOW = 0, 1, 2
 A_EXACT, A_SURROGATE = 0, 1
+BOUNDARY_V2, BOUNDARY_V1 = 0, 1
 COEFF_CONST, COEFF_SINPROD, COEFF_EXPSINCOS, COEFF_POLY = 0, 1, 2, 3
 
 
@@ -27,7 +28,7 @@ class ilu_tet_desc(ctypes.Structure):
 class ilu_opts(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("degree", ctypes.c_int32 * 3), ("sample_stride", ctypes.c_int32),
                 ("schedule", ctypes.c_int32), ("tile", ctypes.c_int32 * 2), ("a_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("boundary", ctypes.c_int32)]
 
 
 class ILUError(RuntimeError):
@@ -141,7 +142,8 @@ class Smoother:
     in lexicographic order, concatenated (see ``offsets``)."""
 
     def __init__(self, tets: Sequence, variant: int = STORED_F64, degree=4, stride: int = 4,
-                 schedule: int = SCHED_AUTO, tile=(0, 0), a_mode: int = A_EXACT, stream=None):
+                 schedule: int = SCHED_AUTO, tile=(0, 0), a_mode: int = A_EXACT, boundary: int = BOUNDARY_V2,
+                 stream=None):
         import torch
         self.torch = torch
         self.L = lib()
@@ -155,6 +157,7 @@ class Smoother:
         opts.schedule = int(schedule)
         opts.tile[:] = [int(tile[0]), int(tile[1])]
         opts.a_mode = int(a_mode)
+        opts.boundary = int(boundary)
         self.variant = variant
         self.degree = dg
         self.h = ctypes.c_void_p()

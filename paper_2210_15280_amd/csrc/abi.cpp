@@ -106,6 +106,9 @@ struct ilu_handle_s {
     hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
     DevBuf cg_r, cg_z, cg_p, cg_q, cg_sc;  // PCG vectors (stream layout) and scalars
     int a_mode = ILU_A_EXACT;            // operator of the residual
+    int boundary = ILU_BOUNDARY_V2;      // boundary stencils of the surrogate variants
+    int64_t v1_nf = 0, v1_nbk = 0;       // points of the V1 sets F and B
+    DevBuf v1f, v1b;                     // their factor planes (variant V1 only)
     DevBuf coefA_d, tabA64, tabA32;      // surrogate operator: coefficients and row tables
     std::vector<double> coefA_h;
     hipGraphExec_t cg_exec = nullptr;    // one PCG iteration
@@ -135,6 +138,12 @@ struct ilu_handle_s {
         if (a_mode == ILU_A_SURROGATE) {
             if (variant == ILU_SURR_F32) c.tabA32 = tabA32.as<float>();
             else c.tabA64 = tabA64.as<double>();
+        }
+        if (boundary == ILU_BOUNDARY_V1) {
+            c.v1f = v1f.p;
+            c.v1b = v1b.p;
+            c.v1f_stride = v1_nf + 1;
+            c.v1b_stride = v1_nbk + 1;
         }
         return c;
     }
@@ -249,6 +258,31 @@ int build_layout(ilu_handle_t h) {
         const int l = (w - B.W0) * bv + (v - B.V0);
         return B.base - (int64_t)B.tlo * lpb + l;
     };
+    // variant V1: the point sets F and B numbered row by row, rows of each
+    // tetrahedron in (w, v) order (independent of the block shape)
+    std::vector<std::vector<int32_t>> fbase(h->ntets), bbase(h->ntets);
+    int64_t nf = 0, nbk = 0;
+    for (int ti = 0; ti < h->ntets; ++ti) {
+        const int n = h->tets[ti].n;
+        fbase[ti].assign((size_t)n * n, -1);
+        bbase[ti].assign((size_t)n * n, -1);
+        for (int w = 1; w <= n - 3; ++w)
+            for (int v = w + 1; v <= n - 2; ++v) {
+                const int y = v - w, z = w, xmax = n - 1 - v;
+                fbase[ti][(size_t)v * n + w] = (int32_t)nf;
+                bbase[ti][(size_t)v * n + w] = (int32_t)nbk;
+                nf += v1f_count(xmax, y, z);
+                nbk += v1b_count(xmax, y, z);
+            }
+    }
+    if (nf >= ((int64_t)1 << 31) - 1 || nbk >= ((int64_t)1 << 31) - 1) return ILU_EINVAL;
+    h->v1_nf = nf;
+    h->v1_nbk = nbk;
+    auto base_of = [&](const std::vector<std::vector<int32_t>>& tab, int ti, int v, int w) -> int32_t {
+        const int n = h->tets[ti].n;
+        if (v < 2 || v > n - 2 || w < 1 || w > v - 1) return -1;
+        return tab[ti][(size_t)v * n + w];
+    };
     h->lanes.resize(h->blocks.size() * lpb);
     h->tmin = 1 << 30;
     h->tmax = 0;
@@ -277,6 +311,13 @@ int build_layout(ilu_handle_t h) {
             L.rp[R_VP] = rp_of(ti, v + 1, w);
             L.rp[R_WP] = rp_of(ti, v, w + 1);
             L.rp[R_VPWP] = rp_of(ti, v + 1, w + 1);
+            L.v1f[0] = valid ? base_of(fbase, ti, v, w) : -1;
+            L.v1f[1] = valid ? base_of(fbase, ti, v + 1, w) : -1;
+            L.v1f[2] = valid ? base_of(fbase, ti, v, w + 1) : -1;
+            L.v1f[3] = valid ? base_of(fbase, ti, v + 1, w + 1) : -1;
+            L.v1b = valid ? base_of(bbase, ti, v, w) : -1;
+            L.pad_ = 0;
+            if (valid && (v - w <= 2 || w == 1)) B.edge = 1;
         }
     }
     return ILU_OK;
@@ -424,6 +465,7 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
     h->sgs = opts->variant == ILU_STORED_SGS;
     h->variant = h->sgs ? ILU_STORED_F64 : opts->variant;
     h->a_mode = opts->a_mode;
+    h->boundary = opts->boundary;
     h->schedule = opts->schedule == ILU_SCHED_PLANE ? ILU_SCHED_PLANE : ILU_SCHED_DATAFLOW;
     const bool surr = h->variant != ILU_STORED_F64;
     for (int k = 0; k < 3; ++k) h->deg[k] = surr ? opts->degree[k] : 0;
@@ -493,6 +535,29 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
 void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
 void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target = nullptr);
 
+// Variant V1: the exact factors of set F, copied once from the full factor
+// arrays of the setup.
+int gather_v1f(ilu_handle_t h, hipStream_t st) {
+    const bool f32 = h->variant == ILU_SURR_F32;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    if (h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
+    launch_gather_v1f(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->v1f.p, f32, h->v1_nf + 1, st);
+    HIPCHK(hipGetLastError());
+    return ILU_OK;
+}
+
+// Variant V1: the backward weights of set B from F and the surrogate tables
+// (after every change of the surrogate coefficients).  The buffer is
+// allocated once; its last entries stay 0.
+int build_v1b(ilu_handle_t h, hipStream_t st) {
+    const bool f32 = h->variant == ILU_SURR_F32;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    if (!h->v1b.p && h->v1b.alloc((size_t)8 * (h->v1_nbk + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
+    launch_build_v1b(h->ctx(), h->tab64.as<double>(), h->v1f.p, h->v1_nf + 1, h->v1b.p, f32, h->v1_nbk + 1, st);
+    HIPCHK(hipGetLastError());
+    return ILU_OK;
+}
+
 // Full setup of one handle.  With `coef_in` (surrogate variants only) the
 // least-squares fit is skipped and these coefficients are used: the fit does
 // not depend on the block shape, so the tile autotuner fits once.
@@ -511,7 +576,8 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     HIPCHK(hipGetLastError());
     // factorisation on the hyperplane schedule
     int32_t fl[4];
-    if (refit) {
+    const bool v1 = h->boundary == ILU_BOUNDARY_V1;
+    if (refit || v1) {
         if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         const Ctx c = h->ctx();
@@ -526,10 +592,17 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     }
     if (!refit) {
         h->coef_h = *coef_in;
+        if (v1) {
+            if (int e = gather_v1f(h, st)) return e;
+            h->Lf.release();
+            h->Df.release();
+        }
         if (h->coef_d.alloc(h->coef_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
         HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double),
                               hipMemcpyHostToDevice, st));
         if (int e = build_tables(h, st)) return e;
+        if (v1)
+            if (int e = build_v1b(h, st)) return e;
     } else if (!surr) {
         if (h->Lb.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         launch_transpose(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->Lb.as<double>(), st);
@@ -547,6 +620,10 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
                               hipMemcpyDeviceToHost, st));
         if (int e = build_tables(h, st)) return e;
         // the exact factors are only needed during setup for the surrogate variants
+        if (v1) {
+            if (int e = gather_v1f(h, st)) return e;
+            if (int e = build_v1b(h, st)) return e;
+        }
         h->Lf.release();
         h->Df.release();
     }
@@ -587,7 +664,7 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     const size_t xwords = (size_t)h->XE * (h->variant == ILU_SURR_F32 ? 1 : 2);
     if (h->xch.alloc(std::max<size_t>(1, xwords) * sizeof(uint64_t), st) || h->ticket.alloc(4 * sizeof(int32_t), st))
         return ILU_ENOMEM;
-    h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->bv, h->bw));
+    h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->boundary == ILU_BOUNDARY_V1, h->bv, h->bw));
     for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
@@ -964,7 +1041,9 @@ double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
 namespace {
 int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
     if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_STORED_SGS) return ILU_EINVAL;
-    if (opts->reserved) return ILU_EINVAL;
+    if (opts->boundary != ILU_BOUNDARY_V2 && opts->boundary != ILU_BOUNDARY_V1) return ILU_EINVAL;
+    if (opts->boundary == ILU_BOUNDARY_V1 && opts->variant != ILU_SURR_F64 && opts->variant != ILU_SURR_F32)
+        return ILU_EINVAL;
     if (opts->a_mode != ILU_A_EXACT && opts->a_mode != ILU_A_SURROGATE) return ILU_EINVAL;
     if (opts->a_mode == ILU_A_SURROGATE && opts->variant != ILU_SURR_F64 && opts->variant != ILU_SURR_F32)
         return ILU_EINVAL;
@@ -1374,6 +1453,8 @@ int ilu_set_surrogate(ilu_handle_t h, int32_t tet, const double* coeffs, void* h
                           st));
     if (int e = drop_graphs(h, st)) return e;  // captured launches hold the old table pointers
     if (int e = build_tables(h, st)) return e;
+    if (h->boundary == ILU_BOUNDARY_V1)
+        if (int e = build_v1b(h, st)) return e;
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
 }

@@ -64,6 +64,27 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+template <int N>
+struct IC {
+    static constexpr int value = N;
+};
+
+template <bool C, typename A, typename B>
+struct Pick {
+    using type = B;
+};
+template <typename A, typename B>
+struct Pick<true, A, B> {
+    using type = A;
+};
+
+// Batch depth of the streamed path of variant V1 (blocks with a row y <= 2 or
+// z = 1): seven or eight factors per hyperplane ride along with the operands.
+template <typename T>
+constexpr int V1_UE() {
+    return sizeof(T) == 4 ? 4 : 2;
+}
+
 template <int NC, typename T>
 __device__ __forceinline__ T horner(const T* c, T eta) {
     T acc = c[NC - 1];
@@ -166,12 +187,13 @@ __device__ __forceinline__ T halo_take(const Halo& h, const uint64_t* xch, int n
 // halo load would otherwise also wait for the slow device-coherent stores
 // issued before it.  All paths pass the same barriers.
 
-template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
+template <typename T, bool STORED, bool V1, int U, int D, int NC, int BV, int BW>
 __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
     k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lf, const T* __restrict__ tab,
-               const T* __restrict__ r, T* __restrict__ w, const int32_t* __restrict__ order,
-               uint64_t* __restrict__ xch, int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+               const T* __restrict__ v1, int64_t v1s, const T* __restrict__ r, T* __restrict__ w,
+               const int32_t* __restrict__ order, uint64_t* __restrict__ xch, int32_t* __restrict__ ticket,
+               int32_t* __restrict__ flags) {
     constexpr int NT = BV * BW;
     constexpr int GW = BV + 1;
     constexpr int GC = (BV + 1) * (BW + 1);
@@ -261,7 +283,7 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
             const int cell = (wl + 1) * GW + (vl + 1);
             const LaneDev& Ln = lanes[(int64_t)b * NT + l];
             const bool valid = Ln.v != 0;
-            const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
+            const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w, y = v - wrow, xmax = n - 1 - v;
             const int64_t rp = Ln.rp[R_SELF];
             T coef[7 * (NC > 0 ? NC : 1)];
             T xm = 0, ihw = 0;
@@ -272,71 +294,117 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
 #pragma unroll
                 for (int i = 0; i < 7 * NC; ++i) coef[i] = c[2 + i];
             }
-            // Operands of two batches of U hyperplanes in flight, in ping-pong buffers:
-            // a batch issues the next batch's loads, then runs its U hyperplanes.  Every
-            // load and store is issued unconditionally (hyperplanes clamped to the block
-            // window; inactive points and unused lanes load from the zero region), so
-            // the number of memory operations between a load and its use is the same on
-            // every path and the wait before a use covers that load only.
-            constexpr int NL = STORED ? 7 * U : 1;
-            T rA[U], rB[U];
-            double LA[NL], LB[NL];
-            auto prefetch = [&](const int T0, T (&rx)[U], double (&Lx)[NL]) {
+            // MODE 0: factors from the stored arrays (STORED) or the surrogate only;
+            // V1, MODE 1 (no row with y = 1 or z = 1 in the block): the exact factors
+            // of the row's two boundary points x = 1 and x = xmax held in registers;
+            // V1, MODE 2: exact factors streamed from set F with the operands
+            // (zero entry for points outside F).
+            auto compute = [&](auto mode_c, auto u_c) {
+                constexpr int MODE = decltype(mode_c)::value, UU = decltype(u_c)::value;
+                using LT = typename Pick<STORED, double, T>::type;
+                // the lane's set index, read once (a lazy read inside the loop would
+                // sit in a branch and wait for every load in flight)
+                const int64_t f0 = V1 && valid ? (int64_t)Ln.v1f[0] : 0;
+                T P0[MODE == 1 ? 7 : 1], P1[MODE == 1 ? 7 : 1];
+                if constexpr (MODE == 1) {
+                    const int64_t j0 = valid ? f0 : v1s - 1;
+                    const int64_t j1 = valid ? f0 + (xmax >= 2 ? 1 : 0) : v1s - 1;
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    // inactive points read the (cache-resident) zero region, not padding
-                    const int t = min(T0 + q, te), xq = t - 2 * v - wrow;
-                    const int64_t i = valid && xq >= 1 && xq <= n - 1 - v ? rp + (int64_t)NT * t : 0;
-                    rx[q] = r[i];
-                    if (STORED)
-#pragma unroll
-                        for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = Lf[(int64_t)s * S + i];
-                }
-            };
-            auto batch = [&](const int T0, T (&rcur)[U], double (&Lcur)[NL], T (&rnxt)[U], double (&Lnxt)[NL]) {
-                prefetch(T0 + U, rnxt, Lnxt);
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int t = T0 + q;
-                    if (t > te) break;
-                    const int x = t - 2 * v - wrow;
-                    T val = (T)0;
-                    if (valid && x >= 1 && x <= n - 1 - v) {
-                        const T* g1 = grid + ((t - 1) & 3) * GC;
-                        const T* g2 = grid + ((t - 2) & 3) * GC;
-                        const T* g3 = grid + ((t - 3) & 3) * GC;
-                        // neighbours p + d: w (own, t-1), s (v-1, t-2), se (v-1, t-1), bnw (w-1, t-2),
-                        // bn (w-1, t-1), bc (v-1 w-1, t-3), be (v-1 w-1, t-2)
-                        const T nb[7] = {g1[cell], g2[cell - 1], g1[cell - 1], g2[cell - GW],
-                                         g1[cell - GW], g3[cell - GW - 1], g2[cell - GW - 1]};
-                        T acc = rcur[q];
-                        if (STORED) {
-#pragma unroll
-                            for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 7 + ORD[jj]] * nb[ORD[jj]];
-                        } else {
-                            const T eta = ((T)x - xm) * ihw;
-                            T Lv[7];
-#pragma unroll
-                            for (int s = 0; s < 7; ++s) Lv[s] = horner<NC>(coef + s * NC, eta);
-#pragma unroll
-                            for (int jj = 0; jj < 7; ++jj) acc -= Lv[ORD[jj]] * nb[ORD[jj]];
-                        }
-                        val = acc;
+                    for (int s = 0; s < 7; ++s) {
+                        P0[s] = v1[(int64_t)s * v1s + j0];
+                        P1[s] = v1[(int64_t)s * v1s + j1];
                     }
-                    // inactive points store 0 into a slot that stays 0 (own padding or the zero region)
-                    w[rp + (int64_t)NT * t] = val;
-                    grid[(t & 3) * GC + cell] = val;
-                    lds_barrier();
+                }
+                // Operands of two batches of UU hyperplanes in flight, in ping-pong buffers:
+                // a batch issues the next batch's loads, then runs its UU hyperplanes.  Every
+                // load and store is issued unconditionally (hyperplanes clamped to the block
+                // window; inactive points and unused lanes load from the zero region), so
+                // the number of memory operations between a load and its use is the same on
+                // every path and the wait before a use covers that load only.
+                constexpr int NL = (STORED || MODE == 2) ? 7 * UU : 1;
+                T rA[UU], rB[UU];
+                LT LA[NL], LB[NL];
+                auto prefetch = [&](const int T0, T (&rx)[UU], LT (&Lx)[NL]) {
+#pragma unroll
+                    for (int q = 0; q < UU; ++q) {
+                        // inactive points read the (cache-resident) zero region, not padding
+                        const int t = min(T0 + q, te), xq = t - 2 * v - wrow;
+                        const bool act = valid && xq >= 1 && xq <= xmax;
+                        const int64_t i = act ? rp + (int64_t)NT * t : 0;
+                        rx[q] = r[i];
+                        if constexpr (STORED) {
+#pragma unroll
+                            for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = Lf[(int64_t)s * S + i];
+                        }
+                        if constexpr (MODE == 2) {
+                            const int pos = v1f_pos_sel(xq, xmax, y, wrow);
+                            const int64_t j = act && pos >= 0 ? f0 + pos : v1s - 1;
+#pragma unroll
+                            for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = v1[(int64_t)s * v1s + j];
+                        }
+                    }
+                };
+                auto batch = [&](const int T0, T (&rcur)[UU], LT (&Lcur)[NL], T (&rnxt)[UU], LT (&Lnxt)[NL]) {
+                    prefetch(T0 + UU, rnxt, Lnxt);
+#pragma unroll
+                    for (int q = 0; q < UU; ++q) {
+                        const int t = T0 + q;
+                        if (t > te) break;
+                        const int x = t - 2 * v - wrow;
+                        T val = (T)0;
+                        if (valid && x >= 1 && x <= xmax) {
+                            const T* g1 = grid + ((t - 1) & 3) * GC;
+                            const T* g2 = grid + ((t - 2) & 3) * GC;
+                            const T* g3 = grid + ((t - 3) & 3) * GC;
+                            // neighbours p + d: w (own, t-1), s (v-1, t-2), se (v-1, t-1), bnw (w-1, t-2),
+                            // bn (w-1, t-1), bc (v-1 w-1, t-3), be (v-1 w-1, t-2)
+                            const T nb[7] = {g1[cell], g2[cell - 1], g1[cell - 1], g2[cell - GW],
+                                             g1[cell - GW], g3[cell - GW - 1], g2[cell - GW - 1]};
+                            T acc = rcur[q];
+                            if constexpr (STORED) {
+#pragma unroll
+                                for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 7 + ORD[jj]] * nb[ORD[jj]];
+                            } else {
+                                const T eta = ((T)x - xm) * ihw;
+                                T Lv[7];
+#pragma unroll
+                                for (int s = 0; s < 7; ++s) Lv[s] = horner<NC>(coef + s * NC, eta);
+                                // plain selects (no branches: the choice differs lane by lane)
+                                if constexpr (MODE == 1) {
+                                    const bool b0 = x == 1, b1 = x == xmax;
+#pragma unroll
+                                    for (int s = 0; s < 7; ++s) {
+                                        T sel = b1 ? P1[s] : Lv[s];
+                                        Lv[s] = b0 ? P0[s] : sel;
+                                    }
+                                } else if constexpr (MODE == 2) {
+                                    const bool bf = v1f_pos_sel(x, xmax, y, wrow) >= 0;
+#pragma unroll
+                                    for (int s = 0; s < 7; ++s) Lv[s] = bf ? (T)Lcur[q * 7 + s] : Lv[s];
+                                }
+#pragma unroll
+                                for (int jj = 0; jj < 7; ++jj) acc -= Lv[ORD[jj]] * nb[ORD[jj]];
+                            }
+                            val = acc;
+                        }
+                        // inactive points store 0 into a slot that stays 0 (own padding or the zero region)
+                        w[rp + (int64_t)NT * t] = val;
+                        grid[(t & 3) * GC + cell] = val;
+                        lds_barrier();
+                    }
+                };
+                __syncthreads();
+                prefetch(tb, rA, LA);
+                __syncthreads();
+                for (int T0 = tb; T0 <= te; T0 += 2 * UU) {
+                    batch(T0, rA, LA, rB, LB);
+                    if (T0 + UU > te) break;
+                    batch(T0 + UU, rB, LB, rA, LA);
                 }
             };
-            __syncthreads();
-            prefetch(tb, rA, LA);
-            __syncthreads();
-            for (int T0 = tb; T0 <= te; T0 += 2 * U) {
-                batch(T0, rA, LA, rB, LB);
-                if (T0 + U > te) break;
-                batch(T0 + U, rB, LB, rA, LA);
-            }
+            if constexpr (!V1) compute(IC<0>{}, IC<U>{});
+            else if (B.edge) compute(IC<2>{}, IC<V1_UE<T>()>{});
+            else compute(IC<1>{}, IC<U>{});
         }
         __syncthreads();
     }
@@ -344,12 +412,13 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
 
 // ----------------------------------------------------------------- backward
 
-template <typename T, bool STORED, int U, int D, int NC, int BV, int BW>
+template <typename T, bool STORED, bool V1, int U, int D, int NC, int BV, int BW>
 __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
     k_bwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lb, const T* __restrict__ tab,
-               const T* __restrict__ w, double* __restrict__ xs, const int32_t* __restrict__ order,
-               uint64_t* __restrict__ xch, int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+               const T* __restrict__ v1, int64_t v1s, const T* __restrict__ w, double* __restrict__ xs,
+               const int32_t* __restrict__ order, uint64_t* __restrict__ xch, int32_t* __restrict__ ticket,
+               int32_t* __restrict__ flags) {
     constexpr int NT = BV * BW;
     constexpr int GW = BV + 1;
     constexpr int GC = (BV + 1) * (BW + 1);
@@ -435,7 +504,7 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
             const int cell = wl * GW + vl;
             const LaneDev& Ln = lanes[(int64_t)b * NT + l];
             const bool valid = Ln.v != 0;
-            const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w;
+            const int n = tets[B.tet].n, v = Ln.v, wrow = Ln.w, y = v - wrow, xmax = n - 1 - v;
             const int64_t rp = Ln.rp[R_SELF];
             T coef[8 * (NC > 0 ? NC : 1)];
             T xm = 0, ihw = 0;
@@ -446,71 +515,118 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
 #pragma unroll
                 for (int i = 0; i < 8 * NC; ++i) coef[i] = c[2 + 7 * NC + i];
             }
-            // ping-pong operand buffers and unconditional memory operations, as in the
-            // forward sweep
-            constexpr int NL = STORED ? 8 * U : 1;
-            T wA[U], wB[U];
-            double xA[U], xB[U];
-            double LA[NL], LB[NL];
-            auto prefetch = [&](const int T0, T (&wx)[U], double (&xx)[U], double (&Lx)[NL]) {
+            // MODE 0: weights from the stored arrays (STORED) or the surrogate only;
+            // V1, MODE 1 (no row with y <= 2 or z = 1 in the block): the weights of the
+            // row's points of set B (x in {1, 2, xmax-1, xmax}) held in registers;
+            // V1, MODE 2: weights of set B streamed with the operands.
+            auto compute = [&](auto mode_c, auto u_c) {
+                constexpr int MODE = decltype(mode_c)::value, UU = decltype(u_c)::value;
+                using LT = typename Pick<STORED, double, T>::type;
+                // the lane's set index, read once (see the forward sweep)
+                const int64_t b0 = V1 && valid ? (int64_t)Ln.v1b : 0;
+                T P[MODE == 1 ? 32 : 1];
+                if constexpr (MODE == 1) {
+                    const int cnt = valid ? v1b_count(xmax, y, wrow) : 0;
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int t = max(T0 - q, tb), xq = t - 2 * v - wrow;
-                    const int64_t i = valid && xq >= 1 && xq <= n - 1 - v ? rp + (int64_t)NT * t : 0;
-                    wx[q] = w[i];
-                    xx[q] = xs[i];
-                    if (STORED)
+                    for (int k = 0; k < 4; ++k) {
+                        const int64_t j = k < cnt ? b0 + k : v1s - 1;
 #pragma unroll
-                        for (int s = 0; s < 8; ++s) Lx[q * 8 + s] = Lb[(int64_t)s * S + i];
-                }
-            };
-            auto batch = [&](const int T0, T (&wcur)[U], double (&xcur)[U], double (&Lcur)[NL], T (&wnxt)[U],
-                             double (&xnxt)[U], double (&Lnxt)[NL]) {
-                prefetch(T0 - U, wnxt, xnxt, Lnxt);
-#pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    const int t = T0 - q;
-                    if (t < tb) break;
-                    const int x = t - 2 * v - wrow;
-                    T val = (T)0;
-                    if (valid && x >= 1 && x <= n - 1 - v) {
-                        const T* g1 = grid + ((t + 1) & 3) * GC;
-                        const T* g2 = grid + ((t + 2) & 3) * GC;
-                        const T* g3 = grid + ((t + 3) & 3) * GC;
-                        // upper neighbours p - d: e (own, t+1), n (v+1, t+2), nw (v+1, t+1),
-                        // tse (w+1, t+2), ts (w+1, t+1), tc (v+1 w+1, t+3), tw (v+1 w+1, t+2)
-                        const T nb[7] = {g1[cell], g2[cell + 1], g1[cell + 1], g2[cell + GW],
-                                         g1[cell + GW], g3[cell + GW + 1], g2[cell + GW + 1]};
-                        T acc;
-                        if (STORED) {
-                            acc = wcur[q] * (T)Lcur[q * 8];
-#pragma unroll
-                            for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 8 + 1 + ORD[jj]] * nb[ORD[jj]];
-                        } else {
-                            const T eta = ((T)x - xm) * ihw;
-                            T Uv[7];
-#pragma unroll
-                            for (int s = 0; s < 7; ++s) Uv[s] = horner<NC>(coef + (1 + s) * NC, eta);
-                            acc = wcur[q] * horner<NC>(coef, eta);
-#pragma unroll
-                            for (int jj = 0; jj < 7; ++jj) acc -= Uv[ORD[jj]] * nb[ORD[jj]];
-                        }
-                        val = acc;
+                        for (int e = 0; e < 8; ++e) P[k * 8 + e] = v1[(int64_t)e * v1s + j];
                     }
-                    // inactive points write their (zero) x slot back unchanged
-                    xs[rp + (int64_t)NT * t] = xcur[q] + (double)val;
-                    grid[(t & 3) * GC + cell] = val;
-                    lds_barrier();
+                }
+                // ping-pong operand buffers and unconditional memory operations, as in the
+                // forward sweep
+                constexpr int NL = (STORED || MODE == 2) ? 8 * UU : 1;
+                T wA[UU], wB[UU];
+                double xA[UU], xB[UU];
+                LT LA[NL], LB[NL];
+                auto prefetch = [&](const int T0, T (&wx)[UU], double (&xx)[UU], LT (&Lx)[NL]) {
+#pragma unroll
+                    for (int q = 0; q < UU; ++q) {
+                        const int t = max(T0 - q, tb), xq = t - 2 * v - wrow;
+                        const bool act = valid && xq >= 1 && xq <= xmax;
+                        const int64_t i = act ? rp + (int64_t)NT * t : 0;
+                        wx[q] = w[i];
+                        xx[q] = xs[i];
+                        if constexpr (STORED) {
+#pragma unroll
+                            for (int s = 0; s < 8; ++s) Lx[q * 8 + s] = Lb[(int64_t)s * S + i];
+                        }
+                        if constexpr (MODE == 2) {
+                            const int pos = v1b_pos_sel(xq, xmax, y, wrow);
+                            const int64_t j = act && pos >= 0 ? b0 + pos : v1s - 1;
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) Lx[q * 8 + e] = v1[(int64_t)e * v1s + j];
+                        }
+                    }
+                };
+                auto batch = [&](const int T0, T (&wcur)[UU], double (&xcur)[UU], LT (&Lcur)[NL], T (&wnxt)[UU],
+                                 double (&xnxt)[UU], LT (&Lnxt)[NL]) {
+                    prefetch(T0 - UU, wnxt, xnxt, Lnxt);
+#pragma unroll
+                    for (int q = 0; q < UU; ++q) {
+                        const int t = T0 - q;
+                        if (t < tb) break;
+                        const int x = t - 2 * v - wrow;
+                        T val = (T)0;
+                        if (valid && x >= 1 && x <= xmax) {
+                            const T* g1 = grid + ((t + 1) & 3) * GC;
+                            const T* g2 = grid + ((t + 2) & 3) * GC;
+                            const T* g3 = grid + ((t + 3) & 3) * GC;
+                            // upper neighbours p - d: e (own, t+1), n (v+1, t+2), nw (v+1, t+1),
+                            // tse (w+1, t+2), ts (w+1, t+1), tc (v+1 w+1, t+3), tw (v+1 w+1, t+2)
+                            const T nb[7] = {g1[cell], g2[cell + 1], g1[cell + 1], g2[cell + GW],
+                                             g1[cell + GW], g3[cell + GW + 1], g2[cell + GW + 1]};
+                            T acc;
+                            if constexpr (STORED) {
+                                acc = wcur[q] * (T)Lcur[q * 8];
+#pragma unroll
+                                for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 8 + 1 + ORD[jj]] * nb[ORD[jj]];
+                            } else {
+                                const T eta = ((T)x - xm) * ihw;
+                                T Wv[8];  // 1/D, then the seven upper weights
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) Wv[e] = horner<NC>(coef + e * NC, eta);
+                                // plain selects (no branches: the choice differs lane by lane)
+                                if constexpr (MODE == 1) {
+                                    const int pos = v1b_pos_sel(x, xmax, y, wrow);
+                                    const bool s0 = pos == 0, s1 = pos == 1, s2 = pos == 2, s3 = pos == 3;
+#pragma unroll
+                                    for (int e = 0; e < 8; ++e) {
+                                        T sel = s3 ? P[24 + e] : Wv[e];
+                                        sel = s2 ? P[16 + e] : sel;
+                                        sel = s1 ? P[8 + e] : sel;
+                                        Wv[e] = s0 ? P[e] : sel;
+                                    }
+                                } else if constexpr (MODE == 2) {
+                                    const bool bb = v1b_pos_sel(x, xmax, y, wrow) >= 0;
+#pragma unroll
+                                    for (int e = 0; e < 8; ++e) Wv[e] = bb ? (T)Lcur[q * 8 + e] : Wv[e];
+                                }
+                                acc = wcur[q] * Wv[0];
+#pragma unroll
+                                for (int jj = 0; jj < 7; ++jj) acc -= Wv[1 + ORD[jj]] * nb[ORD[jj]];
+                            }
+                            val = acc;
+                        }
+                        // inactive points write their (zero) x slot back unchanged
+                        xs[rp + (int64_t)NT * t] = xcur[q] + (double)val;
+                        grid[(t & 3) * GC + cell] = val;
+                        lds_barrier();
+                    }
+                };
+                __syncthreads();
+                prefetch(te, wA, xA, LA);
+                __syncthreads();
+                for (int T0 = te; T0 >= tb; T0 -= 2 * UU) {
+                    batch(T0, wA, xA, LA, wB, xB, LB);
+                    if (T0 - UU < tb) break;
+                    batch(T0 - UU, wB, xB, LB, wA, xA, LA);
                 }
             };
-            __syncthreads();
-            prefetch(te, wA, xA, LA);
-            __syncthreads();
-            for (int T0 = te; T0 >= tb; T0 -= 2 * U) {
-                batch(T0, wA, xA, LA, wB, xB, LB);
-                if (T0 - U < tb) break;
-                batch(T0 - U, wB, xB, LB, wA, xA, LA);
-            }
+            if constexpr (!V1) compute(IC<0>{}, IC<U>{});
+            else if (B.edge) compute(IC<2>{}, IC<V1_UE<T>()>{});
+            else compute(IC<1>{}, IC<U>{});
         }
         __syncthreads();
     }
@@ -553,49 +669,53 @@ constexpr int U_F32 = 8, D_F32 = 2;              // FP32 surrogate
 template <int BV, int BW>
 struct Shape {
     static constexpr int NT = BV * BW;
-    static const void* fwd_stored_ptr() { return (const void*)k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW>; }
-    static const void* bwd_stored_ptr() { return (const void*)k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW>; }
-    template <int NC>
-    static const void* fwd_ptr(int variant) {
-        if (variant == 1) return (const void*)k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW>;
-        return (const void*)k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW>;
+    static const void* fwd_stored_ptr() {
+        return (const void*)k_fwd_flow<double, true, false, U_F64, D_F64, 0, BV, BW>;
     }
-    template <int NC>
+    static const void* bwd_stored_ptr() {
+        return (const void*)k_bwd_flow<double, true, false, U_F64B, D_F64, 0, BV, BW>;
+    }
+    template <int NC, bool V1>
+    static const void* fwd_ptr(int variant) {
+        if (variant == 1) return (const void*)k_fwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW>;
+        return (const void*)k_fwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW>;
+    }
+    template <int NC, bool V1>
     static const void* bwd_ptr(int variant) {
-        if (variant == 1) return (const void*)k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW>;
-        return (const void*)k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW>;
+        if (variant == 1) return (const void*)k_bwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW>;
+        return (const void*)k_bwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW>;
     }
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
-        k_fwd_flow<double, true, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
-            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, (const double*)c.r, (double*)c.w, f.order_fwd,
-            f.xch, f.ticket, f.flags);
+        k_fwd_flow<double, true, false, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
+            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, nullptr, 0, (const double*)c.r, (double*)c.w,
+            f.order_fwd, f.xch, f.ticket, f.flags);
     }
     static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
-        k_bwd_flow<double, true, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
-            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, (const double*)c.w, x, f.order_bwd, f.xch,
-            f.ticket, f.flags);
+        k_bwd_flow<double, true, false, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
+            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, nullptr, 0, (const double*)c.w, x, f.order_bwd,
+            f.xch, f.ticket, f.flags);
     }
-    template <int NC>
+    template <int NC, bool V1>
     static void fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
-                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.r, (double*)c.w,
-                f.order_fwd, f.xch, f.ticket, f.flags);
+            k_fwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.v1f, c.v1f_stride,
+                (const double*)c.r, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
-                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.r, (float*)c.w,
-                f.order_fwd, f.xch, f.ticket, f.flags);
+            k_fwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.v1f, c.v1f_stride,
+                (const float*)c.r, (float*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
     }
-    template <int NC>
+    template <int NC, bool V1>
     static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
         if (variant == 1)
-            k_bwd_flow<double, false, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
-                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.w, x, f.order_bwd,
-                f.xch, f.ticket, f.flags);
+            k_bwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.v1b, c.v1b_stride,
+                (const double*)c.w, x, f.order_bwd, f.xch, f.ticket, f.flags);
         else
-            k_bwd_flow<float, false, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
-                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.w, x, f.order_bwd,
-                f.xch, f.ticket, f.flags);
+            k_bwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
+                c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.v1b, c.v1b_stride,
+                (const float*)c.w, x, f.order_bwd, f.xch, f.ticket, f.flags);
     }
 };
 
@@ -612,14 +732,22 @@ struct Shape {
     }
 
 template <int BV, int BW>
-int resident(int variant, int NC) {
+int resident(int variant, int NC, bool v1) {
     const void* kf = nullptr;
     const void* kb = nullptr;
     if (variant == 0) {
         kf = Shape<BV, BW>::fwd_stored_ptr();
         kb = Shape<BV, BW>::bwd_stored_ptr();
+    } else if (v1) {
+#define ILU_PTRS(N)                                                 \
+    (kf = Shape<BV, BW>::template fwd_ptr<N, true>(variant), \
+     kb = Shape<BV, BW>::template bwd_ptr<N, true>(variant))
+        ILU_NC_SWITCH(NC, ILU_PTRS)
+#undef ILU_PTRS
     } else {
-#define ILU_PTRS(N) (kf = Shape<BV, BW>::template fwd_ptr<N>(variant), kb = Shape<BV, BW>::template bwd_ptr<N>(variant))
+#define ILU_PTRS(N)                                                  \
+    (kf = Shape<BV, BW>::template fwd_ptr<N, false>(variant), \
+     kb = Shape<BV, BW>::template bwd_ptr<N, false>(variant))
         ILU_NC_SWITCH(NC, ILU_PTRS)
 #undef ILU_PTRS
     }
@@ -637,9 +765,15 @@ void run_fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         Shape<BV, BW>::fwd_stored(c, f, st);
         return;
     }
-#define ILU_FWD(N) Shape<BV, BW>::template fwd<N>(c, f, variant, st)
-    ILU_NC_SWITCH(c.NC, ILU_FWD)
+    if (c.v1f) {
+#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, true>(c, f, variant, st)
+        ILU_NC_SWITCH(c.NC, ILU_FWD)
 #undef ILU_FWD
+    } else {
+#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, false>(c, f, variant, st)
+        ILU_NC_SWITCH(c.NC, ILU_FWD)
+#undef ILU_FWD
+    }
 }
 
 template <int BV, int BW>
@@ -648,9 +782,15 @@ void run_bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st
         Shape<BV, BW>::bwd_stored(c, f, x, st);
         return;
     }
-#define ILU_BWD(N) Shape<BV, BW>::template bwd<N>(c, f, variant, x, st)
-    ILU_NC_SWITCH(c.NC, ILU_BWD)
+    if (c.v1b) {
+#define ILU_BWD(N) Shape<BV, BW>::template bwd<N, true>(c, f, variant, x, st)
+        ILU_NC_SWITCH(c.NC, ILU_BWD)
 #undef ILU_BWD
+    } else {
+#define ILU_BWD(N) Shape<BV, BW>::template bwd<N, false>(c, f, variant, x, st)
+        ILU_NC_SWITCH(c.NC, ILU_BWD)
+#undef ILU_BWD
+    }
 }
 
 }  // namespace
@@ -659,15 +799,15 @@ bool flow_shape_supported(int bv, int bw) {
     return (bv == 8 && bw == 8) || (bv == 16 && bw == 16) || (bv == 16 && bw == 32);
 }
 
-int flow_max_resident(int variant, int NC, int bv, int bw) {
+int flow_max_resident(int variant, int NC, bool v1, int bv, int bw) {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 1;
     int per_cu = 1;
-    if (bv == 8 && bw == 8) per_cu = resident<8, 8>(variant, NC);
-    else if (bv == 16 && bw == 16) per_cu = resident<16, 16>(variant, NC);
-    else per_cu = resident<16, 32>(variant, NC);
+    if (bv == 8 && bw == 8) per_cu = resident<8, 8>(variant, NC, v1);
+    else if (bv == 16 && bw == 16) per_cu = resident<16, 16>(variant, NC, v1);
+    else per_cu = resident<16, 32>(variant, NC, v1);
     if (per_cu < 1) per_cu = 1;
     return per_cu * cus;
 }

@@ -58,7 +58,7 @@ struct BlockDev {
     int32_t len;         // te - tb + 1 + 2 PAD stored steps
     int32_t pred[3];     // forward-sweep predecessors: (V-1,W), (V,W-1), (V-1,W-1); -1 if none
     int32_t succ[3];     // backward-sweep predecessors: (V+1,W), (V,W+1), (V+1,W+1)
-    int32_t pad_;
+    int32_t edge;        // some row with y <= 2 or z == 1 (variant V1: streamed factors)
     int64_t base;        // stream index of (tlo, lane 0)
     int64_t xoff;        // first entry of the block's exchange window: len x (BV + BW) entries
 };
@@ -69,7 +69,54 @@ struct BlockDev {
 struct LaneDev {
     int64_t rp[7];       // row pointers, RowSlot order; zero-region pointer if the row is outside
     int32_t v, w;        // row coordinates; v = 0 marks an unused lane
+    int32_t v1f[4];      // variant V1: first set-F index of the rows R_SELF, R_VP, R_WP, R_VPWP
+    int32_t v1b;         // variant V1: first set-B index of the own row (-1: row outside)
+    int32_t pad_;
 };
+
+// Point sets of variant V1 (Sec. 4.1), per row (y, z) with xmax = n-1-y-z:
+//   F, the boundary points: interior points with a stencil neighbour on the
+//      macro boundary, i.e. min(x, y, z) = 1 or x = xmax.  Their exact factors
+//      L^p_d and 1/D^p are stored.
+//   B, the points whose backward substitution may need a stored factor: F and
+//      every point with an upper neighbour p - d in F, which adds x = 2,
+//      y = 2 and x = xmax - 1 (upper offsets have dz >= 0, so no z = 2).
+// Rows with y == 1 or z == 1 lie wholly in F, rows with y <= 2 or z == 1
+// wholly in B; any other row holds x in {1, xmax} of F and x in
+// {1, 2, xmax-1, xmax} of B.  Points of a set are numbered row by row, x
+// ascending; *_pos is the position of x inside its row's run (-1: not in the set).
+__host__ __device__ inline bool v1f_whole(int y, int z) { return y == 1 || z == 1; }
+__host__ __device__ inline bool v1b_whole(int y, int z) { return y <= 2 || z == 1; }
+__host__ __device__ inline int v1f_count(int xmax, int y, int z) {
+    return xmax < 1 ? 0 : v1f_whole(y, z) ? xmax : (xmax < 2 ? xmax : 2);
+}
+__host__ __device__ inline int v1b_count(int xmax, int y, int z) {
+    return xmax < 1 ? 0 : v1b_whole(y, z) ? xmax : (xmax < 4 ? xmax : 4);
+}
+__host__ __device__ inline int v1f_pos(int x, int xmax, int y, int z) {
+    if (v1f_whole(y, z)) return x - 1;
+    if (x == 1) return 0;
+    if (x == xmax) return 1;
+    return -1;
+}
+__host__ __device__ inline int v1b_pos(int x, int xmax, int y, int z) {
+    if (v1b_whole(y, z) || xmax <= 4 || x <= 2) return x - 1;
+    if (x >= xmax - 1) return x - xmax + 3;
+    return -1;
+}
+// The same positions as selects only (no branches for the compiler to keep):
+// the sweep kernels evaluate them per lane on every hyperplane.
+__host__ __device__ inline int v1f_pos_sel(int x, int xmax, int y, int z) {
+    const bool whole = (y == 1) | (z == 1);
+    int p = x == xmax ? 1 : -1;
+    p = x == 1 ? 0 : p;
+    return whole ? x - 1 : p;
+}
+__host__ __device__ inline int v1b_pos_sel(int x, int xmax, int y, int z) {
+    const bool low = (y <= 2) | (z == 1) | (xmax <= 4) | (x <= 2);
+    const int p = x >= xmax - 1 ? x - xmax + 3 : -1;
+    return low ? x - 1 : p;
+}
 
 // Dataflow exchange buffer: word index of entry j (0 <= j < nx = BV + BW) at
 // hyperplane t of the block whose window starts at entry xoff and whose

@@ -28,7 +28,7 @@ struct Flow {
 void launch_flow_reset(const Flow& f, hipStream_t st);
 void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st);
 void launch_bwd_flow(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st);
-int flow_max_resident(int variant, int NC, int bv, int bw);
+int flow_max_resident(int variant, int NC, bool v1, int bv, int bw);
 bool flow_shape_supported(int bv, int bw);
 
 }  // namespace ilu

@@ -37,7 +37,7 @@ def test_strerror(P):
     assert L.ilu_strerror(-99) == b"unknown error"
 
 
-def _setup(P, tets, variant=0, degree=(4, 4, 4), stride=4, reserved=0, tile=(0, 0)):
+def _setup(P, tets, variant=0, degree=(4, 4, 4), stride=4, boundary=0, tile=(0, 0)):
     from paper_2210_15280_amd._lib import ilu_opts, ilu_tet_desc
     arr = (ilu_tet_desc * len(tets))()
     for i, t in enumerate(tets):
@@ -49,7 +49,7 @@ def _setup(P, tets, variant=0, degree=(4, 4, 4), stride=4, reserved=0, tile=(0, 
     o.variant = variant
     o.degree[:] = list(degree)
     o.sample_stride = stride
-    o.reserved = reserved
+    o.boundary = boundary
     o.tile[:] = list(tile)
     h = ctypes.c_void_p()
     return P.lib().ilu_setup_surrogate(arr, len(tets), ctypes.byref(o), None, ctypes.byref(h))
@@ -92,7 +92,8 @@ def test_invalid_arguments(P):
     assert _setup(P, [W.Tet(t.verts, 4, 9, (1.0, 0, 0, 0), 0)]) == -1      # coefficient kind
     assert _setup(P, [t], variant=1, degree=(7, 7, 7)) == -1                 # degree
     assert _setup(P, [t], variant=1, stride=3) == -1                         # stride not a power of two
-    assert _setup(P, [t], reserved=1) == -1
+    assert _setup(P, [t], variant=1, boundary=2) == -1                       # boundary variant
+    assert _setup(P, [t], variant=0, boundary=1) == -1                       # V1 needs a surrogate
     assert _setup(P, [t], tile=(8, 16)) == -1                                # unsupported block shape
     assert _setup(P, [t], variant=5) == -1
     L = P.lib()

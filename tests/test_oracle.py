@@ -447,6 +447,47 @@ def test_surrogate_error_counts_only_interior_neighbours():
     assert rel[7] == pytest.approx(eps, rel=1e-12)
 
 
+# ---------------------------------------------------------- boundary variant V1
+
+
+@pytest.mark.parametrize("level", [2, 3, 4, 5, 6])
+def test_boundary_points_closed_form(level):
+    # a stencil neighbour leaves the interior exactly when one of the four
+    # barycentric lattice coordinates (x, y, z, n-x-y-z) is 1, so the boundary
+    # points number C(n-1,3) - C(n-5,3): O(h^-2), four faces of ~n^2/2 points
+    t = W.make_tet(3, level, *W.KAPPA_SIN, jitter=0.15)
+    P = O.Problem.from_tet(t)
+    n = 1 << level
+    pts = O.interior_points(level)
+    bary = np.column_stack([pts, n - pts.sum(axis=1)])
+    m = P.boundary_points()
+    assert np.array_equal(m, bary.min(axis=1) == 1)
+    assert m.sum() == comb(n - 1, 3) - (comb(n - 5, 3) if n >= 5 else 0)
+
+
+def test_v1_with_exact_interior_is_the_ilu_smoother():
+    # V1 takes the exact factors at the boundary points: with the exact factors
+    # everywhere else and arbitrary values at the boundary points as the
+    # surrogate, its sweeps are the ILU(0) smoother of the matrix form, while
+    # the same weights without the replacement (V2) are far off.  Leaving any
+    # boundary weight (L or 1/D) unreplaced fails the first check.
+    t, P = _jittered(5, *W.KAPPA_EXP)
+    L, U, D = P.ilu0()
+    m = P.boundary_points()
+    rng = np.random.default_rng(5)
+    Lg = L.copy()
+    Lg[m] = rng.uniform(-0.5, 0.0, (m.sum(), 7))
+    Dg = 1.0 / D
+    Dg[m] = rng.uniform(0.5, 2.0, m.sum()) * Dg[m]
+    Lw1, Dinv1 = P.v1_weights(Lg, Dg, L, D)
+    b = t.rhs()
+    x, r = P.smooth(L, D, b, nsweeps=3)
+    x1, r1 = P.smooth_stencil(Lw1, Dinv1, b, nsweeps=3)
+    np.testing.assert_allclose(x1, x, rtol=0, atol=1e-13 * np.abs(x).max())
+    x2, _ = P.smooth_stencil(Lg, Dg, b, nsweeps=3)
+    assert np.abs(x2 - x).max() > 1e-2 * np.abs(x).max()
+
+
 # ---------------------------------------------------------------- contraction
 
 
