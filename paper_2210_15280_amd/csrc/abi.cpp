@@ -541,7 +541,7 @@ int gather_v1f(ilu_handle_t h, hipStream_t st) {
     const bool f32 = h->variant == ILU_SURR_F32;
     const size_t es = f32 ? sizeof(float) : sizeof(double);
     if (h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
-    launch_gather_v1f(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->v1f.p, f32, h->v1_nf + 1, st);
+    launch_gather_v1f(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->v1f.p, f32, st);
     HIPCHK(hipGetLastError());
     return ILU_OK;
 }
@@ -553,7 +553,7 @@ int build_v1b(ilu_handle_t h, hipStream_t st) {
     const bool f32 = h->variant == ILU_SURR_F32;
     const size_t es = f32 ? sizeof(float) : sizeof(double);
     if (!h->v1b.p && h->v1b.alloc((size_t)8 * (h->v1_nbk + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
-    launch_build_v1b(h->ctx(), h->tab64.as<double>(), h->v1f.p, h->v1_nf + 1, h->v1b.p, f32, h->v1_nbk + 1, st);
+    launch_build_v1b(h->ctx(), h->tab64.as<double>(), h->v1f.p, h->v1b.p, f32, st);
     HIPCHK(hipGetLastError());
     return ILU_OK;
 }

@@ -32,13 +32,14 @@ struct Ctx {
     // records [xm, 1/hw, lower 7*NC, centre NC, upper 7*NC], FP32 for the mixed variant
     const double* tabA64 = nullptr;
     const float* tabA32 = nullptr;
-    // variant V1 (null otherwise), FP32 for the mixed variant:
-    //   v1f: 8 planes [L_0..L_6, 1/D] of v1f_stride values, the exact factors of
-    //        the points of set F (boundary points);
-    //   v1b: 8 planes [1/D, L^{p-d}_d for d in D_l] of v1b_stride values, the
-    //        backward weights of the points of set B (exact where the point
-    //        holding the factor is in F, the surrogate elsewhere, 0 outside).
-    // The last entry of every plane is 0: points outside the sets read it.
+    // variant V1 (null otherwise), FP32 for the mixed variant; 8-value records,
+    // one per set point (one 32 B / 64 B read per point):
+    //   v1f: [L_0..L_6, 1/D], the exact factors of the points of set F
+    //        (boundary points), v1f_stride records;
+    //   v1b: [1/D, L^{p-d}_d for d in D_l], the backward weights of the points of
+    //        set B (exact where the point holding the factor is in F, the
+    //        surrogate elsewhere, 0 outside), v1b_stride records.
+    // The last record is 0: points outside the sets read it.
     const void* v1f = nullptr;
     const void* v1b = nullptr;
     int64_t v1f_stride = 0, v1b_stride = 0;

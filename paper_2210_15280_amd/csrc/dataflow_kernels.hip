@@ -85,6 +85,22 @@ constexpr int V1_UE() {
     return sizeof(T) == 4 ? 4 : 2;
 }
 
+// One 8-value record of the V1 sets (32 B FP32, 64 B FP64) in 16-byte loads.
+__device__ __forceinline__ void load8(const float* p, float (&o)[8]) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float4 b = *reinterpret_cast<const float4*>(p + 4);
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+}
+__device__ __forceinline__ void load8(const double* p, double (&o)[8]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 a = *reinterpret_cast<const double2*>(p + 2 * k);
+        o[2 * k] = a.x;
+        o[2 * k + 1] = a.y;
+    }
+}
+
 template <int NC, typename T>
 __device__ __forceinline__ T horner(const T* c, T eta) {
     T acc = c[NC - 1];
@@ -309,10 +325,13 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                 if constexpr (MODE == 1) {
                     const int64_t j0 = valid ? f0 : v1s - 1;
                     const int64_t j1 = valid ? f0 + (xmax >= 2 ? 1 : 0) : v1s - 1;
+                    T a[8], bq[8];
+                    load8(v1 + j0 * 8, a);
+                    load8(v1 + j1 * 8, bq);
 #pragma unroll
                     for (int s = 0; s < 7; ++s) {
-                        P0[s] = v1[(int64_t)s * v1s + j0];
-                        P1[s] = v1[(int64_t)s * v1s + j1];
+                        P0[s] = a[s];
+                        P1[s] = bq[s];
                     }
                 }
                 // Operands of two batches of UU hyperplanes in flight, in ping-pong buffers:
@@ -339,8 +358,10 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                         if constexpr (MODE == 2) {
                             const int pos = v1f_pos_sel(xq, xmax, y, wrow);
                             const int64_t j = act && pos >= 0 ? f0 + pos : v1s - 1;
+                            T a[8];
+                            load8(v1 + j * 8, a);
 #pragma unroll
-                            for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = v1[(int64_t)s * v1s + j];
+                            for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = a[s];
                         }
                     }
                 };
@@ -530,8 +551,10 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         const int64_t j = k < cnt ? b0 + k : v1s - 1;
+                        T a[8];
+                        load8(v1 + j * 8, a);
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) P[k * 8 + e] = v1[(int64_t)e * v1s + j];
+                        for (int e = 0; e < 8; ++e) P[k * 8 + e] = a[e];
                     }
                 }
                 // ping-pong operand buffers and unconditional memory operations, as in the
@@ -555,8 +578,10 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                         if constexpr (MODE == 2) {
                             const int pos = v1b_pos_sel(xq, xmax, y, wrow);
                             const int64_t j = act && pos >= 0 ? b0 + pos : v1s - 1;
+                            T a[8];
+                            load8(v1 + j * 8, a);
 #pragma unroll
-                            for (int e = 0; e < 8; ++e) Lx[q * 8 + e] = v1[(int64_t)e * v1s + j];
+                            for (int e = 0; e < 8; ++e) Lx[q * 8 + e] = a[e];
                         }
                     }
                 };

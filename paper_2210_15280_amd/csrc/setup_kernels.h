@@ -25,12 +25,10 @@ void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, in
                       hipStream_t st);
 void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st);
 void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, double* tab, float* tab32, hipStream_t st);
-// variant V1: exact factors of set F (8 planes of fs values, type FP32 if f32)
-void launch_gather_v1f(const Ctx& c, const double* Lf, const double* Df, void* F, bool f32, int64_t fs,
-                       hipStream_t st);
+// variant V1: exact factors of set F (8-value records, FP32 if f32)
+void launch_gather_v1f(const Ctx& c, const double* Lf, const double* Df, void* F, bool f32, hipStream_t st);
 // variant V1: backward weights of set B from F and the FP64 row tables
-void launch_build_v1b(const Ctx& c, const double* tab, const void* F, int64_t fs, void* Bw, bool f32, int64_t bs,
-                      hipStream_t st);
+void launch_build_v1b(const Ctx& c, const double* tab, const void* F, void* Bw, bool f32, hipStream_t st);
 // mode 0: stream -> lexicographic, mode 1: lexicographic -> stream
 void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,
                     int only_tet, hipStream_t st);

@@ -423,12 +423,11 @@ __global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __
 // ------------------------------------------------------- boundary variant V1
 
 // Exact factors of the points of set F (the boundary points, Sec. 4.1):
-// planes [L^p_d for d in D_l, 1/D^p] at the point's compact index.
+// record j = [L^p_d for d in D_l, 1/D^p] of the point with compact index j.
 template <typename T>
 __global__ void k_gather_v1f(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                              const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S,
-                             const double* __restrict__ Lf, const double* __restrict__ Df, T* __restrict__ F,
-                             int64_t fs) {
+                             const double* __restrict__ Lf, const double* __restrict__ Df, T* __restrict__ F) {
     int b, lane;
     decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
@@ -443,8 +442,8 @@ __global__ void k_gather_v1f(const TetDev* __restrict__ tets, const BlockDev* __
         const int64_t j = (int64_t)Ln.v1f[0] + k;
         const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
 #pragma unroll
-        for (int s = 0; s < NLOW; ++s) F[(int64_t)s * fs + j] = (T)Lf[(int64_t)s * S + idx];
-        F[(int64_t)NLOW * fs + j] = (T)(1.0 / Df[idx]);
+        for (int s = 0; s < NLOW; ++s) F[j * 8 + s] = (T)Lf[(int64_t)s * S + idx];
+        F[j * 8 + NLOW] = (T)(1.0 / Df[idx]);
     }
 }
 
@@ -460,7 +459,7 @@ __device__ __forceinline__ double horner_d(const double* c, int NC, double eta) 
 template <typename T>
 __global__ void k_build_v1b(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                             const LaneDev* __restrict__ lanes, int lpb, int groups, const double* __restrict__ tab,
-                            int NC, const T* __restrict__ F, int64_t fs, T* __restrict__ Bw, int64_t bs) {
+                            int NC, const T* __restrict__ F, T* __restrict__ Bw) {
     int b, lane;
     decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
@@ -476,7 +475,7 @@ __global__ void k_build_v1b(const TetDev* __restrict__ tets, const BlockDev* __r
         const int64_t j = (int64_t)Ln.v1b + k;
         const double eta = ((double)x - c[0]) * c[1];
         const int kf = v1f_pos(x, xmax, y, z);
-        Bw[j] = kf >= 0 ? F[(int64_t)NLOW * fs + Ln.v1f[0] + kf] : (T)horner_d(c + 2 + 7 * NC, NC, eta);
+        Bw[j * 8] = kf >= 0 ? F[((int64_t)Ln.v1f[0] + kf) * 8 + NLOW] : (T)horner_d(c + 2 + 7 * NC, NC, eta);
         for (int s = 0; s < NLOW; ++s) {
             const int xq = x - low_dx(s), yq = y - low_dy(s), zq = z - low_dz(s);
             T val = (T)0;
@@ -484,9 +483,9 @@ __global__ void k_build_v1b(const TetDev* __restrict__ tets, const BlockDev* __r
                 // row of p - d_s: own (s = 0), v+1 (s, se), w+1 (bnw, bn), v+1 w+1 (bc, be)
                 const int fr = s == 0 ? 0 : s <= 2 ? 1 : s <= 4 ? 2 : 3;
                 const int kq = v1f_pos(xq, n - 1 - yq - zq, yq, zq);
-                val = kq >= 0 ? F[(int64_t)s * fs + Ln.v1f[fr] + kq] : (T)horner_d(c + 2 + (8 + s) * NC, NC, eta);
+                val = kq >= 0 ? F[((int64_t)Ln.v1f[fr] + kq) * 8 + s] : (T)horner_d(c + 2 + (8 + s) * NC, NC, eta);
             }
-            Bw[(int64_t)(1 + s) * bs + j] = val;
+            Bw[j * 8 + 1 + s] = val;
         }
     }
 }
@@ -560,24 +559,22 @@ void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, dou
     k_row_tables<<<(nslots + 127) / 128, 128, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, nslots, coef, NC, tab, tab32);
 }
 
-void launch_gather_v1f(const Ctx& c, const double* Lf, const double* Df, void* F, bool f32, int64_t fs,
-                       hipStream_t st) {
+void launch_gather_v1f(const Ctx& c, const double* Lf, const double* Df, void* F, bool f32, hipStream_t st) {
     if (f32)
         k_gather_v1f<float><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf,
-                                                                  Df, (float*)F, fs);
+                                                                  Df, (float*)F);
     else
         k_gather_v1f<double><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf,
-                                                                   Df, (double*)F, fs);
+                                                                   Df, (double*)F);
 }
 
-void launch_build_v1b(const Ctx& c, const double* tab, const void* F, int64_t fs, void* Bw, bool f32, int64_t bs,
-                      hipStream_t st) {
+void launch_build_v1b(const Ctx& c, const double* tab, const void* F, void* Bw, bool f32, hipStream_t st) {
     if (f32)
         k_build_v1b<float><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, tab, c.NC,
-                                                                 (const float*)F, fs, (float*)Bw, bs);
+                                                                 (const float*)F, (float*)Bw);
     else
         k_build_v1b<double><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, tab, c.NC,
-                                                                  (const double*)F, fs, (double*)Bw, bs);
+                                                                  (const double*)F, (double*)Bw);
 }
 
 void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,

@@ -226,7 +226,7 @@ template <typename T, bool STORED>
 __global__ void __launch_bounds__(64) k_fwd_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                                   const LaneDev* __restrict__ lanes, int lpb, int groups, int t, int64_t S,
                                                   const double* __restrict__ Lf, const T* __restrict__ tab, int NC,
-                                                  const T* __restrict__ v1, int64_t v1s, const T* __restrict__ r,
+                                                  const T* __restrict__ v1, const T* __restrict__ r,
                                                   T* __restrict__ w) {
     int b, lane;
     decode_group(groups, b, lane);
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(64) k_fwd_plane(const TetDev* __restrict__ tet
 #pragma unroll
         for (int j = 0; j < NLOW; ++j) {
             const int s = ord[j];
-            const T Ls = pos >= 0 ? v1[(int64_t)s * v1s + Ln.v1f[0] + pos] : horner(c + 2 + s * NC, NC, eta);
+            const T Ls = pos >= 0 ? v1[((int64_t)Ln.v1f[0] + pos) * 8 + s] : horner(c + 2 + s * NC, NC, eta);
             acc -= Ls * w[Ln.rp[low_row(s)] + off + lpb * low_dt(s)];
         }
     }
@@ -269,7 +269,7 @@ template <typename T, bool STORED>
 __global__ void __launch_bounds__(64) k_bwd_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                                   const LaneDev* __restrict__ lanes, int lpb, int groups, int t, int64_t S,
                                                   const double* __restrict__ Lb, const T* __restrict__ tab, int NC,
-                                                  const T* __restrict__ v1, int64_t v1s, T* __restrict__ w,
+                                                  const T* __restrict__ v1, T* __restrict__ w,
                                                   double* __restrict__ x) {
     int b, lane;
     decode_group(groups, b, lane);
@@ -296,11 +296,11 @@ __global__ void __launch_bounds__(64) k_bwd_plane(const TetDev* __restrict__ tet
         const T eta = ((T)xx - c[0]) * c[1];
         const int pos = v1 ? v1b_pos(xx, n - 1 - v, v - Ln.w, Ln.w) : -1;
         const int64_t j1 = (int64_t)Ln.v1b + pos;
-        acc = w[idx] * (pos >= 0 ? v1[j1] : horner(c + 2 + 7 * NC, NC, eta));
+        acc = w[idx] * (pos >= 0 ? v1[j1 * 8] : horner(c + 2 + 7 * NC, NC, eta));
 #pragma unroll
         for (int j = 0; j < NLOW; ++j) {
             const int s = ord[j];
-            const T Us = pos >= 0 ? v1[(int64_t)(1 + s) * v1s + j1] : horner(c + 2 + (8 + s) * NC, NC, eta);
+            const T Us = pos >= 0 ? v1[j1 * 8 + 1 + s] : horner(c + 2 + (8 + s) * NC, NC, eta);
             acc -= Us * w[Ln.rp[up_row(s)] + off + lpb * up_dt(s)];
         }
     }
@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(64) k_bwd_plane(const TetDev* __restrict__ tet
 template <typename T>
 __global__ void k_export_surrogate(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                    const LaneDev* __restrict__ lanes, int lpb, int groups, const T* __restrict__ tab, int NC, int only_tet,
-                                   const T* __restrict__ F, int64_t fs, double* __restrict__ L_out,
+                                   const T* __restrict__ F, double* __restrict__ L_out,
                                    double* __restrict__ Dinv_out) {
     int b, lane;
     decode_group(groups, b, lane);
@@ -333,8 +333,8 @@ __global__ void k_export_surrogate(const TetDev* __restrict__ tets, const BlockD
         const int64_t j = (int64_t)Ln.v1f[0] + pos;
         if (L_out)
             for (int s = 0; s < NLOW; ++s)
-                L_out[li * NLOW + s] = (double)(pos >= 0 ? F[(int64_t)s * fs + j] : horner(c + 2 + s * NC, NC, eta));
-        if (Dinv_out) Dinv_out[li] = (double)(pos >= 0 ? F[(int64_t)NLOW * fs + j] : horner(c + 2 + 7 * NC, NC, eta));
+                L_out[li * NLOW + s] = (double)(pos >= 0 ? F[j * 8 + s] : horner(c + 2 + s * NC, NC, eta));
+        if (Dinv_out) Dinv_out[li] = (double)(pos >= 0 ? F[j * 8 + NLOW] : horner(c + 2 + 7 * NC, NC, eta));
     }
 }
 
@@ -344,11 +344,11 @@ void launch_export_surrogate(const Ctx& c, bool f32, int tet, double* L_out, dou
     if (f32)
         k_export_surrogate<float><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups,
                                                                         c.tab32, c.NC, tet, (const float*)c.v1f,
-                                                                        c.v1f_stride, L_out, Dinv_out);
+                                                                        L_out, Dinv_out);
     else
         k_export_surrogate<double><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups,
                                                                          c.tab64, c.NC, tet, (const double*)c.v1f,
-                                                                         c.v1f_stride, L_out, Dinv_out);
+                                                                         L_out, Dinv_out);
 }
 
 int64_t res_partials(const Ctx& c) { return (int64_t)c.nblocks * c.groups * c.res_chunks; }
@@ -406,25 +406,25 @@ void launch_reduce(const double* partial, int64_t count, double* out, int slot, 
 void launch_fwd_plane(const Ctx& c, int variant, int t, hipStream_t st) {
     if (variant == 0)
         k_fwd_plane<double, true><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.Lf, nullptr, 0,
-                                                            nullptr, 0, (const double*)c.r, (double*)c.w);
+                                                            nullptr, (const double*)c.r, (double*)c.w);
     else if (variant == 1)
         k_fwd_plane<double, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab64, c.NC,
-                                                             (const double*)c.v1f, c.v1f_stride, (const double*)c.r, (double*)c.w);
+                                                             (const double*)c.v1f, (const double*)c.r, (double*)c.w);
     else
         k_fwd_plane<float, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab32, c.NC,
-                                                            (const float*)c.v1f, c.v1f_stride, (const float*)c.r, (float*)c.w);
+                                                            (const float*)c.v1f, (const float*)c.r, (float*)c.w);
 }
 
 void launch_bwd_plane(const Ctx& c, int variant, int t, double* x, hipStream_t st) {
     if (variant == 0)
         k_bwd_plane<double, true><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.Lb, nullptr, 0,
-                                                            nullptr, 0, (double*)c.w, x);
+                                                            nullptr, (double*)c.w, x);
     else if (variant == 1)
         k_bwd_plane<double, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab64, c.NC,
-                                                             (const double*)c.v1b, c.v1b_stride, (double*)c.w, x);
+                                                             (const double*)c.v1b, (double*)c.w, x);
     else
         k_bwd_plane<float, false><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, nullptr, c.tab32, c.NC,
-                                                            (const float*)c.v1b, c.v1b_stride, (float*)c.w, x);
+                                                            (const float*)c.v1b, (float*)c.w, x);
 }
 
 }  // namespace ilu
