@@ -282,6 +282,31 @@ int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable);
  * of ilu_last_timing are 0 after a graph call. */
 int ilu_set_graph(ilu_handle_t h, int32_t enable);
 
+/* Residual of ilu_smooth and the forward substitution (modes below;
+ * ILU_OVERLAP_OFF by default).  ILU_OVERLAP_ON, where available (dataflow
+ * schedule, assembled operator, boundary variant V2), runs each sweep's
+ * residual kernel on a second, handle-owned stream at the same time as the
+ * forward substitution, which takes each point's residual as soon as it is
+ * written (every value carries a sweep tag; one still missing after about
+ * 64 us of polling is computed by the forward sweep itself, with the same
+ * arithmetic).  ILU_OVERLAP_FUSED runs no residual kernel: the forward sweep
+ * computes every residual itself, the first pass of Alg. 2 in its fused form
+ * (its loads then sit on the sweep's dependency chain; calls with
+ * rel_tol > 0, whose residual kernel also reduces the norm, use
+ * ILU_OVERLAP_ON).  Results are bitwise identical in every mode; only the
+ * time changes, and on MI355X neither alternative beats the default: the
+ * residual kernel, bandwidth-bound, slows down by about as much as the
+ * latency-bound forward sweep would save, because the sweep's resident
+ * workgroups hold most of the registers.  With overlap the residual of
+ * ilu_last_timing is measured on the second stream while the forward
+ * substitution runs.  A mode other than ILU_OVERLAP_OFF where it is not
+ * available returns ILU_EINVAL. */
+#define ILU_OVERLAP_OFF 0   /* residual kernel, then the forward substitution */
+#define ILU_OVERLAP_ON 1    /* residual kernel beside the forward substitution */
+#define ILU_OVERLAP_FUSED 2 /* residual computed inside the forward substitution */
+int ilu_set_overlap(ilu_handle_t h, int32_t mode);
+int ilu_get_overlap(ilu_handle_t h, int32_t *mode);
+
 /* Host-only self check (no device needed): builds the stream layout for the
  * given tetrahedra and replays every index the kernels form, counting
  * out-of-range or misdirected accesses in *violations (0 = consistent). */

@@ -13,6 +13,7 @@ STORED_F64, SURR_F64, SURR_F32, STORED_SGS = 0, 1, 2, 3
 SCHED_AUTO, SCHED_PLANE, SCHED_DATAFLOW = 0, 1, 2
 A_EXACT, A_SURROGATE = 0, 1
 BOUNDARY_V2, BOUNDARY_V1 = 0, 1
+OVERLAP_OFF, OVERLAP_ON, OVERLAP_FUSED = 0, 1, 2
 COEFF_CONST, COEFF_SINPROD, COEFF_EXPSINCOS, COEFF_POLY = 0, 1, 2, 3
 
 
@@ -78,6 +79,8 @@ def lib():
         L.ilu_last_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.ilu_set_kernel_timing.argtypes = [P, I32]
         L.ilu_set_graph.argtypes = [P, I32]
+        L.ilu_set_overlap.argtypes = [P, I32]
+        L.ilu_get_overlap.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_check_layout.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, ctypes.POINTER(ilu_opts),
                                        ctypes.POINTER(I64)]
         _lib = L
@@ -287,6 +290,15 @@ class Smoother:
 
     def set_kernel_timing(self, enable: bool):
         _check(self.L.ilu_set_kernel_timing(self.h, 1 if enable else 0), "ilu_set_kernel_timing")
+
+    def set_overlap(self, mode: int):
+        """OVERLAP_OFF (default), OVERLAP_ON or OVERLAP_FUSED (see ilu_set_overlap)."""
+        _check(self.L.ilu_set_overlap(self.h, int(mode)), "ilu_set_overlap")
+
+    def overlap(self) -> int:
+        v = ctypes.c_int32()
+        _check(self.L.ilu_get_overlap(self.h, ctypes.byref(v)), "ilu_get_overlap")
+        return v.value
 
     def set_graph(self, enable: bool):
         """Replay fixed-count sweeps from a captured graph (default on)."""

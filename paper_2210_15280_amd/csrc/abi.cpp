@@ -92,12 +92,13 @@ struct ilu_handle_s {
     DevBuf xs, bs, r, w;
     DevBuf partial, norms, flags;
     DevBuf order_fwd, order_bwd, xch, ticket;
-    int64_t npartial = 0;
+    int64_t npartial = 0;      // partial sums of the residual kernel
+    int64_t npartial_tag = 0;  // ... and of the tagged one (overlapped residual)
     int flow_grid = 0;
     hipEvent_t ev[8] = {};
     bool have_timing = false;
     bool kernel_timing = false;          // events around every kernel of every sweep
-    std::vector<hipEvent_t> kev;         // 4 per sweep: res begin/end = fwd begin, fwd end = bwd begin, bwd end
+    std::vector<hipEvent_t> kev;         // 6 per sweep: res begin/end, fwd begin/end, bwd begin/end
     int kev_sweeps = 0;
     bool use_graph = true;               // replay fixed-count sweeps from a captured graph
     double tuned_ms = 0.0;               // autotuner: measured sweep time of the chosen block shape
@@ -112,6 +113,11 @@ struct ilu_handle_s {
     DevBuf coefA_d, tabA64, tabA32;      // surrogate operator: coefficients and row tables
     std::vector<double> coefA_h;
     hipGraphExec_t cg_exec = nullptr;    // one PCG iteration
+    bool ovl_ok = false;                 // the overlapped residual is available (dataflow, exact A, V2)
+    int ovl = ILU_OVERLAP_OFF;           // ILU_OVERLAP_* mode of ilu_smooth
+    DevBuf rt;                           // its tagged residual entries
+    hipStream_t st2 = nullptr;           // stream of the overlapped residual
+    hipEvent_t oev[2] = {};              // fork and join events
 
     Ctx ctx() const {
         Ctx c;
@@ -124,9 +130,13 @@ struct ilu_handle_s {
         c.lpb = bv * bw;
         c.groups = c.lpb / WAVE;
         c.S = S;
-        int maxlen = 1;
-        for (const auto& b : blocks) maxlen = std::max(maxlen, b.te - b.tb + 1);
+        int maxlen = 1, tlast = 0;
+        for (const auto& b : blocks) {
+            maxlen = std::max(maxlen, b.te - b.tb + 1);
+            tlast = std::max(tlast, b.te);
+        }
         c.res_chunks = (maxlen + RES_T - 1) / RES_T;
+        c.res_bands = (tlast + 1 + RES_T - 1) / RES_T;
         c.A8 = A8.as<double>();
         c.Lf = Lf.as<double>();
         c.Lb = Lb.as<double>();
@@ -161,6 +171,9 @@ struct ilu_handle_s {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
         if (cap) (void)hipStreamDestroy(cap);
+        if (st2) (void)hipStreamDestroy(st2);
+        for (auto& e : oev)
+            if (e) (void)hipEventDestroy(e);
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto& e : kev)
@@ -534,6 +547,7 @@ int prepare(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, ilu_h
 
 void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
 void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target = nullptr);
+int sweep_res_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* partial, hipEvent_t* mk);
 
 // Variant V1: the exact factors of set F, copied once from the full factor
 // arrays of the setup.
@@ -656,7 +670,8 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         return ILU_ENOMEM;
     const Ctx c = h->ctx();
     h->npartial = res_partials(c);
-    if (h->partial.alloc((size_t)h->npartial * sizeof(double), st) || h->norms.alloc(16 * sizeof(double), st))
+    h->npartial_tag = res_tag_partials(c);
+    if (h->partial.alloc((size_t)std::max(h->npartial, h->npartial_tag) * sizeof(double), st) || h->norms.alloc(16 * sizeof(double), st))
         return ILU_ENOMEM;
     if (upload(h->order_fwd, topo_order(h->blocks, true), st) || upload(h->order_bwd, topo_order(h->blocks, false), st))
         return ILU_ENOMEM;
@@ -666,6 +681,14 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         return ILU_ENOMEM;
     h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->boundary == ILU_BOUNDARY_V1, h->bv, h->bw));
     for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
+    // overlapped residual: tagged entries (one 64-bit word per FP32 value, two
+    // per FP64 value), cleared to tag 0, a second stream and fork/join events
+    h->ovl_ok = h->schedule == ILU_SCHED_DATAFLOW && h->a_mode == ILU_A_EXACT && h->boundary == ILU_BOUNDARY_V2;
+    if (h->ovl_ok) {
+        if (h->rt.alloc((size_t)S * (h->variant == ILU_SURR_F32 ? 1 : 2) * sizeof(uint64_t), st)) return ILU_ENOMEM;
+        HIPCHK(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
+        for (auto& e : h->oev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
 }
@@ -679,8 +702,7 @@ int time_sweep(ilu_handle_t h, hipStream_t st, int reps, double* ms) {
     HIPCHK(hipMemsetAsync(h->bs.p, 0, h->bs.bytes, st));
     for (int k = 0; k <= reps; ++k) {
         if (k == 1) HIPCHK(hipEventRecord(h->ev[0], st));
-        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, h->variant == ILU_SURR_F32, 1, nullptr, st);
-        sweep_fwd(h, c, st);
+        if (int e = sweep_res_fwd(h, c, st, nullptr, nullptr)) return e;
         sweep_bwd(h, c, st);
     }
     HIPCHK(hipEventRecord(h->ev[1], st));
@@ -952,6 +974,55 @@ void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target) {
     }
 }
 
+// Residual and forward substitution of one sweep.  With the overlap the
+// residual kernel runs on the handle's second stream and writes tagged entries
+// that the forward sweep consumes as they appear (a missing one it computes
+// itself); the join makes later work on `st` (norms, the backward sweep) see
+// the finished residual kernel, its partial sums included.  mk: six timing
+// events of this sweep (residual begin/end, forward begin/end; the backward
+// pair is recorded by the caller) or null.
+int sweep_res_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* partial, hipEvent_t* mk) {
+    const bool f32 = h->variant == ILU_SURR_F32;
+    if (!h->ovl) {
+        if (mk) HIPCHK(hipEventRecord(mk[0], st));
+        launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1, partial, st);
+        if (mk) HIPCHK(hipEventRecord(mk[1], st));
+        if (mk) HIPCHK(hipEventRecord(mk[2], st));
+        sweep_fwd(h, c, st);
+        if (mk) HIPCHK(hipEventRecord(mk[3], st));
+        return ILU_OK;
+    }
+    Flow f = h->flow();
+    f.rt = h->rt.as<uint64_t>();
+    f.xo = h->xs.as<double>();
+    f.bo = h->bs.as<double>();
+    launch_flow_reset(f, st);  // the tag of this sweep, read by both kernels
+    if (h->ovl == ILU_OVERLAP_FUSED && !partial) {
+        // no residual kernel: no entry carries this sweep's tag, and the
+        // forward sweep computes every residual itself without polling
+        f.rspin = 0;
+        if (mk) HIPCHK(hipEventRecord(mk[0], st));
+        if (mk) HIPCHK(hipEventRecord(mk[1], st));
+        if (mk) HIPCHK(hipEventRecord(mk[2], st));
+        launch_fwd_flow(c, f, h->variant, st);
+        if (mk) HIPCHK(hipEventRecord(mk[3], st));
+        return ILU_OK;
+    }
+    f.rspin = 64;  // about 64 us of polling before computing a missing value
+    HIPCHK(hipEventRecord(h->oev[0], st));
+    HIPCHK(hipStreamWaitEvent(h->st2, h->oev[0], 0));
+    if (mk) HIPCHK(hipEventRecord(mk[0], h->st2));
+    launch_residual_tagged(c, h->xs.as<double>(), h->bs.as<double>(), h->rt.as<uint64_t>(), f32, f.ticket + 2,
+                           partial, h->st2);
+    if (mk) HIPCHK(hipEventRecord(mk[1], h->st2));
+    HIPCHK(hipEventRecord(h->oev[1], h->st2));
+    if (mk) HIPCHK(hipEventRecord(mk[2], st));
+    launch_fwd_flow(c, f, h->variant, st);
+    if (mk) HIPCHK(hipEventRecord(mk[3], st));
+    HIPCHK(hipStreamWaitEvent(st, h->oev[1], 0));
+    return ILU_OK;
+}
+
 // One PCG iteration, entirely on the device (scalars in cg_sc):
 //   q = A p;  alpha = (r.z) / (p.q);  x += alpha p;  r -= alpha q;
 //   z = C^{-1} r (forward and backward substitution from zero);
@@ -1002,8 +1073,7 @@ int capture_cg(ilu_handle_t h, const Ctx& c) {
 int capture_sweep(ilu_handle_t h, const Ctx& c) {
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, h->variant == ILU_SURR_F32, 1, nullptr, h->cap);
-    sweep_fwd(h, c, h->cap);
+    if (int e = sweep_res_fwd(h, c, h->cap, nullptr, nullptr)) return e;
     sweep_bwd(h, c, h->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap, &g);
@@ -1148,15 +1218,15 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
     }
     double rel = -1.0;
     bool converged = false;
-    if (h->kernel_timing && (int)h->kev.size() < 4 * nsweeps) {
+    if (h->kernel_timing && (int)h->kev.size() < 6 * nsweeps) {
         const size_t old = h->kev.size();
-        h->kev.resize(4 * (size_t)nsweeps, nullptr);
+        h->kev.resize(6 * (size_t)nsweeps, nullptr);
         for (size_t i = old; i < h->kev.size(); ++i) HIPCHK(hipEventCreate(&h->kev[i]));
     }
-    auto mark = [&](int k, int i) -> hipError_t {
-        if (h->kernel_timing) return hipEventRecord(h->kev[4 * (size_t)k + i], st);
-        if (k == 0) return hipEventRecord(h->ev[2 + i], st);
-        return hipSuccess;
+    // timing events of sweep k: all sweeps with kernel timing on, else the first
+    auto marks = [&](int k) -> hipEvent_t* {
+        if (h->kernel_timing) return &h->kev[6 * (size_t)k];
+        return k == 0 ? &h->ev[2] : nullptr;
     };
     int done = 0;
     // fixed number of sweeps: replay the captured one-sweep graph
@@ -1178,16 +1248,14 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
     while (!graph && done < nsweeps) {
         const int m = rel_tol > 0.0 ? std::min(CHK, nsweeps - done) : nsweeps - done;
         for (int j = 0; j < m; ++j) {
-            const int k = done + j;
-            HIPCHK(mark(k, 0));
-            launch_residual(c, h->xs.as<double>(), h->bs.as<double>(), h->r.p, f32, 1,
-                            rel_tol > 0.0 ? h->partial.as<double>() : nullptr, st);
-            if (rel_tol > 0.0) launch_reduce(h->partial.as<double>(), h->npartial, h->norms.as<double>(), 2 + j, st);
-            HIPCHK(mark(k, 1));
-            sweep_fwd(h, c, st);
-            HIPCHK(mark(k, 2));
+            hipEvent_t* mk = marks(done + j);
+            if (int e = sweep_res_fwd(h, c, st, rel_tol > 0.0 ? h->partial.as<double>() : nullptr, mk)) return e;
+            if (rel_tol > 0.0)
+                launch_reduce(h->partial.as<double>(), h->ovl ? h->npartial_tag : h->npartial, h->norms.as<double>(),
+                              2 + j, st);
+            if (mk) HIPCHK(hipEventRecord(mk[4], st));
             sweep_bwd(h, c, st);
-            HIPCHK(mark(k, 3));
+            if (mk) HIPCHK(hipEventRecord(mk[5], st));
         }
         done += m;
         if (rel_tol > 0.0) {
@@ -1514,19 +1582,34 @@ int ilu_last_timing(ilu_handle_t h, double* sweep_ms, double* fwd_kernel_ms, dou
     double f = 0, b = 0, r = 0;
     const int ns = h->kev_sweeps;
     for (int k = 0; k < ns; ++k) {
-        hipEvent_t* e = h->kernel_timing ? &h->kev[4 * (size_t)k] : &h->ev[2];
-        float t01 = 0, t12 = 0, t23 = 0;
-        HIPCHK(hipEventElapsedTime(&t01, e[0], e[1]));
-        HIPCHK(hipEventElapsedTime(&t12, e[1], e[2]));
-        HIPCHK(hipEventElapsedTime(&t23, e[2], e[3]));
-        r += t01;
-        f += t12;
-        b += t23;
+        hipEvent_t* e = h->kernel_timing ? &h->kev[6 * (size_t)k] : &h->ev[2];
+        float tr = 0, tf = 0, tb = 0;
+        HIPCHK(hipEventElapsedTime(&tr, e[0], e[1]));
+        HIPCHK(hipEventElapsedTime(&tf, e[2], e[3]));
+        HIPCHK(hipEventElapsedTime(&tb, e[4], e[5]));
+        r += tr;
+        f += tf;
+        b += tb;
     }
     if (sweep_ms) *sweep_ms = a;
     if (fwd_kernel_ms) *fwd_kernel_ms = ns ? f / ns : 0.0;
     if (bwd_kernel_ms) *bwd_kernel_ms = ns ? b / ns : 0.0;
     if (res_kernel_ms) *res_kernel_ms = ns ? r / ns : 0.0;
+    return ILU_OK;
+}
+
+int ilu_set_overlap(ilu_handle_t h, int32_t mode) {
+    if (!h || mode < ILU_OVERLAP_OFF || mode > ILU_OVERLAP_FUSED) return ILU_EINVAL;
+    if (mode != ILU_OVERLAP_OFF && !h->ovl_ok) return ILU_EINVAL;
+    if (h->ovl != mode)
+        if (int e = drop_graphs(h, nullptr)) return e;  // the captured sweep has the other form
+    h->ovl = mode;
+    return ILU_OK;
+}
+
+int ilu_get_overlap(ilu_handle_t h, int32_t* mode) {
+    if (!h || !mode) return ILU_EINVAL;
+    *mode = h->ovl;
     return ILU_OK;
 }
 

@@ -19,6 +19,7 @@ struct Ctx {
     int lpb = 64;            // lanes per block = bv * bw
     int groups = 1;          // 64-lane groups per block
     int res_chunks = 0;      // ceil(max block window / RES_T)
+    int res_bands = 0;       // ceil((last hyperplane + 1) / RES_T): absolute hyperplane bands
     int64_t S = 0;           // stream length (elements)
     const double* A8 = nullptr;   // [8][S]: centre, then lower weights w..be
     const double* Lf = nullptr;   // [7][S] stored forward weights

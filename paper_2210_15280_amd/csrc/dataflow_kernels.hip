@@ -36,8 +36,11 @@
 // error can never hang the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels_common.h"
 #include "sweep_kernels.h"
+#include "tagged_device.h"
 
 namespace ilu {
 
@@ -46,15 +49,6 @@ namespace {
 constexpr long SPIN_LIMIT = 1L << 20;
 // accumulation order over D_l: s, bnw, bc, be (older hyperplanes) then w, se, bn
 constexpr int ORD[7] = {1, 3, 5, 6, 0, 2, 4};
-
-template <typename T>
-__device__ __forceinline__ void st_dev(T* p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ T ld_dev(const T* p) {
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Workgroup barrier that orders LDS traffic only: a full __syncthreads()
 // would also wait for this wave's outstanding global stores and loads.
@@ -109,43 +103,21 @@ __device__ __forceinline__ T horner(const T* c, T eta) {
     return acc;
 }
 
-// ---- tagged exchange entries: 32-bit payload | 32-bit tag per 64-bit word
+// A residual entry that did not carry this sweep's tag when the forward sweep
+// reached it: poll it up to `spins` times, then compute the value here (and
+// poll less from then on).  Kept out of line: it is the rare path, and inlined
+// it would hold registers across the whole sweep loop.
 template <typename T>
-struct XEnt;
-template <>
-struct XEnt<float> {
-    static constexpr int W = 1;
-    uint64_t u[1];
-};
-template <>
-struct XEnt<double> {
-    static constexpr int W = 2;
-    uint64_t u[2];
-};
-
-__device__ __forceinline__ void x_put(uint64_t* p, float v, uint32_t tag) {
-    st_dev(p, ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v));
-}
-__device__ __forceinline__ void x_put(uint64_t* p, double v, uint32_t tag) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    st_dev(p, ((uint64_t)tag << 32) | (b & (uint64_t)0xffffffffu));
-    st_dev(p + 1, ((uint64_t)tag << 32) | (b >> 32));
-}
-template <typename T>
-__device__ __forceinline__ void x_get(XEnt<T>& e, const uint64_t* p) {
-#pragma unroll
-    for (int k = 0; k < XEnt<T>::W; ++k) e.u[k] = ld_dev(p + k);
-}
-template <typename T>
-__device__ __forceinline__ bool x_ok(const XEnt<T>& e, uint32_t tag) {
-    bool ok = true;
-#pragma unroll
-    for (int k = 0; k < XEnt<T>::W; ++k) ok = ok && (uint32_t)(e.u[k] >> 32) == tag;
-    return ok;
-}
-__device__ __forceinline__ float x_val(const XEnt<float>& e) { return __uint_as_float((uint32_t)e.u[0]); }
-__device__ __forceinline__ double x_val(const XEnt<double>& e) {
-    return __longlong_as_double((long long)((e.u[0] & (uint64_t)0xffffffffu) | (e.u[1] << 32)));
+__device__ __noinline__ T late_residual(const uint64_t* e, uint32_t tag, int& spins, const LaneDev& Ln, int lpb,
+                                         int64_t S, int t, const double* A8, const double* xo, const double* bo) {
+    XEnt<T> re;
+    for (int k = 0; k < spins; ++k) {
+        __builtin_amdgcn_s_sleep(2);
+        x_get(re, e);
+        if (x_ok(re, tag)) return x_val(re);
+    }
+    spins = 2;
+    return (T)residual_point(Ln, lpb, S, t, A8, xo, bo);
 }
 
 // Halo role of a thread: one incoming row (column halo, row halo or corner).
@@ -203,13 +175,20 @@ __device__ __forceinline__ T halo_take(const Halo& h, const uint64_t* xch, int n
 // halo load would otherwise also wait for the slow device-coherent stores
 // issued before it.  All paths pass the same barriers.
 
-template <typename T, bool STORED, bool V1, int U, int D, int NC, int BV, int BW>
+//
+// OVL: the residual comes from the tagged stream rt that the residual kernel
+// fills while this kernel runs.  A point whose entry does not yet carry this
+// sweep's tag is polled a bounded number of times and then computed here
+// (residual_point, bitwise the residual kernel's value), so the sweep never
+// depends on the residual kernel being scheduled alongside it.
+template <typename T, bool STORED, bool V1, bool OVL, int U, int D, int NC, int BV, int BW>
 __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
     k_fwd_flow(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks, const LaneDev* __restrict__ lanes,
                int nblocks, int64_t S, const double* __restrict__ Lf, const T* __restrict__ tab,
-               const T* __restrict__ v1, int64_t v1s, const T* __restrict__ r, T* __restrict__ w,
-               const int32_t* __restrict__ order, uint64_t* __restrict__ xch, int32_t* __restrict__ ticket,
-               int32_t* __restrict__ flags) {
+               const T* __restrict__ v1, int64_t v1s, const T* __restrict__ r, const uint64_t* __restrict__ rt,
+               const double* __restrict__ A8, const double* __restrict__ xo, const double* __restrict__ bo,
+               int rspin0, T* __restrict__ w, const int32_t* __restrict__ order, uint64_t* __restrict__ xch,
+               int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
     constexpr int NT = BV * BW;
     constexpr int GW = BV + 1;
     constexpr int GC = (BV + 1) * (BW + 1);
@@ -341,16 +320,19 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                 // the number of memory operations between a load and its use is the same on
                 // every path and the wait before a use covers that load only.
                 constexpr int NL = (STORED || MODE == 2) ? 7 * UU : 1;
-                T rA[UU], rB[UU];
+                using RE = typename Pick<OVL, XEnt<T>, T>::type;
+                RE rA[UU], rB[UU];
                 LT LA[NL], LB[NL];
-                auto prefetch = [&](const int T0, T (&rx)[UU], LT (&Lx)[NL]) {
+                int rspin = rspin0;  // polls of a stale residual entry before computing it here
+                auto prefetch = [&](const int T0, RE (&rx)[UU], LT (&Lx)[NL]) {
 #pragma unroll
                     for (int q = 0; q < UU; ++q) {
                         // inactive points read the (cache-resident) zero region, not padding
                         const int t = min(T0 + q, te), xq = t - 2 * v - wrow;
                         const bool act = valid && xq >= 1 && xq <= xmax;
                         const int64_t i = act ? rp + (int64_t)NT * t : 0;
-                        rx[q] = r[i];
+                        if constexpr (OVL) x_get(rx[q], rt + i * XW);
+                        else rx[q] = r[i];
                         if constexpr (STORED) {
 #pragma unroll
                             for (int s = 0; s < 7; ++s) Lx[q * 7 + s] = Lf[(int64_t)s * S + i];
@@ -365,7 +347,7 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                         }
                     }
                 };
-                auto batch = [&](const int T0, T (&rcur)[UU], LT (&Lcur)[NL], T (&rnxt)[UU], LT (&Lnxt)[NL]) {
+                auto batch = [&](const int T0, RE (&rcur)[UU], LT (&Lcur)[NL], RE (&rnxt)[UU], LT (&Lnxt)[NL]) {
                     prefetch(T0 + UU, rnxt, Lnxt);
 #pragma unroll
                     for (int q = 0; q < UU; ++q) {
@@ -381,7 +363,15 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                             // bn (w-1, t-1), bc (v-1 w-1, t-3), be (v-1 w-1, t-2)
                             const T nb[7] = {g1[cell], g2[cell - 1], g1[cell - 1], g2[cell - GW],
                                              g1[cell - GW], g3[cell - GW - 1], g2[cell - GW - 1]};
-                            T acc = rcur[q];
+                            T acc;
+                            if constexpr (OVL) {
+                                acc = x_val(rcur[q]);
+                                if (!x_ok(rcur[q], tag))
+                                    acc = late_residual<T>(rt + (rp + (int64_t)NT * t) * XW, tag, rspin, Ln, NT, S, t,
+                                                           A8, xo, bo);
+                            } else {
+                                acc = rcur[q];
+                            }
                             if constexpr (STORED) {
 #pragma unroll
                                 for (int jj = 0; jj < 7; ++jj) acc -= (T)Lcur[q * 7 + ORD[jj]] * nb[ORD[jj]];
@@ -690,46 +680,52 @@ namespace {
 constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 2;  // stored factors
 constexpr int U_S64 = 4, D_S64 = 2;              // FP64 surrogate
 constexpr int U_F32 = 8, D_F32 = 2;              // FP32 surrogate
+// With the overlapped residual the forward sweep advances at the rate the
+// residual kernel produces its input, and every register it holds is one the
+// residual kernel beside it cannot use: shallower operand batches.
+constexpr int UO_F64 = 2, UO_S64 = 2, UO_F32 = 4;
 
 template <int BV, int BW>
 struct Shape {
     static constexpr int NT = BV * BW;
+    template <bool OVL>
     static const void* fwd_stored_ptr() {
-        return (const void*)k_fwd_flow<double, true, false, U_F64, D_F64, 0, BV, BW>;
+        return (const void*)k_fwd_flow<double, true, false, OVL, (OVL ? UO_F64 : U_F64), D_F64, 0, BV, BW>;
     }
     static const void* bwd_stored_ptr() {
         return (const void*)k_bwd_flow<double, true, false, U_F64B, D_F64, 0, BV, BW>;
     }
-    template <int NC, bool V1>
+    template <int NC, bool V1, bool OVL>
     static const void* fwd_ptr(int variant) {
-        if (variant == 1) return (const void*)k_fwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW>;
-        return (const void*)k_fwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW>;
+        if (variant == 1) return (const void*)k_fwd_flow<double, false, V1, OVL, (OVL ? UO_S64 : U_S64), D_S64, NC, BV, BW>;
+        return (const void*)k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), D_F32, NC, BV, BW>;
     }
     template <int NC, bool V1>
     static const void* bwd_ptr(int variant) {
         if (variant == 1) return (const void*)k_bwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW>;
         return (const void*)k_bwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW>;
     }
+    template <bool OVL>
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
-        k_fwd_flow<double, true, false, U_F64, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
-            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, nullptr, 0, (const double*)c.r, (double*)c.w,
-            f.order_fwd, f.xch, f.ticket, f.flags);
+        k_fwd_flow<double, true, false, OVL, (OVL ? UO_F64 : U_F64), D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
+            c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, nullptr, 0, (const double*)c.r, f.rt, c.A8,
+            f.xo, f.bo, f.rspin, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
     }
     static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
         k_bwd_flow<double, true, false, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lb, nullptr, nullptr, 0, (const double*)c.w, x, f.order_bwd,
             f.xch, f.ticket, f.flags);
     }
-    template <int NC, bool V1>
+    template <int NC, bool V1, bool OVL>
     static void fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
         if (variant == 1)
-            k_fwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
+            k_fwd_flow<double, false, V1, OVL, (OVL ? UO_S64 : U_S64), D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.v1f, c.v1f_stride,
-                (const double*)c.r, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
+                (const double*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
+            k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.v1f, c.v1f_stride,
-                (const float*)c.r, (float*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
+                (const float*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, (float*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
     }
     template <int NC, bool V1>
     static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {
@@ -756,46 +752,57 @@ struct Shape {
     default: CALL(7); break;     \
     }
 
+// Resident workgroups per CU of both sweep kernels (the forward one in both
+// residual modes where the handle can use the overlapped one).
 template <int BV, int BW>
 int resident(int variant, int NC, bool v1) {
     const void* kf = nullptr;
+    const void* ko = nullptr;
     const void* kb = nullptr;
     if (variant == 0) {
-        kf = Shape<BV, BW>::fwd_stored_ptr();
+        kf = Shape<BV, BW>::template fwd_stored_ptr<false>();
+        ko = Shape<BV, BW>::template fwd_stored_ptr<true>();
         kb = Shape<BV, BW>::bwd_stored_ptr();
     } else if (v1) {
-#define ILU_PTRS(N)                                                 \
-    (kf = Shape<BV, BW>::template fwd_ptr<N, true>(variant), \
+#define ILU_PTRS(N)                                                       \
+    (kf = ko = Shape<BV, BW>::template fwd_ptr<N, true, false>(variant), \
      kb = Shape<BV, BW>::template bwd_ptr<N, true>(variant))
         ILU_NC_SWITCH(NC, ILU_PTRS)
 #undef ILU_PTRS
     } else {
-#define ILU_PTRS(N)                                                  \
-    (kf = Shape<BV, BW>::template fwd_ptr<N, false>(variant), \
+#define ILU_PTRS(N)                                                    \
+    (kf = Shape<BV, BW>::template fwd_ptr<N, false, false>(variant), \
+     ko = Shape<BV, BW>::template fwd_ptr<N, false, true>(variant),  \
      kb = Shape<BV, BW>::template bwd_ptr<N, false>(variant))
         ILU_NC_SWITCH(NC, ILU_PTRS)
 #undef ILU_PTRS
     }
     const int nthreads = BV * BW + (1 + (variant == 0 ? D_F64 : variant == 1 ? D_S64 : D_F32)) * WAVE;
-    int a = 0, b = 0;
+    int a = 0, b = 0, o = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, nthreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, ko, nthreads, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, nthreads, 0) != hipSuccess)
         return 1;
-    return a < b ? a : b;
+    return std::min(a, std::min(o, b));
 }
 
 template <int BV, int BW>
 void run_fwd(const Ctx& c, const Flow& f, int variant, hipStream_t st) {
     if (variant == 0) {
-        Shape<BV, BW>::fwd_stored(c, f, st);
+        if (f.rt) Shape<BV, BW>::template fwd_stored<true>(c, f, st);
+        else Shape<BV, BW>::template fwd_stored<false>(c, f, st);
         return;
     }
     if (c.v1f) {
-#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, true>(c, f, variant, st)
+#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, true, false>(c, f, variant, st)
+        ILU_NC_SWITCH(c.NC, ILU_FWD)
+#undef ILU_FWD
+    } else if (f.rt) {
+#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, false, true>(c, f, variant, st)
         ILU_NC_SWITCH(c.NC, ILU_FWD)
 #undef ILU_FWD
     } else {
-#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, false>(c, f, variant, st)
+#define ILU_FWD(N) Shape<BV, BW>::template fwd<N, false, false>(c, f, variant, st)
         ILU_NC_SWITCH(c.NC, ILU_FWD)
 #undef ILU_FWD
     }

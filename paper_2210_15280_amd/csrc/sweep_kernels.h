@@ -7,6 +7,12 @@ namespace ilu {
 
 void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
                      hipStream_t st);
+// r = b - A x (assembled A) as tagged entries (XEnt words, tag *tagp) for a
+// forward sweep consuming them while this kernel runs; res_tag_partials
+// partial sums of ||r||^2
+int64_t res_tag_partials(const Ctx& c);
+void launch_residual_tagged(const Ctx& c, const double* x, const double* b, uint64_t* rt, bool f32,
+                            const int32_t* tagp, double* partial, hipStream_t st);
 void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st);
 // number of partial sums the residual and norm kernels write
 int64_t res_partials(const Ctx& c);
@@ -24,6 +30,13 @@ struct Flow {
     int32_t* ticket = nullptr;           // [4] work counters (fwd, bwd) and the launch tag
     int32_t* flags = nullptr;            // [4] error flags (flags[2]: wait limit hit)
     int grid = 0;                        // resident workgroups
+    // overlapped residual (forward sweep only; null: read the plain residual
+    // stream): tagged residual entries and the x, b streams to compute a
+    // missing one from
+    const uint64_t* rt = nullptr;
+    const double* xo = nullptr;
+    const double* bo = nullptr;
+    int rspin = 0;                       // polls of a missing entry before computing it
 };
 void launch_flow_reset(const Flow& f, hipStream_t st);
 void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st);
