@@ -1073,10 +1073,14 @@ int capture_cg(ilu_handle_t h, const Ctx& c) {
 int capture_sweep(ilu_handle_t h, const Ctx& c) {
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    if (int e = sweep_res_fwd(h, c, h->cap, nullptr, nullptr)) return e;
-    sweep_bwd(h, c, h->cap);
+    const int rc = sweep_res_fwd(h, c, h->cap, nullptr, nullptr);
+    if (rc == ILU_OK) sweep_bwd(h, c, h->cap);
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(h->cap, &g);
+    const hipError_t e = hipStreamEndCapture(h->cap, &g);  // also after a failed launch: leave no open capture
+    if (rc != ILU_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
     const hipError_t e2 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
     hipGraphDestroy(g);
