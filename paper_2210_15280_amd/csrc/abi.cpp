@@ -330,7 +330,23 @@ int build_layout(ilu_handle_t h) {
             L.v1f[3] = valid ? base_of(fbase, ti, v + 1, w + 1) : -1;
             L.v1b = valid ? base_of(bbase, ti, v, w) : -1;
             L.pad_ = 0;
+            L.gt[0] = 1 << 30;
+            L.gt[1] = -1;
             if (valid && (v - w <= 2 || w == 1)) B.edge = 1;
+        }
+        // hyperplane window of each 64-lane group (same value in all its lanes)
+        for (int g = 0; g < lpb / WAVE; ++g) {
+            int gtb = 1 << 30, gte = -1;
+            for (int l = g * WAVE; l < (g + 1) * WAVE; ++l) {
+                const LaneDev& L = h->lanes[bi * lpb + l];
+                if (L.v == 0) continue;
+                gtb = std::min(gtb, 2 * L.v + L.w + 1);
+                gte = std::max(gte, n - 1 + L.v + L.w);
+            }
+            for (int l = g * WAVE; l < (g + 1) * WAVE; ++l) {
+                h->lanes[bi * lpb + l].gt[0] = gtb;
+                h->lanes[bi * lpb + l].gt[1] = gte;
+            }
         }
     }
     return ILU_OK;

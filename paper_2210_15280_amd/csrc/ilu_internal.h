@@ -71,6 +71,8 @@ struct LaneDev {
     int32_t v, w;        // row coordinates; v = 0 marks an unused lane
     int32_t v1f[4];      // variant V1: first set-F index of the rows R_SELF, R_VP, R_WP, R_VPWP
     int32_t v1b;         // variant V1: first set-B index of the own row (-1: row outside)
+    int32_t gt[2];       // hyperplanes [gt[0], gt[1]] with an active point in this lane's 64-lane
+                         // group (empty if gt[0] > gt[1]): the point-parallel kernels skip the rest
     int32_t pad_;
 };
 

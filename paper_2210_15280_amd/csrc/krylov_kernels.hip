@@ -26,8 +26,8 @@ __device__ __forceinline__ void for_active(const TetDev* __restrict__ tets, cons
     const int t0 = B.tb + it.chunk * RES_T;
     if (Ln.v == 0 || t0 > B.te) return;
     const int n = tets[B.tet].n;
-    const int t1 = min(B.te, t0 + RES_T - 1);
-    for (int t = t0 + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
+    const int t1 = min(min(B.te, t0 + RES_T - 1), Ln.gt[1]);
+    for (int t = max(t0, Ln.gt[0]) + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
         const int x = t - 2 * Ln.v - Ln.w;
         if (x < 1 || x > n - 1 - Ln.v) continue;
         f(Ln.rp[R_SELF] + (int64_t)lpb * t);

@@ -35,8 +35,9 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
             rpl[s] = Ln.rp[low_row(s)] + (int64_t)lpb * low_dt(s);
             rpu[s] = Ln.rp[up_row(s)] + (int64_t)lpb * up_dt(s);
         }
-        const int t1 = min(B.te, t0 + RES_T - 1);
-        for (int t = t0 + sub; t <= t1; t += 8) {
+        // the chunk, clipped to the hyperplanes where this 64-lane group has an active point
+        const int t1 = min(min(B.te, t0 + RES_T - 1), Ln.gt[1]);
+        for (int t = max(t0, Ln.gt[0]) + sub; t <= t1; t += 8) {
             const int tp[2] = {t, min(t + 4, B.te + 1)};
             bool act[2];
             double a[2][15], xv[2][15], bv[2];
@@ -67,7 +68,10 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
 #pragma unroll
                 for (int k = 1; k < 15; ++k) acc = fma(a[p][k], xv[p][k], acc);
                 const double rv = act[p] ? (SUB ? bv[p] - acc : acc) : 0.0;
-                r[rs + (int64_t)lpb * tp[p]] = (RT)rv;
+                // only active points: the second point of a pair may lie in the next
+                // chunk (the clipped range need not be a multiple of 8 long), whose
+                // item writes it; inactive slots stay 0 from the allocation
+                if (act[p]) r[rs + (int64_t)lpb * tp[p]] = (RT)rv;
                 acc2 += rv * rv;
             }
         }
@@ -101,7 +105,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
     double acc2 = 0.0;
     const BlockDev& B = blocks[it.live ? it.blk : 0];
     const LaneDev& Ln = lanes[(int64_t)(it.live ? it.blk : 0) * lpb + (it.live ? it.lane : 0)];
-    const int t0 = max(B.tb, it.chunk * RES_T), t1 = min(B.te, it.chunk * RES_T + RES_T - 1);
+    const int t0 = max(max(B.tb, it.chunk * RES_T), Ln.gt[0]);
+    const int t1 = min(min(B.te, it.chunk * RES_T + RES_T - 1), Ln.gt[1]);
     if (it.live && Ln.v != 0 && t0 <= t1) {
         const int n = tets[B.tet].n, v = Ln.v, w = Ln.w;
         const int64_t rs = Ln.rp[R_SELF];
@@ -187,8 +192,8 @@ __global__ void __launch_bounds__(256) k_residual_sa(const TetDev* __restrict__ 
         TT c[15 * NC];
 #pragma unroll
         for (int i = 0; i < 15 * NC; ++i) c[i] = tr[2 + i];
-        const int t1 = min(B.te, t0 + RES_T - 1);
-        for (int t = t0 + sub; t <= t1; t += 4) {
+        const int t1 = min(min(B.te, t0 + RES_T - 1), Ln.gt[1]);  // clipped as in k_residual
+        for (int t = max(t0, Ln.gt[0]) + sub; t <= t1; t += 4) {
             const int xx = t - 2 * v - w;
             const bool act = valid && xx >= 1 && xx <= n - 1 - v;
             // inactive points read the zero region, as in the assembled residual
@@ -235,8 +240,8 @@ __global__ void __launch_bounds__(256) k_sumsq(const TetDev* __restrict__ tets, 
     const int t0 = B.tb + it.chunk * RES_T;
     if (it.live && Ln.v != 0 && t0 <= B.te) {
         const int n = tets[B.tet].n;
-        const int t1 = min(B.te, t0 + RES_T - 1);
-        for (int t = t0 + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
+        const int t1 = min(min(B.te, t0 + RES_T - 1), Ln.gt[1]);
+        for (int t = max(t0, Ln.gt[0]) + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
             const int xx = t - 2 * Ln.v - Ln.w;
             if (xx < 1 || xx > n - 1 - Ln.v) continue;
             const double a = v_s[Ln.rp[R_SELF] + (int64_t)lpb * t];
