@@ -443,3 +443,54 @@ def test_full_size_level9_fp32_surrogate(torch, pkg):
     ip = O.index_of(9, pts)
     bp = b[torch.tensor(ip, device="cuda")].cpu().numpy()
     assert np.abs(Cx - bp).max() <= 1e-4 * np.abs(bp).max()
+
+
+def _boundary_heavy_points(level, count, seed):
+    # interior points moved onto the boundary layers x, y, z in {1, 2} and
+    # x + y + z in {n-1, n-2} (the points whose factors or neighbours' factors
+    # variant V1 stores), plus the plain random sample
+    n = 1 << level
+    rng = np.random.default_rng(seed)
+    pts = O.random_interior(level, count, seed=seed).astype(np.int64)
+    face = rng.integers(0, 4, len(pts))
+    layer = rng.integers(1, 3, len(pts))
+    for i, (f, k) in enumerate(zip(face, layer)):
+        if f < 3:
+            pts[i, f] = k
+        else:
+            pts[i, 0] = n - k - pts[i, 1] - pts[i, 2]
+    ok = (pts >= 1).all(axis=1) & (pts.sum(axis=1) <= n - 1)
+    return np.unique(pts[ok], axis=0).astype(np.int32)
+
+
+def test_full_size_level9_fp32_surrogate_v1(torch, pkg):
+    # the V1 variant of the benchmark workload at full size: at boundary points
+    # the exported weights are the exact factors of a stored-factor handle
+    # (to FP32 rounding), elsewhere the surrogate; one FP32 sweep from x = 0
+    # solves L~ D~ L~^T x = b with these weights at points on and next to the
+    # boundary layers and at random points
+    wl, t, pts0 = _l9_setup()
+    pts = np.concatenate([pts0, _boundary_heavy_points(9, 1500, seed=2)])
+    n = 512
+    bary = np.column_stack([pts, n - pts.sum(axis=1)])
+    onb = bary.min(axis=1) == 1
+    assert onb.sum() > 300
+    ip = O.index_of(9, pts)
+    st = pkg.Smoother([t], pkg.STORED_F64)
+    L_ex, D_ex = st.factors(0)
+    Le = _gather(torch, L_ex, ip[onb])
+    De = _gather(torch, D_ex, ip[onb])
+    del L_ex, D_ex
+    st.close()
+    sm = pkg.Smoother([t], pkg.SURR_F32, degree=wl.degree, stride=wl.stride, boundary=pkg.BOUNDARY_V1)
+    Lw, Dinv = sm.surrogate_values(0)
+    Lb = _gather(torch, Lw, ip[onb])
+    Db = _gather(torch, Dinv, ip[onb])
+    assert np.abs(Lb - Le).max() <= 1e-6 * np.abs(Le).max()
+    assert np.abs(Db - 1.0 / De).max() <= 1e-6 * np.abs(1.0 / De).max()
+    b = torch.tensor(t.rhs(), device="cuda")
+    x = torch.zeros_like(b)
+    sm.smooth(x, b, 1)
+    Cx = _ldlt_apply_at(torch, 9, pts, Lw, Dinv, x, diag_is_inverse=True)
+    bp = b[torch.tensor(ip, device="cuda")].cpu().numpy()
+    assert np.abs(Cx - bp).max() <= 1e-4 * np.abs(bp).max()
