@@ -184,3 +184,22 @@ def test_v1_setup_fit_matches_v2_fit(torch, pkg):
     s1.smooth(x, torch.tensor(b, device="cuda"), 3)
     want, _ = P.smooth_stencil(Lw1, Dinv1, b, nsweeps=3)
     assert _rel(x.cpu().numpy(), want) < 1e-11
+
+
+def test_v1_with_surrogate_operator(torch, pkg):
+    # V1 factors together with the surrogate operator in the residual (the two
+    # options are independent): FP64 sweeps against the oracle with both
+    # surrogates' coefficients injected
+    level, deg = 5, 3
+    t, P, c, (L, D), _, (Lw1, Dinv1) = _case(level, seed=36, coeff=W.KAPPA_EXP)
+    ca = O.fit_operator_surrogate(level, P.A, deg, O.effective_stride(level, deg, 4))
+    At = O.eval_operator_surrogate(level, ca, deg)
+    sm = pkg.Smoother([t], pkg.SURR_F64, degree=deg, stride=4, tile=(8, 8), boundary=pkg.BOUNDARY_V1,
+                      a_mode=pkg.A_SURROGATE)
+    sm.set_surrogate(0, c)
+    sm.set_surrogate_a(0, ca)
+    b = t.rhs()
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    sm.smooth(x, torch.tensor(b, device="cuda"), 5)
+    want, _ = P.smooth_stencil(Lw1, Dinv1, b, nsweeps=5, A=At)
+    assert _rel(x.cpu().numpy(), want) < 1e-11
