@@ -232,7 +232,9 @@ int build_layout(ilu_handle_t h) {
                 const int V0 = 2 + bv * kv, W0 = 1 + bw * kw;
                 int tb = 1 << 30, te = -1;
                 for (int l = 0; l < lpb; ++l) {
-                    const int v = V0 + l % bv, w = W0 + l / bv;
+                    int vl = 0, wl = 0;
+                    lane_rc(l, bv, &vl, &wl);
+                    const int v = V0 + vl, w = W0 + wl;
                     if (v > n - 2 || w > v - 1) continue;
                     tb = std::min(tb, 2 * v + w + 1);
                     te = std::max(te, n - 1 + v + w);
@@ -268,7 +270,7 @@ int build_layout(ilu_handle_t h) {
         if (v < 2 || v > n - 2 || w < 1 || w > v - 1) return 0;  // zero region
         const int b = block_at(ti, (v - 2) / bv, (w - 1) / bw);
         const BlockDev& B = h->blocks[b];
-        const int l = (w - B.W0) * bv + (v - B.V0);
+        const int l = lane_at(v - B.V0, w - B.W0, bv);
         return B.base - (int64_t)B.tlo * lpb + l;
     };
     // variant V1: the point sets F and B numbered row by row, rows of each
@@ -313,7 +315,9 @@ int build_layout(ilu_handle_t h) {
         h->tmax = std::max(h->tmax, B.te);
         for (int l = 0; l < lpb; ++l) {
             LaneDev& L = h->lanes[bi * lpb + l];
-            const int v = B.V0 + l % bv, w = B.W0 + l / bv;
+            int vl = 0, wl = 0;
+            lane_rc(l, bv, &vl, &wl);
+            const int v = B.V0 + vl, w = B.W0 + wl;
             const bool valid = v <= n - 2 && w <= v - 1;
             L.v = valid ? v : 0;
             L.w = w;
@@ -884,7 +888,7 @@ int64_t check_layout(ilu_handle_t h) {
                 for (int j = 0; j < nx; ++j) {
                     int vl, wl;
                     xch_out_lane(dir, j, bv, bw, &vl, &wl);
-                    const int l = wl * bv + vl;
+                    const int l = lane_at(vl, wl, bv);
                     if (vl < 0 || vl >= bv || wl < 0 || wl >= bw) { ++bad; continue; }
                     for (int t = B.tb; t <= B.te; ++t) {
                         const int64_t q = xch_word(B.xoff, B.tlo, nx, wds, t, j);

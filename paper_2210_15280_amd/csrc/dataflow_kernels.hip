@@ -274,7 +274,8 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
             }
         } else {
             // ---------------- compute waves
-            const int vl = l % BV, wl = l / BV;
+            int vl = 0, wl = 0;
+            lane_rc(l, BV, &vl, &wl);
             const int cell = (wl + 1) * GW + (vl + 1);
             const LaneDev& Ln = lanes[(int64_t)b * NT + l];
             const bool valid = Ln.v != 0;
@@ -511,7 +512,8 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
             }
         } else {
             // ---------------- compute waves
-            const int vl = l % BV, wl = l / BV;
+            int vl = 0, wl = 0;
+            lane_rc(l, BV, &vl, &wl);
             const int cell = wl * GW + vl;
             const LaneDev& Ln = lanes[(int64_t)b * NT + l];
             const bool valid = Ln.v != 0;

@@ -8,8 +8,11 @@
 // components, and the hyperplane index of the wavefront schedule is
 //     t = x + 2y + 3z = u + v + w.
 // A "row" is a fixed (v, w), i.e. a fixed (y, z); it runs along x (= along u).
-// Rows are tiled into BV x BW blocks in (v, w) (BV*BW a multiple of 64); one
-// workgroup owns one block, lane = BV (w - W0) + (v - V0).
+// Rows are tiled into BV x BW blocks in (v, w) (BV, BW multiples of 8); one
+// workgroup owns one block.  Lanes go by 8x8 tiles of rows: each 64-lane
+// group (one wavefront) holds one tile (lane_rc / lane_at), so the rows a
+// wavefront shares are close in both v and w and their hyperplane windows
+// overlap as much as possible.
 //
 // Stream layout.  Every per-point array (x, b, r, w, stencil and factor
 // arrays) is stored block by block; inside a block the element of lane l at
@@ -62,6 +65,18 @@ struct BlockDev {
     int64_t base;        // stream index of (tlo, lane 0)
     int64_t xoff;        // first entry of the block's exchange window: len x (BV + BW) entries
 };
+
+// Row (vl, wl) = (v - V0, w - W0) of lane l in a block of width bv, and back:
+// 64-lane group g holds the 8x8 tile (g mod (bv/8), g div (bv/8)) of the
+// block, row-major inside the tile.
+__host__ __device__ inline void lane_rc(int l, int bv, int* vl, int* wl) {
+    const int g = l >> 6, r = l & 63, gv = bv >> 3;
+    *vl = (g % gv) * 8 + (r & 7);
+    *wl = (g / gv) * 8 + (r >> 3);
+}
+__host__ __device__ inline int lane_at(int vl, int wl, int bv) {
+    return (((wl >> 3) * (bv >> 3) + (vl >> 3)) << 6) + ((wl & 7) << 3) + (vl & 7);
+}
 
 // Lane-group decoding for the point-parallel kernels: workgroup x-index g
 // covers lanes [64 (g % groups), +64) of block g / groups.
