@@ -494,3 +494,25 @@ def test_full_size_level9_fp32_surrogate_v1(torch, pkg):
     Cx = _ldlt_apply_at(torch, 9, pts, Lw, Dinv, x, diag_is_inverse=True)
     bp = b[torch.tensor(ip, device="cuda")].cpu().numpy()
     assert np.abs(Cx - bp).max() <= 1e-4 * np.abs(bp).max()
+
+
+def test_maximum_level_10(torch, pkg):
+    # the largest level the interface accepts (1024 intervals per edge,
+    # 177,910,271 points): an FP32 surrogate handle sets up, one sweep from
+    # x = 0 solves L~ D~ L~^T x = b with the kernels' own weights at sampled
+    # points, and further sweeps reduce the residual
+    t = W.make_tet(17, 10, *W.KAPPA_EXP, jitter=0.15)
+    assert O.num_interior(10) == 177_910_271
+    sm = pkg.Smoother([t], pkg.SURR_F32, degree=4, stride=4, tile=(16, 16))
+    assert sm.n_total == O.num_interior(10)
+    b = torch.tensor(t.rhs(), device="cuda")
+    x = torch.zeros_like(b)
+    rel1, _ = sm.smooth(x, b, 1, want_relres=True)
+    pts = np.concatenate([O.random_interior(10, 800, seed=3), _boundary_heavy_points(10, 400, seed=4)])
+    Lw, Dinv = sm.surrogate_values(0)
+    Cx = _ldlt_apply_at(torch, 10, pts, Lw, Dinv, x, diag_is_inverse=True)
+    del Lw, Dinv
+    bp = b[torch.tensor(O.index_of(10, pts), device="cuda")].cpu().numpy()
+    assert np.abs(Cx - bp).max() <= 1e-4 * np.abs(bp).max()
+    rel5, _ = sm.smooth(x, b, 4, want_relres=True)
+    assert 0.0 < rel5 < rel1 < 1.0
