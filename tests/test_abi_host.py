@@ -87,6 +87,7 @@ def test_lfa_orientation_argument_checks(P):
 
 def test_invalid_arguments(P):
     t = W.make_tet(1, 4, W.COEFF_CONST, (1.0,))
+    assert _setup(P, []) == -1                                               # no tetrahedron
     assert _setup(P, [W.Tet(t.verts, 1, 0, (1.0, 0, 0, 0), 0)]) == -1      # level < 2
     assert _setup(P, [W.Tet(t.verts, 11, 0, (1.0, 0, 0, 0), 0)]) == -1     # level > 10
     assert _setup(P, [W.Tet(t.verts, 4, 9, (1.0, 0, 0, 0), 0)]) == -1      # coefficient kind

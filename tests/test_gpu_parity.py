@@ -516,3 +516,26 @@ def test_maximum_level_10(torch, pkg):
     assert np.abs(Cx - bp).max() <= 1e-4 * np.abs(bp).max()
     rel5, _ = sm.smooth(x, b, 4, want_relres=True)
     assert 0.0 < rel5 < rel1 < 1.0
+
+
+def test_zero_sweeps_and_tiny_batch(torch, pkg):
+    # nsweeps = 0 leaves x as it is and reports the residual of the start;
+    # a batch of the smallest lattices (levels 2 and 3: 1 and 35 points) next
+    # to a level-5 one matches the oracle tetrahedron by tetrahedron
+    tets = [W.make_tet(61, 2, *W.KAPPA_SIN, jitter=0.15), W.make_tet(62, 3, *W.KAPPA_SIN, jitter=0.15),
+            W.make_tet(63, 5, *W.KAPPA_EXP, jitter=0.15)]
+    sm = pkg.Smoother(tets, pkg.STORED_F64, tile=(8, 8))
+    b = np.concatenate([t.rhs() for t in tets])
+    x0 = np.random.default_rng(6).uniform(-1, 1, len(b))
+    x = torch.tensor(x0, device="cuda")
+    rel, ok = sm.smooth(x, torch.tensor(b, device="cuda"), 0, want_relres=True)
+    assert ok and np.array_equal(x.cpu().numpy(), x0)
+    r = np.concatenate([O.Problem.from_tet(t).apply(x0[o:o + n]) for t, o, n in zip(tets, sm.offsets, sm.counts)])
+    assert rel == pytest.approx(np.linalg.norm(b - r) / np.linalg.norm(b), rel=1e-12)
+    sm.smooth(x, torch.tensor(b, device="cuda"), 3)
+    xg = x.cpu().numpy()
+    for t, o, n in zip(tets, sm.offsets, sm.counts):
+        P = O.Problem.from_tet(t)
+        L, U, D = P.ilu0()
+        want, _ = P.smooth(L, D, b[o:o + n], x0[o:o + n], nsweeps=3)
+        assert _rel(xg[o:o + n], want) < 1e-12
