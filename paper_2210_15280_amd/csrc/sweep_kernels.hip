@@ -49,9 +49,12 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
                 // padding slots, so padding costs no memory traffic
                 const int64_t off = act[p] ? (int64_t)lpb * tp[p] : 0;
                 const int64_t idx = act[p] ? rs + off : 0;
-                a[p][0] = A8[idx];
+                // the centre weight and b are read once per launch: streaming
+                // loads, so they do not take L2 space from x and the lower
+                // weights, which the neighbours read again
+                a[p][0] = __builtin_nontemporal_load(A8 + idx);
                 xv[p][0] = x[idx];
-                bv[p] = SUB ? b[idx] : 0.0;
+                bv[p] = SUB ? __builtin_nontemporal_load(b + idx) : 0.0;
 #pragma unroll
                 for (int s = 0; s < NLOW; ++s) {
                     const int64_t ql = act[p] ? rpl[s] + off : 0, qu = act[p] ? rpu[s] + off : 0;
@@ -70,8 +73,9 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
                 const double rv = act[p] ? (SUB ? bv[p] - acc : acc) : 0.0;
                 // only active points: the second point of a pair may lie in the next
                 // chunk (the clipped range need not be a multiple of 8 long), whose
-                // item writes it; inactive slots stay 0 from the allocation
-                if (act[p]) r[rs + (int64_t)lpb * tp[p]] = (RT)rv;
+                // item writes it; inactive slots stay 0 from the allocation.  A
+                // streaming store: r is read back only by the next kernel.
+                if (act[p]) __builtin_nontemporal_store((RT)rv, r + rs + (int64_t)lpb * tp[p]);
                 acc2 += rv * rv;
             }
         }
