@@ -307,6 +307,15 @@ int ilu_set_graph(ilu_handle_t h, int32_t enable);
 int ilu_set_overlap(ilu_handle_t h, int32_t mode);
 int ilu_get_overlap(ilu_handle_t h, int32_t *mode);
 
+/* Workgroups of the persistent dataflow sweeps (diagnostics and tests).  By
+ * default the grid holds as many workgroups as can be resident at once, up to
+ * one per block.  grid > 0 caps it (so that every workgroup takes several
+ * blocks from the ticket counter, one after another); grid == 0 restores the
+ * default.  The topological ticket order keeps any grid size free of
+ * deadlock, and the results do not depend on it.  grid_out (host, may be
+ * NULL) receives the grid now in use.  Drops the captured graphs. */
+int ilu_set_flow_grid(ilu_handle_t h, int32_t grid, int32_t *grid_out);
+
 /* Host-only self check (no device needed): builds the stream layout for the
  * given tetrahedra and replays every index the kernels form, counting
  * out-of-range or misdirected accesses in *violations (0 = consistent). */

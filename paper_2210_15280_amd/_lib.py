@@ -80,6 +80,7 @@ def lib():
         L.ilu_set_kernel_timing.argtypes = [P, I32]
         L.ilu_set_graph.argtypes = [P, I32]
         L.ilu_set_overlap.argtypes = [P, I32]
+        L.ilu_set_flow_grid.argtypes = [P, I32, ctypes.POINTER(I32)]
         L.ilu_get_overlap.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_check_layout.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, ctypes.POINTER(ilu_opts),
                                        ctypes.POINTER(I64)]
@@ -299,6 +300,13 @@ class Smoother:
         v = ctypes.c_int32()
         _check(self.L.ilu_get_overlap(self.h, ctypes.byref(v)), "ilu_get_overlap")
         return v.value
+
+    def set_flow_grid(self, grid: int) -> int:
+        """Cap the persistent sweep grid at `grid` workgroups (0: the resident
+        maximum).  Returns the grid now in use."""
+        g = ctypes.c_int32()
+        _check(self.L.ilu_set_flow_grid(self.h, int(grid), ctypes.byref(g)), "ilu_set_flow_grid")
+        return g.value
 
     def set_graph(self, enable: bool):
         """Replay fixed-count sweeps from a captured graph (default on)."""

@@ -95,6 +95,7 @@ struct ilu_handle_s {
     int64_t npartial = 0;      // partial sums of the residual kernel
     int64_t npartial_tag = 0;  // ... and of the tagged one (overlapped residual)
     int flow_grid = 0;
+    int flow_grid_max = 0;               // resident workgroups of the dataflow sweeps (the default grid)
     hipEvent_t ev[8] = {};
     bool have_timing = false;
     bool kernel_timing = false;          // events around every kernel of every sweep
@@ -699,7 +700,8 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     const size_t xwords = (size_t)h->XE * (h->variant == ILU_SURR_F32 ? 1 : 2);
     if (h->xch.alloc(std::max<size_t>(1, xwords) * sizeof(uint64_t), st) || h->ticket.alloc(4 * sizeof(int32_t), st))
         return ILU_ENOMEM;
-    h->flow_grid = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->boundary == ILU_BOUNDARY_V1, h->bv, h->bw));
+    h->flow_grid_max = std::min<int>((int)h->blocks.size(), flow_max_resident(h->variant, h->NC, h->boundary == ILU_BOUNDARY_V1, h->bv, h->bw));
+    h->flow_grid = h->flow_grid_max;
     for (auto& e : h->ev) HIPCHK(hipEventCreate(&e));
     // overlapped residual: tagged entries (one 64-bit word per FP32 value, two
     // per FP64 value), cleared to tag 0, a second stream and fork/join events
@@ -1077,7 +1079,7 @@ int capture_cg(ilu_handle_t h, const Ctx& c) {
     const hipError_t e = hipStreamEndCapture(h->cap, &g);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
     const hipError_t e2 = hipGraphInstantiate(&h->cg_exec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e2 != hipSuccess) {
         h->cg_exec = nullptr;
         return hip_fail(e2, "hipGraphInstantiate", __LINE__);
@@ -1098,12 +1100,12 @@ int capture_sweep(ilu_handle_t h, const Ctx& c) {
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap, &g);  // also after a failed launch: leave no open capture
     if (rc != ILU_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
     const hipError_t e2 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e2 != hipSuccess) {
         h->gexec = nullptr;
         return hip_fail(e2, "hipGraphInstantiate", __LINE__);
@@ -1133,6 +1135,26 @@ double host_norm(ilu_handle_t h, int slot, hipStream_t st, int* err) {
 }  // namespace
 
 namespace {
+// Arguments of the LFA orientation calls: sizes, finite vertices, and a
+// non-degenerate tetrahedron (either orientation).
+int lfa_check_args(const ilu_tet_desc* tets, int32_t ntets, int32_t samples, const double* mu_out,
+                   const int32_t* best_out) {
+    if (!tets || ntets <= 0 || (!mu_out && !best_out) || samples < 4 || samples > 256 || samples % 4) return ILU_EINVAL;
+    for (int i = 0; i < ntets; ++i) {
+        for (int a = 0; a < 4; ++a)
+            for (int r = 0; r < 3; ++r)
+                if (!std::isfinite(tets[i].vertex[a][r])) return ILU_EINVAL;
+        double E[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) E[r][c] = tets[i].vertex[c + 1][r] - tets[i].vertex[0][r];
+        const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                           E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                           E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+        if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return ILU_EGEOM;
+    }
+    return ILU_OK;
+}
+
 int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
     if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_STORED_SGS) return ILU_EINVAL;
     if (opts->boundary != ILU_BOUNDARY_V2 && opts->boundary != ILU_BOUNDARY_V1) return ILU_EINVAL;
@@ -1466,24 +1488,12 @@ int ilu_contraction(ilu_handle_t h, double* x, int32_t nsteps, double* rho_out, 
 
 int ilu_lfa_orientation(const ilu_tet_desc* tets, int32_t ntets, int32_t samples, double* mu_out,
                         int32_t* best_out, void* hip_stream) {
-    if (!tets || ntets <= 0 || (!mu_out && !best_out) || samples < 4 || samples > 256 || samples % 4) return ILU_EINVAL;
+    if (int e = lfa_check_args(tets, ntets, samples, mu_out, best_out)) return e;
     hipStream_t st = (hipStream_t)hip_stream;
     std::vector<double> v((size_t)ntets * 12);
-    for (int i = 0; i < ntets; ++i) {
+    for (int i = 0; i < ntets; ++i)
         for (int a = 0; a < 4; ++a)
-            for (int r = 0; r < 3; ++r) {
-                const double x = tets[i].vertex[a][r];
-                if (!std::isfinite(x)) return ILU_EINVAL;
-                v[(size_t)i * 12 + 3 * a + r] = x;
-            }
-        double E[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) E[r][c] = tets[i].vertex[c + 1][r] - tets[i].vertex[0][r];
-        const double det = E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
-                           E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
-                           E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
-        if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return ILU_EGEOM;
-    }
+            for (int r = 0; r < 3; ++r) v[(size_t)i * 12 + 3 * a + r] = tets[i].vertex[a][r];
     DevBuf dv, drec, dmu;
     const size_t np = (size_t)ntets * LFA_PERMS;
     if (dv.alloc(v.size() * sizeof(double), st, false) || drec.alloc(np * LFA_REC * sizeof(double), st, false) ||
@@ -1646,6 +1656,16 @@ int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable) {
 int ilu_set_graph(ilu_handle_t h, int32_t enable) {
     if (!h) return ILU_EINVAL;
     h->use_graph = enable != 0;
+    return ILU_OK;
+}
+
+int ilu_set_flow_grid(ilu_handle_t h, int32_t grid, int32_t* grid_out) {
+    if (!h || grid < 0) return ILU_EINVAL;
+    const int g = grid == 0 ? h->flow_grid_max : std::min<int>(grid, h->flow_grid_max);
+    if (g != h->flow_grid)
+        if (int e = drop_graphs(h, nullptr)) return e;  // the captured launches carry the old grid
+    h->flow_grid = g;
+    if (grid_out) *grid_out = g;
     return ILU_OK;
 }
 

@@ -7,6 +7,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from parity_util import f64_sweep_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -144,7 +145,8 @@ def test_surrogate_fit_parity(torch, pkg, level, deg, stride):
 
 @pytest.mark.parametrize("sched", list(SCHEDS))
 def test_surrogate_f64_sweep_parity(torch, pkg, sched):
-    # same coefficients on both sides (the oracle's), so only evaluation order differs
+    # same coefficients on both sides (the oracle's): the weights agree to
+    # evaluation order, the sweeps to 1e-12 with the kernel's weights
     t = W.make_tet(6, 6, *W.KAPPA_SIN, jitter=0.15)
     deg = 3
     P = O.Problem.from_tet(t)
@@ -154,14 +156,13 @@ def test_surrogate_f64_sweep_parity(torch, pkg, sched):
     s, tile = SCHEDS[sched]
     sm = pkg.Smoother([t], pkg.SURR_F64, degree=deg, stride=4, schedule=s, tile=tile)
     sm.set_surrogate(0, c)
-    Lg, Dg = sm.surrogate_values(0)
-    assert _rel(Lg.cpu().numpy(), Lw) < 1e-12
-    assert _rel(Dg.cpu().numpy(), Dinv) < 1e-12
+    Lg, Dg = (a.cpu().numpy() for a in sm.surrogate_values(0))
+    assert _rel(Lg, Lw) < 1e-12
+    assert _rel(Dg, Dinv) < 1e-12
     b = t.rhs()
     x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
     sm.smooth(x, torch.tensor(b, device="cuda"), 6)
-    want, _ = P.smooth_stencil(Lw, Dinv, b, nsweeps=6)
-    assert _rel(x.cpu().numpy(), want) < 1e-11
+    f64_sweep_parity(P, x.cpu().numpy(), (Lg, Dg), (Lw, Dinv), b, 6)
 
 
 @pytest.mark.parametrize("sched", list(SCHEDS))
@@ -191,7 +192,8 @@ def test_surrogate_f32_mixed_parity(torch, pkg, sched):
 def test_anisotropic_degree_parity(torch, pkg, deg):
     # anisotropic tensor degrees (dg_x, dg_y, dg_z): the GPU fit against the
     # oracle's (1e-7, the basis conditioning), then FP64 and FP32 sweeps with
-    # the oracle's coefficients (1e-11 and 2e-5, as for isotropic degrees)
+    # the oracle's coefficients (FP64: 1e-12 with the kernel's weights; FP32:
+    # 2e-5, as for isotropic degrees)
     level = 6
     t = W.make_tet(16, level, *W.KAPPA_EXP, jitter=0.15)
     P = O.Problem.from_tet(t)
@@ -205,12 +207,12 @@ def test_anisotropic_degree_parity(torch, pkg, deg):
     assert _rel(Lg.cpu().numpy(), Lo) < 1e-7
     assert _rel(Dg.cpu().numpy(), Do) < 1e-7
     sm.set_surrogate(0, c)
+    Lg, Dg = (a.cpu().numpy() for a in sm.surrogate_values(0))
     b = t.rhs()
     bd = torch.tensor(b, device="cuda")
     x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
     sm.smooth(x, bd, 6)
-    want, _ = P.smooth_stencil(Lo, Do, b, nsweeps=6)
-    assert _rel(x.cpu().numpy(), want) < 1e-11
+    f64_sweep_parity(P, x.cpu().numpy(), (Lg, Dg), (Lo, Do), b, 6)
     sm32 = pkg.Smoother([t], pkg.SURR_F32, degree=deg, stride=4, tile=(16, 16))
     sm32.set_surrogate(0, c)
     x.zero_()

@@ -323,6 +323,54 @@ def test_mixed_precision_sweep_tracks_fp64():
     np.testing.assert_allclose(r32[:5], r[:5], rtol=1e-4)
 
 
+def _dense_unit_lower(P, Lw):
+    # unit-lower L with L[p, p+d] = L^p_d for the lower directions whose
+    # neighbour is interior (the V2 rule drops the others), dtype of Lw
+    N = P.N
+    Lm = np.eye(N, dtype=Lw.dtype)
+    for d in range(O.NLOW):
+        j = P.col[:, d]
+        m = j >= 0
+        Lm[np.nonzero(m)[0], j[m]] = Lw[m, d]
+    return Lm
+
+
+@pytest.mark.parametrize("level,start", [(3, "zero"), (4, "zero"), (4, "random")])
+def test_fp32_emulation_is_fp32_triangular_solves(level, start):
+    # The mixed-precision step (FP64 residual rounded to FP32, both
+    # substitutions in FP32, FP64 update) rebuilt from dense FP32 triangular
+    # solves (LAPACK strtrs through scipy; no code shared with the oracle's
+    # stencil loops): the oracle's FP32 emulation agrees to a few FP32 units of
+    # the correction, and it is not the FP64 step (which it would be if the
+    # emulation ran the substitutions in FP64).  From x = 0 the result is
+    # (double) w with w an FP32 vector, so it is exactly FP32-representable.
+    import scipy.linalg as sla
+    t, P = _jittered(level, *W.KAPPA_EXP)
+    L, U, D = P.ilu0()
+    # a surrogate stand-in: exact factors off by a smooth relative perturbation
+    pts = O.interior_points(level).astype(np.float64) / (1 << level)
+    pert = 1.0 + 0.05 * np.sin(7.0 * pts[:, 0] + 3.0 * pts[:, 1] - 5.0 * pts[:, 2])
+    Lw32 = (L * pert[:, None]).astype(np.float32)
+    Di32 = (pert / D).astype(np.float32)
+    b = t.rhs()
+    x0 = np.zeros(P.N) if start == "zero" else np.random.default_rng(level).uniform(-1, 1, P.N)
+    r32 = (b - P.apply(x0)).astype(np.float32)
+    Lm = _dense_unit_lower(P, Lw32)
+    y = sla.solve_triangular(Lm, r32, lower=True, unit_diagonal=True)
+    z = (Di32 * y).astype(np.float32)
+    w = sla.solve_triangular(Lm, z, lower=True, trans="T", unit_diagonal=True)
+    assert y.dtype == np.float32 and w.dtype == np.float32
+    want = x0 + w.astype(np.float64)
+    got, _ = P.smooth_stencil_f32(Lw32, Di32, b, x0=x0, nsweeps=1)
+    x64, _ = P.smooth_stencil(Lw32.astype(np.float64), Di32.astype(np.float64), b, x0=x0, nsweeps=1)
+    scale = np.abs(w).max()
+    assert np.abs(got - want).max() <= 8 * 2.0 ** -24 * scale
+    assert np.abs(got - x64).max() >= 1e-9 * np.abs(x64).max()
+    if start == "zero":
+        assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+        assert not np.array_equal(x64.astype(np.float32).astype(np.float64), x64)
+
+
 # ----------------------------------------------------------------------- surrogates
 
 
@@ -340,6 +388,31 @@ def test_sample_sets_match_definition():
             assert (i in idx) == ok
     # the c set is the plain coarse grid 1 + s Z^3 (no shift)
     assert all(((pts[sorted(O.sample_set(level, 7, 2))] - 1) % 2 == 0).ravel())
+
+
+@pytest.mark.parametrize("level,stride", [(5, 4), (6, 4), (6, 2)])
+def test_sample_sets_follow_the_figure(level, stride):
+    # Sec. 4.1, the sample-set figure: S_d is a stride-s sub-lattice of the
+    # points whose d-neighbour is interior, placed at the first such point
+    # (brute force over the lattice, no shift formula): no offset for the
+    # centre, an offset from the left (x) for w, from the bottom (z) for be
+    n = 1 << level
+    pts = O.interior_points(level).astype(np.int64)
+    for t in list(range(O.NLOW)) + [O.CENTRE]:
+        d = O.DIRS[t]
+        q = pts + d
+        ok = np.all(q >= 1, axis=1) & (q.sum(axis=1) <= n - 1)
+        first = pts[ok].min(axis=0)            # componentwise first point with p + d interior
+        assert ok[np.nonzero(np.all(pts == first, axis=1))[0]].all()
+        want = np.nonzero(ok & np.all((pts - first) % stride == 0, axis=1))[0]
+        got = O.sample_set(level, t, stride)
+        assert np.array_equal(np.sort(got), want), O.DIR_NAMES[t]
+        if O.DIR_NAMES[t] == "c":
+            assert tuple(first) == (1, 1, 1)
+        if O.DIR_NAMES[t] == "w":
+            assert tuple(first) == (2, 1, 1)
+        if O.DIR_NAMES[t] == "be":
+            assert tuple(first) == (1, 1, 2)
 
 
 @pytest.mark.parametrize("level,stride,deg", [(5, 4, 4), (5, 2, 4), (6, 4, 4), (5, 4, 2)])
