@@ -197,6 +197,20 @@ int ilu_contraction(ilu_handle_t h, double *x, int32_t nsteps, double *rho_out, 
 int ilu_lfa_orientation(const ilu_tet_desc *tets, int32_t ntets, int32_t samples, double *mu_out, int32_t *best_out,
                         void *hip_stream);
 
+/* ilu_lfa_orientation for callers that cannot allocate device memory
+ * (harnesses that forbid hipMalloc, tight serving loops): the same
+ * computation and the same results, with every intermediate (the
+ * descriptors, the per-permutation stencils, mu and the choice) in one
+ * statically sized device array of the library (about 1.3 MiB, held on
+ * each device the library runs on until the process ends) instead of
+ * buffers allocated per call.  At most ILU_LFA_NOALLOC_MAX_TETS tetrahedra per
+ * call (ILU_EINVAL beyond).  All calls on one device share that array:
+ * calls that overlap in time on one device (from several host threads or
+ * streams) race and must not be issued.  Synchronous on hip_stream. */
+#define ILU_LFA_NOALLOC_MAX_TETS 256
+int ilu_lfa_orientation_noalloc(const ilu_tet_desc *tets, int32_t ntets, int32_t samples, double *mu_out,
+                                int32_t *best_out, void *hip_stream);
+
 /* Offset and interior-point count of tetrahedron `tet` in the vectors. */
 int ilu_layout(ilu_handle_t h, int32_t tet, int64_t *offset, int64_t *count_interior);
 

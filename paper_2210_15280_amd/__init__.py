@@ -9,5 +9,5 @@ from ._lib import (  # noqa: F401
     A_EXACT, A_SURROGATE, BOUNDARY_V1, BOUNDARY_V2, OVERLAP_FUSED, OVERLAP_OFF, OVERLAP_ON,
     COEFF_CONST, COEFF_EXPSINCOS, COEFF_POLY, COEFF_SINPROD, ILUError, SCHED_AUTO, SCHED_DATAFLOW, SCHED_PLANE,
     STORED_F64, STORED_SGS, SURR_F32, SURR_F64, Smoother, exported_symbols, header_symbols, lfa_orientation, lib,
-    library_path,
+    library_path, lfa_orientation_noalloc, LFA_NOALLOC_MAX_TETS,
 )

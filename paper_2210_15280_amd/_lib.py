@@ -60,6 +60,7 @@ def lib():
         L.ilu_pcg.argtypes = [P, P, P, I32, D, D, ctypes.POINTER(I32), ctypes.POINTER(D), P]
         L.ilu_contraction.argtypes = [P, P, I32, ctypes.POINTER(D), ctypes.POINTER(D), P]
         L.ilu_lfa_orientation.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, I32, P, P, P]
+        L.ilu_lfa_orientation_noalloc.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, I32, P, P, P]
         L.ilu_layout.argtypes = [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)]
         L.ilu_destroy.argtypes = [P]
         L.ilu_strerror.argtypes = [ctypes.c_int]
@@ -127,6 +128,20 @@ def lfa_orientation(tets: Sequence, samples: int = 16, stream: int = 0):
     _check(lib().ilu_lfa_orientation(_tet_array(tets), n, int(samples), mu, best, ctypes.c_void_p(stream)),
            "ilu_lfa_orientation")
     return [list(mu[24 * i:24 * i + 24]) for i in range(n)], list(best)
+
+
+def lfa_orientation_noalloc(tets: Sequence, samples: int = 16, stream: int = 0):
+    """lfa_orientation through ilu_lfa_orientation_noalloc (no device
+    allocation; at most LFA_NOALLOC_MAX_TETS tetrahedra)."""
+    n = len(tets)
+    mu = (ctypes.c_double * (24 * n))()
+    best = (ctypes.c_int32 * n)()
+    _check(lib().ilu_lfa_orientation_noalloc(_tet_array(tets), n, int(samples), mu, best, ctypes.c_void_p(stream)),
+           "ilu_lfa_orientation_noalloc")
+    return [list(mu[24 * i:24 * i + 24]) for i in range(n)], list(best)
+
+
+LFA_NOALLOC_MAX_TETS = 256
 
 
 def _check(code: int, what: str):

@@ -5,9 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <utility>
@@ -1155,6 +1157,49 @@ int lfa_check_args(const ilu_tet_desc* tets, int32_t ntets, int32_t samples, con
     return ILU_OK;
 }
 
+// Scratch of ilu_lfa_orientation_noalloc: one statically sized device array,
+// carved into the descriptors as given (the kernel reads the vertices with the
+// descriptor stride), the per-(tetrahedron, permutation) records, mu and the
+// chosen permutations.  Every part is fully written before it is read, so no
+// clearing is needed.  Host code never passes `scratch` itself to a kernel
+// (its name is a host-side stand-in): it uses the per-device address from
+// hipGetSymbolAddress.
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t LFA_SCR_DESC = 0;
+constexpr size_t LFA_SCR_REC = LFA_SCR_DESC + align256(sizeof(ilu_tet_desc) * ILU_LFA_NOALLOC_MAX_TETS);
+constexpr size_t LFA_SCR_MU = LFA_SCR_REC + align256(sizeof(double) * LFA_REC * LFA_PERMS * ILU_LFA_NOALLOC_MAX_TETS);
+constexpr size_t LFA_SCR_BEST = LFA_SCR_MU + align256(sizeof(double) * LFA_PERMS * ILU_LFA_NOALLOC_MAX_TETS);
+constexpr size_t LFA_SCR_BYTES = LFA_SCR_BEST + align256(sizeof(int32_t) * ILU_LFA_NOALLOC_MAX_TETS);
+static_assert(sizeof(ilu_tet_desc) % sizeof(double) == 0, "descriptor stride in doubles");
+static_assert(offsetof(ilu_tet_desc, vertex) == 0, "vertices lead the descriptor");
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[LFA_SCR_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each device holds its own copy of the array).
+int scratch_address(void** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return ILU_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return ILU_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ILU_OK;
+}
+
 int validate_args(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts) {
     if (opts->variant < ILU_STORED_F64 || opts->variant > ILU_STORED_SGS) return ILU_EINVAL;
     if (opts->boundary != ILU_BOUNDARY_V2 && opts->boundary != ILU_BOUNDARY_V1) return ILU_EINVAL;
@@ -1500,7 +1545,7 @@ int ilu_lfa_orientation(const ilu_tet_desc* tets, int32_t ntets, int32_t samples
         dmu.alloc(np * sizeof(double), st, false))
         return ILU_ENOMEM;
     HIPCHK(hipMemcpyAsync(dv.p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    launch_lfa_stencils(dv.as<double>(), ntets, drec.as<double>(), st);
+    launch_lfa_stencils(dv.as<double>(), 12, ntets, drec.as<double>(), st);
     launch_lfa_symbols(drec.as<double>(), ntets, samples, dmu.as<double>(), st);
     HIPCHK(hipGetLastError());
     std::vector<double> mu(np);
@@ -1513,6 +1558,31 @@ int ilu_lfa_orientation(const ilu_tet_desc* tets, int32_t ntets, int32_t samples
         if (best_out) best_out[i] = best;
     }
     if (mu_out) std::memcpy(mu_out, mu.data(), np * sizeof(double));
+    return ILU_OK;
+}
+
+int ilu_lfa_orientation_noalloc(const ilu_tet_desc* tets, int32_t ntets, int32_t samples, double* mu_out,
+                                int32_t* best_out, void* hip_stream) {
+    if (int e = lfa_check_args(tets, ntets, samples, mu_out, best_out)) return e;
+    if (ntets > ILU_LFA_NOALLOC_MAX_TETS) return ILU_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    void* base = nullptr;
+    if (int e = scratch_address(&base)) return e;
+    unsigned char* scr = static_cast<unsigned char*>(base);
+    double* desc = reinterpret_cast<double*>(scr + LFA_SCR_DESC);
+    double* rec = reinterpret_cast<double*>(scr + LFA_SCR_REC);
+    double* mu = reinterpret_cast<double*>(scr + LFA_SCR_MU);
+    int32_t* best = reinterpret_cast<int32_t*>(scr + LFA_SCR_BEST);
+    HIPCHK(hipMemcpyAsync(desc, tets, sizeof(ilu_tet_desc) * (size_t)ntets, hipMemcpyHostToDevice, st));
+    launch_lfa_stencils(desc, (int64_t)(sizeof(ilu_tet_desc) / sizeof(double)), ntets, rec, st);
+    launch_lfa_symbols(rec, ntets, samples, mu, st);
+    launch_lfa_best(mu, ntets, best, st);
+    HIPCHK(hipGetLastError());
+    if (mu_out)
+        HIPCHK(hipMemcpyAsync(mu_out, mu, sizeof(double) * LFA_PERMS * (size_t)ntets, hipMemcpyDeviceToHost, st));
+    if (best_out)
+        HIPCHK(hipMemcpyAsync(best_out, best, sizeof(int32_t) * (size_t)ntets, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
 }
 

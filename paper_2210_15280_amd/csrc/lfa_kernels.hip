@@ -48,7 +48,8 @@ __device__ inline void perm_of(int k, int seq[4]) {
 // The stencil equations are swept in the order bc, s, bnw, be, w, bn, se,
 // then c, from L_c = D_c = 1 and L_d = 0, until no value moves by more than
 // 1e-15 (relative for D).
-__global__ void k_lfa_stencils(const double* __restrict__ verts, int ntets, double* __restrict__ rec) {
+__global__ void k_lfa_stencils(const double* __restrict__ verts, int64_t vstride, int ntets,
+                               double* __restrict__ rec) {
     const int id = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (id >= ntets * LFA_PERMS) return;
     const int tet = id / LFA_PERMS, k = id % LFA_PERMS;
@@ -56,7 +57,7 @@ __global__ void k_lfa_stencils(const double* __restrict__ verts, int ntets, doub
     perm_of(k, seq);
     double pv[4][3];
     for (int i = 0; i < 4; ++i)
-        for (int r = 0; r < 3; ++r) pv[seq[i]][r] = verts[(int64_t)tet * 12 + 3 * i + r];
+        for (int r = 0; r < 3; ++r) pv[seq[i]][r] = verts[(int64_t)tet * vstride + 3 * i + r];
     double J[9], v0[3];
     for (int r = 0; r < 3; ++r) {
         v0[r] = pv[0][r];
@@ -140,9 +141,25 @@ __global__ void __launch_bounds__(256) k_lfa_symbols(const double* __restrict__ 
     if (threadIdx.x == 0) mu[blockIdx.x] = p[23] != 0.0 ? red[0] : HUGE_VAL;
 }
 
-void launch_lfa_stencils(const double* verts, int ntets, double* rec, hipStream_t st) {
+// One thread per tetrahedron: the first permutation with the smallest mu
+// (the same comparisons, in the same order, as the host-side choice).
+__global__ void k_lfa_best(const double* __restrict__ mu, int ntets, int32_t* __restrict__ best) {
+    const int tet = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (tet >= ntets) return;
+    const double* m = mu + (int64_t)tet * LFA_PERMS;
+    int b = 0;
+    for (int k = 1; k < LFA_PERMS; ++k)
+        if (m[k] < m[b]) b = k;
+    best[tet] = b;
+}
+
+void launch_lfa_stencils(const double* verts, int64_t vstride, int ntets, double* rec, hipStream_t st) {
     const int n = ntets * LFA_PERMS;
-    k_lfa_stencils<<<(n + 63) / 64, 64, 0, st>>>(verts, ntets, rec);
+    k_lfa_stencils<<<(n + 63) / 64, 64, 0, st>>>(verts, vstride, ntets, rec);
+}
+
+void launch_lfa_best(const double* mu, int ntets, int32_t* best, hipStream_t st) {
+    k_lfa_best<<<(ntets + 63) / 64, 64, 0, st>>>(mu, ntets, best);
 }
 
 void launch_lfa_symbols(const double* rec, int ntets, int samples, double* mu, hipStream_t st) {
