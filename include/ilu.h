@@ -65,7 +65,7 @@ extern "C" {
 
 /* operator in the residual b - A x */
 #define ILU_A_EXACT 0     /* the assembled FP64 stencil (8 values per point in HBM) */
-#define ILU_A_SURROGATE 1 /* surrogate polynomials for A as well (Sec. 4.3): the lower
+#define ILU_A_SURROGATE 1 /* surrogate polynomials for A as well (Sec. 4.2): the lower
                              weights fitted on the sample sets S_d with the same
                              degrees, the upper weights evaluated as the lower
                              polynomials at p - d (symmetric), the centre as minus the
@@ -149,7 +149,7 @@ int stencil_apply(ilu_handle_t h, const double *x, double *y, void *hip_stream);
 
 /* Preconditioned conjugate gradients for A x = b with the handle's C^{-1} as
  * preconditioner: the ILU (stored or surrogate) applied directly as a CG
- * preconditioner as in the CG experiment of Sec. 4.3, or with ILU_STORED_SGS
+ * preconditioner as in the CG experiment of Sec. 4.2, or with ILU_STORED_SGS
  * the symmetric Gauss-Seidel comparator.  Applying C^{-1} is one forward and
  * one backward substitution from zero (in FP32 for ILU_SURR_F32: the vectors,
  * A p and the CG scalars stay FP64).  x (in: start, out: iterate) and b are
@@ -167,7 +167,7 @@ int ilu_pcg(ilu_handle_t h, double *x, const double *b, int32_t maxit, double re
             int32_t *iters_out, double *resnorm_out, void *hip_stream);
 
 /* Asymptotic contraction factor of the smoother by power iteration (the rate
- * definition of the numerical results in Sec. 4.3, applied to one smoothing
+ * definition of the numerical results in Sec. 4.2, applied to one smoothing
  * step): with b = 0 a step maps x to (I - C^{-1} A) x.  Starting from x (FP64
  * device array in the layout above, not zero), nsteps steps are applied, each
  * followed by scaling to unit 2-norm.  rho_out (host): ||x_k||_2 / ||x_{k-1}||_2

@@ -17,13 +17,13 @@ Functions and the passage they follow:
     Problem.v1_weights         stored exact factors in place of the surrogate
   sample_set, fit_surrogate    Sec. 4.1 sample sets S_d and LSQ fit
   eval_surrogate               Sec. 4.1 surrogate polynomials
-  fit/eval_operator_surrogate  Sec. 4.3 surrogate for the operator A itself
+  fit/eval_operator_surrogate  Sec. 4.2 surrogate for the operator A itself
   asymptotic_stencil           Sec. 3 Gauss-Seidel iteration of the stencil equations
-  contraction_factor           Sec. 4.3 asymptotic rate by power iteration, applied to
+  contraction_factor           Sec. 4.2 asymptotic rate by power iteration, applied to
                                the smoother's error propagation I - C^{-1} A
   Problem.sgs_factors          Sec. 2.1 symmetric Gauss-Seidel preconditioner in L D L^T form
-  pcg                          Sec. 4.3 CG experiment: CG preconditioned by C^{-1}
-  lfa_orientation              Sec. 3 (strategy on macro-elements): LFA smoothing factor of
+  pcg                          Sec. 4.2 CG experiment: CG preconditioned by C^{-1}
+  lfa_orientation              Sec. 3.1 (strategy on macro-elements): LFA smoothing factor of
                                the asymptotic ILU stencil for each vertex permutation
 """
 from __future__ import annotations
@@ -282,7 +282,7 @@ class Problem:
 def pcg(problem: "Problem", precond, b, x0=None, maxit: int = 1000, rel_tol: float = 0.0, abs_tol: float = 0.0):
     """Preconditioned conjugate gradients (Hestenes-Stiefel) for A x = b with
     z = precond(r) ~ C^{-1} r, the use of the ILU as a CG preconditioner in
-    Sec. 4.3.  Stops at the first k with ||r_k|| <= max(rel_tol ||b||, abs_tol)
+    Sec. 4.2.  Stops at the first k with ||r_k|| <= max(rel_tol ||b||, abs_tol)
     for the recursively updated residual.  Returns (x, iterations, ||r_k|| per
     iteration starting with k = 0, converged)."""
     b = np.asarray(b, dtype=np.float64)
@@ -417,7 +417,7 @@ def eval_surrogate(level: int, coeffs: np.ndarray, degree, basis: str = "legendr
 
 
 def fit_operator_surrogate(level: int, A: np.ndarray, degree, stride: int, basis: str = "legendre"):
-    """Surrogate for the operator (Sec. 4.3 approximates A by surrogate
+    """Surrogate for the operator (Sec. 4.2 approximates A by surrogate
     polynomials as well): one polynomial per d in D_l fit to A^p_d and one
     for c fit to A^p_c, on the sample sets S_d of the ILU fit (p + d interior,
     so the dropped boundary entries are never samples).  A is the (N,15)
@@ -505,7 +505,7 @@ def asymptotic_stencil(Ad, iters: int = 20000, tol: float = 1e-15):
 
 def contraction_factor(problem: "Problem", step, x0, steps: int = 20):
     """Asymptotic contraction of one smoother by power iteration (the rate
-    definition of the numerical results in Sec. 4.3, applied to the smoothing
+    definition of the numerical results in Sec. 4.2, applied to the smoothing
     step itself): with b = 0 a step maps the error e to (I - C^{-1} A) e.
     Start from x0, apply `steps` steps, normalising after each.
 
@@ -533,7 +533,7 @@ def constant_stencil(verts) -> np.ndarray:
     """The 15 stencil weights A_d (listing order of D) for kappa = 1 at an
     interior point whose neighbours are all interior (level 4, point (4,4,4)):
     with an affine macro map and a constant coefficient every such point has
-    the same stencil (Sec. 3, strategy on macro-elements)."""
+    the same stencil (Sec. 3.1, strategy on macro-elements)."""
     class _T:
         pass
     t = _T()
@@ -579,7 +579,7 @@ def permute_vertices(verts, s):
 def lfa_orientation(verts, samples: int = 16):
     """Smoothing factor mu of the asymptotic ILU stencil (LFA) for each of the
     24 vertex permutations of one macro-tetrahedron, and the index of the
-    smallest (Sec. 3, strategy on macro-elements).  Returns (mu (24,), best)."""
+    smallest (Sec. 3.1, strategy on macro-elements).  Returns (mu (24,), best)."""
     th = lfa_frequencies(samples)
     mu = []
     for s in permutations():

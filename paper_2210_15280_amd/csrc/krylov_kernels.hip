@@ -1,5 +1,5 @@
 // Vector kernels of libilu around the smoother: preconditioned CG with the
-// ILU (stored or surrogate) as preconditioner (the CG experiment of Sec. 4.3),
+// ILU (stored or surrogate) as preconditioner (the CG experiment of Sec. 4.2),
 // its symmetric Gauss-Seidel comparator (Sec. 2.1), and the normalisation of
 // the contraction-factor power iteration.  They run over the active points of
 // stream-layout vectors with the work items of the residual kernel; the CG

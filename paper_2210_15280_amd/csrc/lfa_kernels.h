@@ -1,4 +1,4 @@
-// Launchers of the LFA orientation kernels (Sec. 3, strategy on macro-elements).
+// Launchers of the LFA orientation kernels (Sec. 3.1, strategy on macro-elements).
 #pragma once
 
 #include <hip/hip_runtime.h>

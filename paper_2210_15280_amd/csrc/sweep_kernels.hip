@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
     if (threadIdx.x == 0 && partial) partial[it.id] = red[0];
 }
 
-// Residual with the surrogate operator (Sec. 4.3 approximates A by surrogate
+// Residual with the surrogate operator (Sec. 4.2 approximates A by surrogate
 // polynomials too): the neighbour weights come from the row's table -- the
 // seven lower weights at p, the seven upper weights as the lower polynomials
 // at p - d -- evaluated by Horner in the table's precision TT, and the centre

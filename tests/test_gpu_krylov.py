@@ -1,6 +1,6 @@
 """GPU parity of the pieces around the smoother, through the C-ABI: the
 symmetric Gauss-Seidel comparator, preconditioned CG (ILU as preconditioner,
-Sec. 4.3) and the contraction factor, each against the CPU oracle.
+Sec. 4.2) and the contraction factor, each against the CPU oracle.
 
 Tolerances: FP64 variants take the same decisions as the oracle, so CG runs
 the same number of iterations and the iterates differ by rounding amplified

@@ -1,4 +1,4 @@
-"""GPU parity of the surrogate operator (ILU_A_SURROGATE; Sec. 4.3
+"""GPU parity of the surrogate operator (ILU_A_SURROGATE; Sec. 4.2
 approximates A by surrogate polynomials too), through the C-ABI.
 
 With the oracle's coefficients injected, both sides evaluate the same

@@ -659,7 +659,7 @@ def test_pcg_special_cases():
 
 
 def test_ilu_preconditioner_beats_sgs_and_plain_cg():
-    # the ordering reported with the CG experiment of Sec. 4.3: the ILU
+    # the ordering reported with the CG experiment of Sec. 4.2: the ILU
     # preconditioner needs fewer CG iterations than symmetric Gauss-Seidel
     t, P = _jittered(5, *W.KAPPA_SIN, seed=7)
     b = t.rhs()
@@ -744,7 +744,7 @@ def test_lfa_orientation_matches_printed_choices():
 
 
 def test_z_only_surrogate_on_a_flat_tetrahedron():
-    # distorted tetrahedron of height 0.1 with a unit coefficient (Sec. 4.3):
+    # distorted tetrahedron of height 0.1 with a unit coefficient (Sec. 4.2):
     # the factors vary mainly along z, so dg_x = dg_y = 0 with a high dg_z
     # comes close to the exact ILU's contraction, while a low dg_z does not
     wl = W.workload("flat_L8_const")
