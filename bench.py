@@ -232,6 +232,77 @@ def roofline(res, variant, dg, workload):
             "kernel_ms_per_launch": round(km[dom], 5)}
 
 
+def step_roofline(res, variant, wl):
+    """The whole step (residual, forward and backward substitution) against
+    the HBM roofline: the three kernels' algorithmic bytes per DOF (r and w
+    written and read back between kernels included) over the measured time per
+    step; beside it the compulsory bytes of the fused step, where r never
+    leaves the chip."""
+    bpd = kernel_bytes(variant)
+    step_b = sum(bpd.values())
+    n = res["n_dof"]
+    t = res["ms_per_step"] * 1e-3
+    gbs = step_b * n / t / 1e9
+    wb = 4 if variant.startswith("surr_f32") else 8
+    fused = step_b - 2 * wb
+    return {"bound": "hbm", "bytes_per_dof": step_b, "fused_bytes_per_dof": fused, "achieved": round(gbs, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+            "dof_updates_per_s_at_peak": HBM_PEAK_GBS * 1e9 / step_b,
+            "fused_dof_updates_per_s_at_peak": HBM_PEAK_GBS * 1e9 / fused}
+
+
+def latency_floor(res, variant, wl):
+    """Dependency-latency floor of the two substitutions: each runs the
+    3n - 11 hyperplanes of the largest tetrahedron one after another, so a
+    sweep takes at least 2 (3n - 11) t_h, t_h the time per hyperplane.  Reports
+    the measured t_h (substitution kernel times over the hyperplane count) and
+    the t_h at which the substitutions' algorithmic bytes would bind at the
+    HBM peak instead."""
+    n = 1 << max(t.level for t in wl.tets)
+    hp = 3 * n - 11
+    km = res["kernel_ms"]
+    sweep_ms = km["forward"] + km["backward"]
+    bpd = kernel_bytes(variant)
+    hbm_ms = (bpd["forward"] + bpd["backward"]) * res["n_dof"] / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"hyperplanes_per_substitution": hp, "substitutions_ms": round(sweep_ms, 5),
+            "us_per_hyperplane": round(sweep_ms * 1e3 / (2 * hp), 4),
+            "floor_ms_at_measured_t_h": round(sweep_ms, 5),
+            "hbm_binds_below_us_per_hyperplane": round(hbm_ms * 1e3 / (2 * hp), 4),
+            "substitutions_hbm_bound_ms": round(hbm_ms, 5)}
+
+
+def extra_configs(pkg, torch, steps):
+    """The level-8 refinement to 1e-10 (FP32 surrogate + FP64 refinement vs
+    FP64 stored factors) and the batch of 256 tetrahedra (levels 5-7, FP32
+    surrogate vs FP64 stored, `steps` sweeps as one graph launch)."""
+    import workloads as W
+    out = {}
+    wl8 = W.workload("jit_L8_sin")
+    c3 = {}
+    for v in ("surr_f32", "stored_f64"):
+        r = run_to_tol(pkg, torch, wl8, v, wl8.rel_tol, 20000)
+        r.pop("x")
+        c3[v] = r
+        print("# %s %s: %d sweeps to relres %.3e in %.1f ms" % (wl8.name, v, r["sweeps"], r["relres_after"], r["ms"]),
+              file=sys.stderr, flush=True)
+    c3["time_to_tol_speedup_vs_stored_f64"] = c3["stored_f64"]["ms"] / c3["surr_f32"]["ms"]
+    out[wl8.name + "_to_1e-10"] = c3
+    wlb = W.workload("batch256_L567")
+    c4 = {}
+    for v in ("surr_f32", "stored_f64"):
+        r, h = run_variant(pkg, torch, wlb, v, steps, 3)
+        h.close()
+        torch.cuda.empty_cache()
+        c4[v] = {k: r[k] for k in ("value", "ms_per_step", "setup_s", "kernel_ms", "tile", "relres_after", "n_dof")}
+        c4[v]["roofline"] = step_roofline(r, v, wlb)
+        print("# %s %s: %.3e DOF-updates/s, %.4f ms/step" % (wlb.name, v, r["value"], r["ms_per_step"]),
+              file=sys.stderr, flush=True)
+    c4["speedup_vs_stored_f64"] = c4["surr_f32"]["value"] / c4["stored_f64"]["value"]
+    c4["sweeps_per_graph_launch"] = steps
+    out[wlb.name] = c4
+    return out
+
+
 def cpu_baseline(wl, variant, budget_s=12.0, sample_level=7):
     """The oracle (plain C, one thread) on a bounded sample of the workload: its
     first tetrahedron (same geometry, coefficient, surrogate degree and stride)
@@ -292,6 +363,8 @@ def main():
     ap.add_argument("--workload", default="jit_L9_exp")
     ap.add_argument("--variants", default="surr_f32,stored_f64,surr_f64")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the level-8 refinement and the 256-tetrahedron batch of the default run")
     ap.add_argument("--tile", default="auto", help="block shape BVxBW of the sweep schedule, e.g. 16x32")
     ap.add_argument("--copy-bytes", type=int, default=0, help="also run a streaming copy of this size")
     ap.add_argument("--to-tol", type=float, default=0.0,
@@ -368,10 +441,14 @@ def main():
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "loop_ms_per_step", "relres_after", "setup_s",
                                             "kernel_ms", "tile")} for v, r in results.items()},
         "roofline": roofline(hr, head, wl.degree, wl.name),
+        "step_roofline": step_roofline(hr, head, wl),
+        "latency_floor": latency_floor(hr, head, wl),
         "quality": quality,
     }
     if "stored_f64" in results and head != "stored_f64":
         line["speedup_vs_stored_f64"] = hr["value"] / results["stored_f64"]["value"]
+    if not a.no_extra and a.workload == "jit_L9_exp":
+        line["configs"] = extra_configs(pkg, torch, a.steps)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, head)
     print(json.dumps(line))

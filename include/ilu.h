@@ -286,11 +286,12 @@ int ilu_last_timing(ilu_handle_t h, double *sweep_ms, double *fwd_kernel_ms, dou
 int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable);
 
 /* Graph replay (on by default).  An ilu_smooth call with rel_tol == 0 runs its
- * sweeps as replays of one captured graph per handle.  That graph holds the
- * batched sweep over every tetrahedron: the residual kernel, the forward
- * substitution and the backward substitution with the update, each one
- * persistent launch.  The graph is captured on the first such call, on a
- * private stream, and replayed on the caller's stream.  Calls with
+ * sweeps from captured graphs.  A sweep is the batched sweep over every
+ * tetrahedron: the residual kernel, the forward substitution and the backward
+ * substitution with the update, each one persistent launch.  2 to 64 sweeps
+ * run as one graph launch holding all of them (captured for that count on
+ * the first call with it, on a private stream, and kept until a call asks for
+ * another count); 1 or more than 64 sweeps replay a one-sweep graph.  Calls with
  * rel_tol > 0 (which test the residual between sweeps) and calls with kernel
  * timing on run eagerly.  Results are identical either way.  Per-kernel times
  * of ilu_last_timing are 0 after a graph call. */

@@ -108,6 +108,8 @@ struct ilu_handle_s {
     int last_sweeps = 0;                 // sweeps the last ilu_smooth call ran
     hipStream_t cap = nullptr;           // private stream the sweep graph is captured on
     hipGraphExec_t gexec = nullptr;      // one sweep: residual, forward and backward substitution
+    hipGraphExec_t gexec_n = nullptr;    // gexec_count sweeps in one graph (the last fixed count asked for)
+    int gexec_count = 0;
     DevBuf cg_r, cg_z, cg_p, cg_q, cg_sc;  // PCG vectors (stream layout) and scalars
     int a_mode = ILU_A_EXACT;            // operator of the residual
     int boundary = ILU_BOUNDARY_V2;      // boundary stencils of the surrogate variants
@@ -172,6 +174,7 @@ struct ilu_handle_s {
     }
     ~ilu_handle_s() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (gexec_n) (void)hipGraphExecDestroy(gexec_n);
         if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
         if (cap) (void)hipStreamDestroy(cap);
         if (st2) (void)hipStreamDestroy(st2);
@@ -1089,16 +1092,19 @@ int capture_cg(ilu_handle_t h, const Ctx& c) {
     return ILU_OK;
 }
 
-// Capture one sweep (residual, forward and backward substitution over every
-// tetrahedron of the handle) into an executable graph.  It only touches
-// handle-owned buffers, so it stays valid for the life of the handle; it holds
-// kernel nodes only, and the dataflow tag is advanced by a kernel on device,
-// so every replay is a fresh sweep.
-int capture_sweep(ilu_handle_t h, const Ctx& c) {
+// Capture `count` sweeps (each: residual, forward and backward substitution
+// over every tetrahedron of the handle) into one executable graph.  It only
+// touches handle-owned buffers, so it stays valid for the life of the handle;
+// it holds kernel nodes only, and the dataflow tag is advanced by a kernel on
+// device before every substitution, so every replay runs fresh sweeps.
+int capture_sweeps(ilu_handle_t h, const Ctx& c, int count, hipGraphExec_t* out) {
     if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
     HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    const int rc = sweep_res_fwd(h, c, h->cap, nullptr, nullptr);
-    if (rc == ILU_OK) sweep_bwd(h, c, h->cap);
+    int rc = ILU_OK;
+    for (int k = 0; k < count && rc == ILU_OK; ++k) {
+        rc = sweep_res_fwd(h, c, h->cap, nullptr, nullptr);
+        if (rc == ILU_OK) sweep_bwd(h, c, h->cap);
+    }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap, &g);  // also after a failed launch: leave no open capture
     if (rc != ILU_OK) {
@@ -1106,10 +1112,10 @@ int capture_sweep(ilu_handle_t h, const Ctx& c) {
         return rc;
     }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture", __LINE__);
-    const hipError_t e2 = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e2 != hipSuccess) {
-        h->gexec = nullptr;
+        *out = nullptr;
         return hip_fail(e2, "hipGraphInstantiate", __LINE__);
     }
     return ILU_OK;
@@ -1121,6 +1127,9 @@ int drop_graphs(ilu_handle_t h, hipStream_t st) {
     (void)st;
     HIPCHK(hipDeviceSynchronize());  // a replay may be in flight on any stream
     if (h->gexec) HIPCHK(hipGraphExecDestroy(h->gexec));
+    if (h->gexec_n) HIPCHK(hipGraphExecDestroy(h->gexec_n));
+    h->gexec_n = nullptr;
+    h->gexec_count = 0;
     if (h->cg_exec) HIPCHK(hipGraphExecDestroy(h->cg_exec));
     h->gexec = nullptr;
     h->cg_exec = nullptr;
@@ -1322,10 +1331,26 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
     int done = 0;
     // fixed number of sweeps: replay the captured one-sweep graph
     const bool graph = h->use_graph && rel_tol == 0.0 && !h->kernel_timing && nsweeps > 0;
-    if (graph && !h->gexec)
-        if (int e = capture_sweep(h, c)) return e;
+    // up to MULTI sweeps run as one graph holding all of them (captured for the
+    // count asked for, kept until another count is asked for); longer runs
+    // replay the one-sweep graph
+    constexpr int MULTI = 64;
+    const bool multi = graph && nsweeps > 1 && nsweeps <= MULTI;
+    if (multi && h->gexec_count != nsweeps) {
+        if (h->gexec_n) HIPCHK(hipGraphExecDestroy(h->gexec_n));
+        h->gexec_n = nullptr;
+        h->gexec_count = 0;
+        if (int e = capture_sweeps(h, c, nsweeps, &h->gexec_n)) return e;
+        h->gexec_count = nsweeps;
+    }
+    if (graph && !multi && !h->gexec)
+        if (int e = capture_sweeps(h, c, 1, &h->gexec)) return e;
     HIPCHK(hipEventRecord(h->ev[0], st));
-    for (int k = 0; graph && k < nsweeps; ++k) {
+    if (multi) {
+        HIPCHK(hipGraphLaunch(h->gexec_n, st));
+        done = nsweeps;
+    }
+    for (int k = 0; graph && !multi && k < nsweeps; ++k) {
         HIPCHK(hipGraphLaunch(h->gexec, st));
         ++done;
     }

@@ -72,3 +72,21 @@ def test_lattice_coords_enumerate_the_interior_in_lexicographic_order(level):
     assert (x >= 1).all() and (y >= 1).all() and (z >= 1).all() and (x + y + z <= n - 1).all()
     key = (z * n + y) * n + x  # z slowest, then y, then x
     assert (np.diff(key) > 0).all()
+
+
+def test_step_roofline_and_latency_floor_arithmetic():
+    import workloads as W
+    n = 22_108_415
+    wl = W.workload("jit_L9_exp")
+    res = {"kernel_ms": {"forward": 0.49, "backward": 0.535, "residual": 0.70}, "n_dof": n, "ms_per_step": 1.77}
+    r = bench.step_roofline(res, "surr_f32", wl)
+    # residual 84 + forward 8 + backward 20; the fused step keeps r on chip (4 B out, 4 B in)
+    assert r["bytes_per_dof"] == 112 and r["fused_bytes_per_dof"] == 104
+    gbs = 112 * n / 1.77e-3 / 1e9
+    assert math.isclose(r["achieved"], gbs, rel_tol=1e-3) and math.isclose(r["frac"], gbs / 8000.0, rel_tol=1e-3)
+    assert bench.step_roofline(res, "stored_f64", wl)["bytes_per_dof"] == 88 + 72 + 88
+    f = bench.latency_floor(res, "surr_f32", wl)
+    assert f["hyperplanes_per_substitution"] == 3 * 512 - 11 == 1525
+    assert math.isclose(f["us_per_hyperplane"], (0.49 + 0.535) * 1e3 / 3050, rel_tol=1e-3)
+    hbm_us = (8 + 20) * n / 8e12 * 1e6 / 3050
+    assert math.isclose(f["hbm_binds_below_us_per_hyperplane"], hbm_us, rel_tol=1e-2)

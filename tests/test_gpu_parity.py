@@ -321,6 +321,27 @@ def test_graph_replays_match_eager(torch, pkg, variant, tile):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("variant", ["STORED_F64", "SURR_F32"])
+def test_multi_sweep_graph_matches_eager(torch, pkg, variant):
+    # 20 sweeps as one graph launch, 70 as replays of the one-sweep graph, and
+    # a different count afterwards (the graph is recaptured): bitwise equal to
+    # the same sweeps run eagerly, in a batch of tetrahedra
+    tets = W.batch_tets(71, 5, (4, 5, 6))
+    v = getattr(pkg, variant)
+    kw = {} if v == pkg.STORED_F64 else dict(degree=3, stride=4)
+    sm = pkg.Smoother(tets, v, tile=(8, 8), **kw)
+    b = torch.tensor(np.concatenate([t.rhs() for t in tets]), device="cuda")
+    for n in (20, 70, 7, 20):
+        sm.set_graph(False)
+        xe = torch.zeros_like(b)
+        sm.smooth(xe, b, n)
+        sm.set_graph(True)
+        xg = torch.zeros_like(b)
+        sm.smooth(xg, b, n)
+        torch.cuda.synchronize()
+        assert torch.equal(xg, xe), (variant, n)
+
+
 def test_autotuned_tile(torch, pkg):
     # tile (0, 0): setup times every supported block shape and keeps one; the
     # result equals an explicitly tiled run bit for bit (the per-point
