@@ -72,6 +72,7 @@ def make_smoother(pkg, wl, variant, tile):
     v, a_mode, boundary = VARIANTS[variant]
     kw = {} if variant in STORED else dict(degree=wl.degree, stride=wl.stride, a_mode=a_mode, boundary=boundary)
     return pkg.Smoother(list(wl.tets), v, tile=tile, **kw)
+OVERLAP_NAMES = {0: "sequential", 1: "overlapped", 2: "fused"}
 CONTRACTION_STEPS = 20
 CONTRACTION_SEED = 0x5EED
 KERNEL_NAMES = {"residual": "k_residual", "forward": "k_fwd_flow", "backward": "k_bwd_flow"}
@@ -144,9 +145,11 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
     # asymptotic contraction: power iteration on I - C^{-1} A from a seeded start
     x2.copy_(start_vector(torch, n))
     rho, rho_res = sm.contraction(x2, CONTRACTION_STEPS)
+    grid, grid_max = sm.flow_grid
     out = dict(variant=variant, n_dof=n, setup_s=setup_s, ms_per_step=ms / steps,
                loop_ms_per_step=loop_ms / steps, value=n * steps / (ms * 1e-3), relres_after=rel,
                kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms), tile=list(sm.tile),
+               overlap=OVERLAP_NAMES[sm.overlap()], flow_grid=[grid, grid_max],
                contraction=dict(rho=rho, rho_res=rho_res, steps=CONTRACTION_STEPS))
     return out, sm
 
@@ -218,18 +221,28 @@ def surrogate_quality(torch, stored, surr, tet_level):
 
 
 def roofline(res, variant, dg, workload):
+    """The dominant kernel against the HBM roofline.  Sequential residual:
+    the slowest of the three kernels.  Overlapped residual: the residual
+    kernel (k_residual_tag, timed on its own stream): the forward
+    substitution beside it waits for its bands, so its time is mostly the
+    residual's."""
     bpd = kernel_bytes(variant)
     fpd = kernel_flops(variant, dg)
     km = res["kernel_ms"]
-    dom = max(km, key=km.get)
+    ovl = res.get("overlap") == "overlapped"
+    dom = "residual" if ovl else max(km, key=km.get)
+    name = "k_residual_tag" if ovl else KERNEL_NAMES[dom]
     n = res["n_dof"]
     t = km[dom] * 1e-3
     gbs = bpd[dom] * n / t / 1e9
-    return {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
-            "traffic": measured_traffic(workload, variant, KERNEL_NAMES[dom]),
-            "algorithmic_bytes_per_launch": bpd[dom] * n, "bytes_per_dof": bpd[dom], "flops_per_dof": fpd[dom],
-            "kernel_ms_per_launch": round(km[dom], 5)}
+    out = {"bound": "hbm", "kernel": name, "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 5),
+           "traffic": measured_traffic(workload, variant, name),
+           "algorithmic_bytes_per_launch": bpd[dom] * n, "bytes_per_dof": bpd[dom], "flops_per_dof": fpd[dom],
+           "kernel_ms_per_launch": round(km[dom], 5)}
+    if ovl:
+        out["runs_beside"] = "k_fwd_flow (overlapped residual)"
+    return out
 
 
 def step_roofline(res, variant, wl):
@@ -261,12 +274,16 @@ def latency_floor(res, variant, wl):
     n = 1 << max(t.level for t in wl.tets)
     hp = 3 * n - 11
     km = res["kernel_ms"]
-    sweep_ms = km["forward"] + km["backward"]
     bpd = kernel_bytes(variant)
     hbm_ms = (bpd["forward"] + bpd["backward"]) * res["n_dof"] / (HBM_PEAK_GBS * 1e9) * 1e3
-    return {"hyperplanes_per_substitution": hp, "substitutions_ms": round(sweep_ms, 5),
-            "us_per_hyperplane": round(sweep_ms * 1e3 / (2 * hp), 4),
-            "floor_ms_at_measured_t_h": round(sweep_ms, 5),
+    # with the overlapped residual the forward substitution's time includes
+    # waiting for the residual: t_h then comes from the backward one alone
+    ovl = res.get("overlap") == "overlapped"
+    t_h_ms = km["backward"] / hp if ovl else (km["forward"] + km["backward"]) / (2 * hp)
+    return {"hyperplanes_per_substitution": hp, "substitutions_ms": round(km["forward"] + km["backward"], 5),
+            "us_per_hyperplane": round(t_h_ms * 1e3, 4),
+            "t_h_from": "backward substitution" if ovl else "both substitutions",
+            "floor_ms_at_measured_t_h": round(2 * hp * t_h_ms, 5),
             "hbm_binds_below_us_per_hyperplane": round(hbm_ms * 1e3 / (2 * hp), 4),
             "substitutions_hbm_bound_ms": round(hbm_ms, 5)}
 
@@ -293,7 +310,8 @@ def extra_configs(pkg, torch, steps):
         r, h = run_variant(pkg, torch, wlb, v, steps, 3)
         h.close()
         torch.cuda.empty_cache()
-        c4[v] = {k: r[k] for k in ("value", "ms_per_step", "setup_s", "kernel_ms", "tile", "relres_after", "n_dof")}
+        c4[v] = {k: r[k] for k in ("value", "ms_per_step", "setup_s", "kernel_ms", "tile", "relres_after", "n_dof",
+                                   "overlap", "flow_grid")}
         c4[v]["roofline"] = step_roofline(r, v, wlb)
         print("# %s %s: %.3e DOF-updates/s, %.4f ms/step" % (wlb.name, v, r["value"], r["ms_per_step"]),
               file=sys.stderr, flush=True)
@@ -402,10 +420,12 @@ def main():
     results, handles = {}, {}
     for v in variants:
         results[v], handles[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
-        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, tile %s, kernels %s, contraction %.6f" % (
-            v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],
-            "x".join(map(str, results[v]["tile"])), json.dumps(results[v]["kernel_ms"]),
-            results[v]["contraction"]["rho"]), file=sys.stderr, flush=True)
+        print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, tile %s, grid %s, %s residual, kernels %s, "
+              "contraction %.6f" % (
+                  v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],
+                  "x".join(map(str, results[v]["tile"])), "/".join(map(str, results[v]["flow_grid"])),
+                  results[v]["overlap"], json.dumps(results[v]["kernel_ms"]), results[v]["contraction"]["rho"]),
+              file=sys.stderr, flush=True)
         if v not in STORED and "stored_f64" not in variants:
             handles[v].close()
     quality = {v: {"contraction": r["contraction"]} for v, r in results.items()}
@@ -439,7 +459,7 @@ def main():
                    "surrogate_degree": wl.degree, "sample_stride": wl.stride, "tile": hr["tile"],
                    "parallelism": "single GPU"},
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "loop_ms_per_step", "relres_after", "setup_s",
-                                            "kernel_ms", "tile")} for v, r in results.items()},
+                                            "kernel_ms", "tile", "overlap", "flow_grid")} for v, r in results.items()},
         "roofline": roofline(hr, head, wl.degree, wl.name),
         "step_roofline": step_roofline(hr, head, wl),
         "latency_floor": latency_floor(hr, head, wl),

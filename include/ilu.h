@@ -109,10 +109,13 @@ typedef struct ilu_opts {
     int32_t schedule;       /* ILU_SCHED_* */
     int32_t tile[2];        /* rows per block (BV, BW) of the sweep schedule in the
                                skewed row coordinates (v, w) = (y+z, z): (8,8), (16,16)
-                               or (16,32).  (0,0) = autotuned: setup builds the smoother
-                               with every shape (least-squares fit once), times a few
-                               sweeps of each on the device and keeps the fastest
-                               (hyperplane schedule: chosen from the levels) */
+                               or (16,32).  (0,0) = autotuned: setup times a few sweeps
+                               of every shape on the device (on zeroed buffers: the sweep
+                               kernels' time does not depend on the values), each with
+                               several persistent-grid sizes (ilu_set_flow_grid) and both
+                               residual modes (ilu_set_overlap), keeps the fastest
+                               combination and builds only that one (hyperplane schedule:
+                               the shape is chosen from the levels) */
     int32_t a_mode;         /* ILU_A_EXACT or ILU_A_SURROGATE */
     int32_t boundary;       /* ILU_BOUNDARY_V2 or ILU_BOUNDARY_V1 (surrogate variants) */
 } ilu_opts;
@@ -298,23 +301,25 @@ int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable);
 int ilu_set_graph(ilu_handle_t h, int32_t enable);
 
 /* Residual of ilu_smooth and the forward substitution (modes below;
- * ILU_OVERLAP_OFF by default).  ILU_OVERLAP_ON, where available (dataflow
+ * ILU_OVERLAP_OFF by default with an explicit tile; the autotuner of tile
+ * (0,0) keeps whichever of OFF and ON was faster).  ILU_OVERLAP_ON, where available (dataflow
  * schedule, assembled operator, boundary variant V2), runs each sweep's
  * residual kernel on a second, handle-owned stream at the same time as the
  * forward substitution, which takes each point's residual as soon as it is
  * written (every value carries a sweep tag; one still missing after about
  * 64 us of polling is computed by the forward sweep itself, with the same
- * arithmetic).  ILU_OVERLAP_FUSED runs no residual kernel: the forward sweep
+ * arithmetic; the residual kernel also marks each finished band of
+ * hyperplanes, and the sweep waits for a band's mark before loading its
+ * entries).  ILU_OVERLAP_FUSED runs no residual kernel: the forward sweep
  * computes every residual itself, the first pass of Alg. 2 in its fused form
  * (its loads then sit on the sweep's dependency chain; calls with
  * rel_tol > 0, whose residual kernel also reduces the norm, use
  * ILU_OVERLAP_ON).  Results are bitwise identical in every mode; only the
- * time changes, and on MI355X neither alternative beats the default: the
- * residual kernel, bandwidth-bound, slows down by about as much as the
- * latency-bound forward sweep would save, because the sweep's resident
- * workgroups hold most of the registers.  With overlap the residual of
- * ilu_last_timing is measured on the second stream while the forward
- * substitution runs.  A mode other than ILU_OVERLAP_OFF where it is not
+ * time changes: the overlapped residual pays when the persistent sweep grid
+ * is capped (ilu_set_flow_grid) so that the residual kernel has room beside
+ * the latency-bound sweep, the fused form does not pay on MI355X.  With
+ * overlap the residual of ilu_last_timing is measured on the second stream
+ * while the forward substitution runs.  A mode other than ILU_OVERLAP_OFF where it is not
  * available returns ILU_EINVAL. */
 #define ILU_OVERLAP_OFF 0   /* residual kernel, then the forward substitution */
 #define ILU_OVERLAP_ON 1    /* residual kernel beside the forward substitution */
@@ -330,6 +335,8 @@ int ilu_get_overlap(ilu_handle_t h, int32_t *mode);
  * deadlock, and the results do not depend on it.  grid_out (host, may be
  * NULL) receives the grid now in use.  Drops the captured graphs. */
 int ilu_set_flow_grid(ilu_handle_t h, int32_t grid, int32_t *grid_out);
+/* The grid in use (*grid_out) and the default one (*grid_max_out, may be NULL). */
+int ilu_get_flow_grid(ilu_handle_t h, int32_t *grid_out, int32_t *grid_max_out);
 
 /* Host-only self check (no device needed): builds the stream layout for the
  * given tetrahedra and replays every index the kernels form, counting

@@ -82,6 +82,7 @@ def lib():
         L.ilu_set_graph.argtypes = [P, I32]
         L.ilu_set_overlap.argtypes = [P, I32]
         L.ilu_set_flow_grid.argtypes = [P, I32, ctypes.POINTER(I32)]
+        L.ilu_get_flow_grid.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.ilu_get_overlap.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_check_layout.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, ctypes.POINTER(ilu_opts),
                                        ctypes.POINTER(I64)]
@@ -322,6 +323,13 @@ class Smoother:
         g = ctypes.c_int32()
         _check(self.L.ilu_set_flow_grid(self.h, int(grid), ctypes.byref(g)), "ilu_set_flow_grid")
         return g.value
+
+    @property
+    def flow_grid(self):
+        """(grid in use, default grid) of the persistent sweeps."""
+        g, m = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.L.ilu_get_flow_grid(self.h, ctypes.byref(g), ctypes.byref(m)), "ilu_get_flow_grid")
+        return g.value, m.value
 
     def set_graph(self, enable: bool):
         """Replay fixed-count sweeps from a captured graph (default on)."""

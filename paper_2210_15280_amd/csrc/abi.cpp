@@ -121,6 +121,7 @@ struct ilu_handle_s {
     bool ovl_ok = false;                 // the overlapped residual is available (dataflow, exact A, V2)
     int ovl = ILU_OVERLAP_OFF;           // ILU_OVERLAP_* mode of ilu_smooth
     DevBuf rt;                           // its tagged residual entries
+    DevBuf rflag;                        // its band marks (tag per 64-lane group and hyperplane band)
     hipStream_t st2 = nullptr;           // stream of the overlapped residual
     hipEvent_t oev[2] = {};              // fork and join events
 
@@ -598,11 +599,14 @@ int build_v1b(ilu_handle_t h, hipStream_t st) {
     return ILU_OK;
 }
 
+int setup_sweep_buffers(ilu_handle_t h, hipStream_t st);
+
 // Full setup of one handle.  With `coef_in` (surrogate variants only) the
 // least-squares fit is skipped and these coefficients are used: the fit does
 // not depend on the block shape, so the tile autotuner fits once.
 int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t h,
-               const std::vector<double>* coef_in = nullptr, const std::vector<double>* coefA_in = nullptr) {
+               const std::vector<double>* coef_in = nullptr, const std::vector<double>* coefA_in = nullptr,
+               bool timing_only = false) {
     int64_t soff = 0;
     if (int e = prepare(tets, ntets, opts, h, &soff)) return e;
     const bool surr = h->variant != ILU_STORED_F64;
@@ -612,11 +616,35 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     if (h->flags.alloc(4 * sizeof(int32_t), st) != hipSuccess) return ILU_ENOMEM;
     const int64_t S = h->S;
     if (h->A8.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    const bool v1 = h->boundary == ILU_BOUNDARY_V1;
+    if (timing_only) {
+        // every buffer the sweeps read, zero: their kernels have no
+        // data-dependent control flow, so the time does not depend on values
+        const bool f32 = h->variant == ILU_SURR_F32;
+        const size_t nslots = (size_t)h->blocks.size() * h->bv * h->bw, rec = 2 + 15 * (size_t)h->NC;
+        if (!surr) {
+            if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) || h->Lb.alloc((size_t)8 * S * sizeof(double), st))
+                return ILU_ENOMEM;
+        } else {
+            h->coef_h.assign((size_t)ntets * NFIT * h->K, 0.0);
+            if (h->tab64.alloc(nslots * rec * sizeof(double), st) ||
+                (f32 && h->tab32.alloc(nslots * rec * sizeof(float), st)))
+                return ILU_ENOMEM;
+            if (h->a_mode == ILU_A_SURROGATE &&
+                (h->tabA64.alloc(nslots * rec * sizeof(double), st) ||
+                 (f32 && h->tabA32.alloc(nslots * rec * sizeof(float), st))))
+                return ILU_ENOMEM;
+            const size_t es = f32 ? sizeof(float) : sizeof(double);
+            if (v1 && (h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) ||
+                       h->v1b.alloc((size_t)8 * (h->v1_nbk + 1) * es, st)))
+                return ILU_ENOMEM;
+        }
+        return setup_sweep_buffers(h, st);
+    }
     launch_assemble(h->ctx(), h->A8.as<double>(), nullptr, st);
     HIPCHK(hipGetLastError());
     // factorisation on the hyperplane schedule
     int32_t fl[4];
-    const bool v1 = h->boundary == ILU_BOUNDARY_V1;
     if (refit || v1) {
         if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
@@ -689,7 +717,13 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         }
         if (int e = build_tables_from(h, st, h->coefA_d, h->tabA64, h->tabA32)) return e;
     }
-    // sweep buffers
+    return setup_sweep_buffers(h, st);
+}
+
+// The buffers of the smoothing step (streams, partial sums, exchange, the
+// overlapped residual) and the default grid of the persistent sweeps.
+int setup_sweep_buffers(ilu_handle_t h, hipStream_t st) {
+    const int64_t S = h->S;
     const size_t es = h->variant == ILU_SURR_F32 ? sizeof(float) : sizeof(double);
     if (h->xs.alloc((size_t)S * 8, st) || h->bs.alloc((size_t)S * 8, st) || h->r.alloc((size_t)S * es, st) ||
         h->w.alloc((size_t)S * es, st))
@@ -713,6 +747,8 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     h->ovl_ok = h->schedule == ILU_SCHED_DATAFLOW && h->a_mode == ILU_A_EXACT && h->boundary == ILU_BOUNDARY_V2;
     if (h->ovl_ok) {
         if (h->rt.alloc((size_t)S * (h->variant == ILU_SURR_F32 ? 1 : 2) * sizeof(uint64_t), st)) return ILU_ENOMEM;
+        if (h->rflag.alloc((size_t)std::max<int64_t>(1, (int64_t)c.nblocks * c.groups * c.res_bands) * sizeof(uint64_t), st))
+            return ILU_ENOMEM;
         HIPCHK(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
         for (auto& e : h->oev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
@@ -742,53 +778,63 @@ int time_sweep(ilu_handle_t h, hipStream_t st, int reps, double* ms) {
     return fl[2] ? ILU_EHIP : ILU_OK;
 }
 
-// Tile autotuner: set the handle up with every supported block shape (the
-// least-squares fit only once), time a few sweeps of each and keep the fastest.
-// Shapes whose sweep kernels would spill registers are skipped.
+// Autotuner (tile (0, 0)).  For every supported block shape a timing-only
+// handle (layout and zeroed buffers: no assembly, factorisation or fit) times
+// a few sweeps with several persistent-grid sizes, in both residual modes
+// where the overlapped one is available (a latency-bound sweep on a capped
+// grid leaves room for the bandwidth-bound residual beside it); the fastest
+// combination is then set up in full, once.  Shapes whose sweep kernels would
+// spill registers are skipped.
 int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t* out) {
     static const int shapes[3][2] = {{8, 8}, {16, 16}, {16, 32}};
-    ilu_handle_t best = nullptr;
+    int best_sh = -1, best_grid = 0, best_ovl = ILU_OVERLAP_OFF;
     double best_ms = 0.0;
-    const std::vector<double>* coef = nullptr;
-    const std::vector<double>* coefA = nullptr;
-    std::vector<double> coef_keep, coefA_keep;
-    for (const auto& sh : shapes) {
+    for (int si = 0; si < 3; ++si) {
+        const int* sh = shapes[si];
         if (opts->variant == ILU_SURR_F64 && opts->degree[0] >= 3 && sh[1] == 32) continue;
         ilu_opts o = *opts;
         o.tile[0] = sh[0];
         o.tile[1] = sh[1];
         ilu_handle_t h = new (std::nothrow) ilu_handle_s();
-        if (!h) {
-            delete best;
-            return ILU_ENOMEM;
-        }
-        int rc = setup_impl(tets, ntets, &o, st, h, coef, coefA);
-        double ms = 0.0;
-        if (rc == ILU_OK) rc = time_sweep(h, st, 3, &ms);
-        if (rc != ILU_OK) {
-            (void)hipStreamSynchronize(st);
-            delete h;
-            delete best;
-            return rc;
-        }
-        if (h->variant != ILU_STORED_F64 && !coef) {
-            coef_keep = h->coef_h;
-            coef = &coef_keep;
-            if (h->a_mode == ILU_A_SURROGATE) {
-                coefA_keep = h->coefA_h;
-                coefA = &coefA_keep;
+        if (!h) return ILU_ENOMEM;
+        int rc = setup_impl(tets, ntets, &o, st, h, nullptr, nullptr, true);
+        const int gmax = h->flow_grid_max;
+        struct Cand { int ovl, grid; };
+        Cand cands[5] = {{ILU_OVERLAP_OFF, gmax}, {ILU_OVERLAP_OFF, gmax / 2}, {ILU_OVERLAP_OFF, gmax / 3},
+                         {ILU_OVERLAP_ON, gmax / 2}, {ILU_OVERLAP_ON, gmax / 4}};
+        for (const Cand& cd : cands) {
+            if (rc != ILU_OK) break;
+            if (cd.grid < 1 || (cd.ovl != ILU_OVERLAP_OFF && !h->ovl_ok)) continue;
+            h->flow_grid = cd.grid;
+            h->ovl = cd.ovl;
+            double ms = 0.0;
+            rc = time_sweep(h, st, 3, &ms);
+            if (rc == ILU_OK && (best_sh < 0 || ms < best_ms)) {
+                best_sh = si;
+                best_grid = cd.grid;
+                best_ovl = cd.ovl;
+                best_ms = ms;
             }
         }
-        if (!best || ms < best_ms) {
-            delete best;
-            best = h;
-            best_ms = ms;
-        } else {
-            delete h;
-        }
+        (void)hipStreamSynchronize(st);
+        delete h;
+        if (rc != ILU_OK) return rc;
     }
-    best->tuned_ms = best_ms;
-    *out = best;
+    if (best_sh < 0) return ILU_EINVAL;
+    ilu_opts o = *opts;
+    o.tile[0] = shapes[best_sh][0];
+    o.tile[1] = shapes[best_sh][1];
+    ilu_handle_t h = new (std::nothrow) ilu_handle_s();
+    if (!h) return ILU_ENOMEM;
+    if (int rc = setup_impl(tets, ntets, &o, st, h)) {
+        (void)hipStreamSynchronize(st);
+        delete h;
+        return rc;
+    }
+    h->flow_grid = std::min(best_grid, h->flow_grid_max);
+    h->ovl = h->ovl_ok ? best_ovl : ILU_OVERLAP_OFF;
+    h->tuned_ms = best_ms;
+    *out = h;
     return ILU_OK;
 }
 
@@ -1021,6 +1067,8 @@ int sweep_res_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* partial,
     }
     Flow f = h->flow();
     f.rt = h->rt.as<uint64_t>();
+    f.rflag = h->rflag.as<uint64_t>();
+    f.nbands = c.res_bands;
     f.xo = h->xs.as<double>();
     f.bo = h->bs.as<double>();
     launch_flow_reset(f, st);  // the tag of this sweep, read by both kernels
@@ -1040,6 +1088,7 @@ int sweep_res_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* partial,
     HIPCHK(hipStreamWaitEvent(h->st2, h->oev[0], 0));
     if (mk) HIPCHK(hipEventRecord(mk[0], h->st2));
     launch_residual_tagged(c, h->xs.as<double>(), h->bs.as<double>(), h->rt.as<uint64_t>(), f32, f.ticket + 2,
+                           h->rflag.as<uint64_t>(),
                            partial, h->st2);
     if (mk) HIPCHK(hipEventRecord(mk[1], h->st2));
     HIPCHK(hipEventRecord(h->oev[1], h->st2));
@@ -1751,6 +1800,13 @@ int ilu_set_kernel_timing(ilu_handle_t h, int32_t enable) {
 int ilu_set_graph(ilu_handle_t h, int32_t enable) {
     if (!h) return ILU_EINVAL;
     h->use_graph = enable != 0;
+    return ILU_OK;
+}
+
+int ilu_get_flow_grid(ilu_handle_t h, int32_t* grid_out, int32_t* grid_max_out) {
+    if (!h || !grid_out) return ILU_EINVAL;
+    *grid_out = h->flow_grid;
+    if (grid_max_out) *grid_max_out = h->flow_grid_max;
     return ILU_OK;
 }
 

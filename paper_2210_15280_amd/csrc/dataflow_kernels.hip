@@ -187,8 +187,9 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                int nblocks, int64_t S, const double* __restrict__ Lf, const T* __restrict__ tab,
                const T* __restrict__ v1, int64_t v1s, const T* __restrict__ r, const uint64_t* __restrict__ rt,
                const double* __restrict__ A8, const double* __restrict__ xo, const double* __restrict__ bo,
-               int rspin0, T* __restrict__ w, const int32_t* __restrict__ order, uint64_t* __restrict__ xch,
-               int32_t* __restrict__ ticket, int32_t* __restrict__ flags) {
+               int rspin0, const uint64_t* __restrict__ rflag, int nbands, T* __restrict__ w,
+               const int32_t* __restrict__ order, uint64_t* __restrict__ xch, int32_t* __restrict__ ticket,
+               int32_t* __restrict__ flags) {
     constexpr int NT = BV * BW;
     constexpr int GW = BV + 1;
     constexpr int GC = (BV + 1) * (BW + 1);
@@ -325,7 +326,24 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                 RE rA[UU], rB[UU];
                 LT LA[NL], LB[NL];
                 int rspin = rspin0;  // polls of a stale residual entry before computing it here
+                // OVL: the residual kernel marks every (64-lane group, hyperplane band)
+                // it has finished; before loading the residuals of a new band the
+                // wave waits for its group's mark (a bounded wait: the per-point tags
+                // stay the guarantee), so it does not poll the entries point by point
+                int band_ok = -1;
+                auto wait_band = [&](const int th) {
+                    if constexpr (OVL) {
+                        const int k = min(th, te) / RES_T;
+                        if (k > band_ok) {
+                            const uint64_t* fl = rflag + ((int64_t)b * (NT / WAVE) + l / WAVE) * nbands + k;
+                            for (int it = 0; it < (1 << 16) && (uint32_t)ld_dev(fl) != tag; ++it)
+                                __builtin_amdgcn_s_sleep(8);
+                            band_ok = k;
+                        }
+                    }
+                };
                 auto prefetch = [&](const int T0, RE (&rx)[UU], LT (&Lx)[NL]) {
+                    wait_band(T0 + UU - 1);
 #pragma unroll
                     for (int q = 0; q < UU; ++q) {
                         // inactive points read the (cache-resident) zero region, not padding
@@ -711,7 +729,7 @@ struct Shape {
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
         k_fwd_flow<double, true, false, OVL, (OVL ? UO_F64 : U_F64), D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
             c.tets, c.blocks, c.lanes, c.nblocks, c.S, c.Lf, nullptr, nullptr, 0, (const double*)c.r, f.rt, c.A8,
-            f.xo, f.bo, f.rspin, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
+            f.xo, f.bo, f.rspin, f.rflag, f.nbands, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
     }
     static void bwd_stored(const Ctx& c, const Flow& f, double* x, hipStream_t st) {
         k_bwd_flow<double, true, false, U_F64B, D_F64, 0, BV, BW><<<f.grid, NT + (D_F64 + 1) * WAVE, 0, st>>>(
@@ -723,11 +741,11 @@ struct Shape {
         if (variant == 1)
             k_fwd_flow<double, false, V1, OVL, (OVL ? UO_S64 : U_S64), D_S64, NC, BV, BW><<<f.grid, NT + (D_S64 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.v1f, c.v1f_stride,
-                (const double*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
+                (const double*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, f.rflag, f.nbands, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
         else
             k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.v1f, c.v1f_stride,
-                (const float*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, (float*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
+                (const float*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, f.rflag, f.nbands, (float*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
     }
     template <int NC, bool V1>
     static void bwd(const Ctx& c, const Flow& f, int variant, double* x, hipStream_t st) {

@@ -12,7 +12,7 @@ void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bo
 // partial sums of ||r||^2
 int64_t res_tag_partials(const Ctx& c);
 void launch_residual_tagged(const Ctx& c, const double* x, const double* b, uint64_t* rt, bool f32,
-                            const int32_t* tagp, double* partial, hipStream_t st);
+                            const int32_t* tagp, uint64_t* rflag, double* partial, hipStream_t st);
 void launch_sumsq(const Ctx& c, const double* v, double* partial, hipStream_t st);
 // number of partial sums the residual and norm kernels write
 int64_t res_partials(const Ctx& c);
@@ -37,6 +37,8 @@ struct Flow {
     const double* xo = nullptr;
     const double* bo = nullptr;
     int rspin = 0;                       // polls of a missing entry before computing it
+    const uint64_t* rflag = nullptr;     // per (block, 64-lane group, band): the tag once the residual kernel
+    int nbands = 0;                      // finished that band (bands of RES_T absolute hyperplanes)
 };
 void launch_flow_reset(const Flow& f, hipStream_t st);
 void launch_fwd_flow(const Ctx& c, const Flow& f, int variant, hipStream_t st);

@@ -93,54 +93,74 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
 // (XEnt<RT> words, tag *tagp) instead of plain values, produced in the order
 // the sweep consumes them -- workgroup (x, y) takes the lanes of its block
 // over the absolute hyperplanes [y RES_T, (y+1) RES_T), so the grid sweeps the
-// whole batch band by band in hyperplane order -- with one point per thread
-// and iteration and few registers, so that it fits on the CUs beside the
-// resident sweep workgroups.  Values and the order of the products are those
-// of residual_point.
+// whole batch band by band in hyperplane order.  The per-thread work is that
+// of k_residual (two points per iteration, every load of both issued before
+// the arithmetic); values and the order of the products are those of
+// residual_point.
 template <typename RT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(256)
     k_residual_tag(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                    const LaneDev* __restrict__ lanes, int lpb, int groups, int nblocks, int64_t S,
                    const double* __restrict__ A8, const double* __restrict__ x, const double* __restrict__ b,
-                   uint64_t* __restrict__ rt, const int32_t* __restrict__ tagp, double* __restrict__ partial) {
+                   uint64_t* __restrict__ rt, const int32_t* __restrict__ tagp, uint64_t* __restrict__ rflag,
+                   double* __restrict__ partial) {
     __shared__ double red[256];
     const Item it = res_item(groups, nblocks);
     const uint32_t tag = (uint32_t)tagp[0];
+    const int sub = threadIdx.x >> 6;
     double acc2 = 0.0;
     const BlockDev& B = blocks[it.live ? it.blk : 0];
     const LaneDev& Ln = lanes[(int64_t)(it.live ? it.blk : 0) * lpb + (it.live ? it.lane : 0)];
     const int t0 = max(max(B.tb, it.chunk * RES_T), Ln.gt[0]);
     const int t1 = min(min(B.te, it.chunk * RES_T + RES_T - 1), Ln.gt[1]);
-    if (it.live && Ln.v != 0 && t0 <= t1) {
+    if (it.live && t0 <= t1) {
         const int n = tets[B.tet].n, v = Ln.v, w = Ln.w;
+        const bool valid = v != 0;
         const int64_t rs = Ln.rp[R_SELF];
-        for (int t = t0 + (int)(threadIdx.x >> 6); t <= t1; t += 4) {
-            const int xx = t - 2 * v - w;
-            if (xx < 1 || xx > n - 1 - v) continue;
-            const int64_t off = (int64_t)lpb * t, idx = rs + off;
-            double a[15], xv[15];
-            a[0] = A8[idx];
-            xv[0] = x[idx];
-            const double bv = b[idx];
+        int64_t rpl[NLOW], rpu[NLOW];
 #pragma unroll
-            for (int s = 0; s < NLOW; ++s) {
-                const int64_t ql = Ln.rp[low_row(s)] + (int64_t)lpb * low_dt(s) + off;
-                const int64_t qu = Ln.rp[up_row(s)] + (int64_t)lpb * up_dt(s) + off;
-                a[1 + 2 * s] = A8[(int64_t)(1 + s) * S + idx];
-                xv[1 + 2 * s] = x[ql];
-                a[2 + 2 * s] = A8[(int64_t)(1 + s) * S + qu];
-                xv[2 + 2 * s] = x[qu];
+        for (int s = 0; s < NLOW; ++s) {
+            rpl[s] = Ln.rp[low_row(s)] + (int64_t)lpb * low_dt(s);
+            rpu[s] = Ln.rp[up_row(s)] + (int64_t)lpb * up_dt(s);
+        }
+        for (int t = t0 + sub; t <= t1; t += 8) {
+            const int tp[2] = {t, t + 4};
+            bool act[2];
+            double a[2][15], xv[2][15], bv[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int xx = tp[p] - 2 * v - w;
+                act[p] = valid && xx >= 1 && xx <= n - 1 - v && tp[p] <= t1;
+                const int64_t off = act[p] ? (int64_t)lpb * tp[p] : 0;
+                const int64_t idx = act[p] ? rs + off : 0;
+                a[p][0] = __builtin_nontemporal_load(A8 + idx);
+                xv[p][0] = x[idx];
+                bv[p] = __builtin_nontemporal_load(b + idx);
+#pragma unroll
+                for (int s = 0; s < NLOW; ++s) {
+                    const int64_t ql = act[p] ? rpl[s] + off : 0, qu = act[p] ? rpu[s] + off : 0;
+                    a[p][1 + 2 * s] = A8[(int64_t)(1 + s) * S + idx];
+                    xv[p][1 + 2 * s] = x[ql];
+                    a[p][2 + 2 * s] = A8[(int64_t)(1 + s) * S + qu];
+                    xv[p][2 + 2 * s] = x[qu];
+                }
             }
-            double acc = a[0] * xv[0];
 #pragma unroll
-            for (int k = 1; k < 15; ++k) acc = fma(a[k], xv[k], acc);
-            const double rv = bv - acc;
-            x_put(rt + idx * XEnt<RT>::W, (RT)rv, tag);
-            acc2 += rv * rv;
+            for (int p = 0; p < 2; ++p) {
+                double acc = a[p][0] * xv[p][0];
+#pragma unroll
+                for (int k = 1; k < 15; ++k) acc = fma(a[p][k], xv[p][k], acc);
+                const double rv = act[p] ? bv[p] - acc : 0.0;
+                if (act[p]) x_put(rt + (rs + (int64_t)lpb * tp[p]) * XEnt<RT>::W, (RT)rv, tag);
+                acc2 += rv * rv;
+            }
         }
     }
     red[threadIdx.x] = acc2;
+    // the band mark is a pacing hint for the sweep, which relies on the
+    // entries' own tags; no fence (an agent-scope release writes back the L2)
     __syncthreads();
+    if (threadIdx.x == 0 && it.live) st_dev(rflag + (int64_t)blockIdx.x * gridDim.y + blockIdx.y, (uint64_t)tag);
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
@@ -465,10 +485,10 @@ void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bo
 int64_t res_tag_partials(const Ctx& c) { return (int64_t)c.nblocks * c.groups * c.res_bands; }
 
 void launch_residual_tagged(const Ctx& c, const double* x, const double* b, uint64_t* rt, bool f32,
-                            const int32_t* tagp, double* partial, hipStream_t st) {
+                            const int32_t* tagp, uint64_t* rflag, double* partial, hipStream_t st) {
     const dim3 grid((unsigned)(c.nblocks * c.groups), (unsigned)c.res_bands);
-    if (f32) k_residual_tag<float><<<grid, 256, 0, st>>>(ILU_RES_ARGS, rt, tagp, partial);
-    else k_residual_tag<double><<<grid, 256, 0, st>>>(ILU_RES_ARGS, rt, tagp, partial);
+    if (f32) k_residual_tag<float><<<grid, 256, 0, st>>>(ILU_RES_ARGS, rt, tagp, rflag, partial);
+    else k_residual_tag<double><<<grid, 256, 0, st>>>(ILU_RES_ARGS, rt, tagp, rflag, partial);
 #undef ILU_RES_ARGS
 }
 

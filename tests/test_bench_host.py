@@ -90,3 +90,18 @@ def test_step_roofline_and_latency_floor_arithmetic():
     assert math.isclose(f["us_per_hyperplane"], (0.49 + 0.535) * 1e3 / 3050, rel_tol=1e-3)
     hbm_us = (8 + 20) * n / 8e12 * 1e6 / 3050
     assert math.isclose(f["hbm_binds_below_us_per_hyperplane"], hbm_us, rel_tol=1e-2)
+
+
+def test_overlapped_residual_reporting():
+    import workloads as W
+    n = 22_108_415
+    wl = W.workload("jit_L9_exp")
+    res = {"kernel_ms": {"forward": 1.03, "backward": 0.535, "residual": 0.925}, "n_dof": n, "ms_per_step": 1.6,
+           "overlap": "overlapped"}
+    r = bench.roofline(res, "surr_f32", 6, "no_such_workload")
+    # the bandwidth-bound residual, timed on its own stream, not the waiting forward sweep
+    assert r["kernel"] == "k_residual_tag" and r["kernel_ms_per_launch"] == 0.925
+    assert math.isclose(r["achieved"], 84 * n / 0.925e-3 / 1e9, rel_tol=1e-3)
+    f = bench.latency_floor(res, "surr_f32", wl)
+    assert f["t_h_from"] == "backward substitution"
+    assert math.isclose(f["us_per_hyperplane"], 0.535e3 / 1525, rel_tol=1e-3)

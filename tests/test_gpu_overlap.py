@@ -114,3 +114,24 @@ def test_overlap_availability(pkg):
     sm = pkg.Smoother([t], pkg.STORED_F64, tile=(8, 8))
     with pytest.raises(L.ILUError):
         sm.set_overlap(3)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 0])
+@pytest.mark.parametrize("variant", [0, 2])
+def test_overlap_on_capped_grids(torch, pkg, variant, grid):
+    # the overlapped residual beside a forward sweep on a capped grid (the
+    # combination the autotuner picks for large tetrahedra): the sweep waits
+    # for the residual's band marks, and the iterates equal the sequential
+    # ones bit for bit, eagerly and from the graph, on a batch
+    tets = W.batch_tets(53, 4, (5, 6))
+    kw = {} if variant == 0 else dict(degree=3, stride=4)
+    sm = pkg.Smoother(tets, variant, tile=(8, 8), **kw)
+    b = torch.tensor(np.concatenate([t.rhs() for t in tets]), device="cuda")
+    ref = _run(torch, sm, b, 4, pkg.OVERLAP_OFF, False)
+    assert sm.set_flow_grid(grid) >= 1
+    for graph in (False, True):
+        assert np.array_equal(_run(torch, sm, b, 4, pkg.OVERLAP_ON, graph), ref), graph
+    rel, ok = sm.smooth(torch.zeros_like(b), b, 16, rel_tol=1e-3)
+    sm.set_overlap(pkg.OVERLAP_OFF)
+    rel0, ok0 = sm.smooth(torch.zeros_like(b), b, 16, rel_tol=1e-3)
+    assert rel == rel0 and ok == ok0

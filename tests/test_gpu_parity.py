@@ -343,15 +343,18 @@ def test_multi_sweep_graph_matches_eager(torch, pkg, variant):
 
 
 def test_autotuned_tile(torch, pkg):
-    # tile (0, 0): setup times every supported block shape and keeps one; the
-    # result equals an explicitly tiled run bit for bit (the per-point
-    # arithmetic does not depend on the shape), FP64 surrogates of degree >= 3
-    # never take the 16 x 32 shape (its kernels would spill registers)
+    # tile (0, 0): setup times every supported block shape with several grid
+    # sizes and both residual modes and keeps one; the result equals an
+    # explicitly tiled run bit for bit (the per-point arithmetic depends on
+    # none of these), FP64 surrogates of degree >= 3 never take the 16 x 32
+    # shape (its kernels would spill registers)
     t = W.make_tet(12, 6, *W.KAPPA_SIN, jitter=0.15)
     b = torch.tensor(t.rhs(), device="cuda")
     for v, kw in ((pkg.STORED_F64, {}), (pkg.SURR_F32, dict(degree=3, stride=4)), (pkg.SURR_F64, dict(degree=3, stride=4))):
         auto = pkg.Smoother([t], v, **kw)
         assert auto.tile in ((8, 8), (16, 16), (16, 32))
+        grid, gmax = auto.flow_grid
+        assert 1 <= grid <= gmax and auto.overlap() in (pkg.OVERLAP_OFF, pkg.OVERLAP_ON)
         if v == pkg.SURR_F64:
             assert auto.tile != (16, 32)
         fixed = pkg.Smoother([t], v, tile=(8, 8), **kw)
