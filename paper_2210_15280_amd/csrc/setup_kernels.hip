@@ -193,6 +193,27 @@ __global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev
 
 // ------------------------------------------------------------ least squares
 
+constexpr int QB = 8;  // Householder panel width of the chunk QR
+
+// Sums of NV per-thread values over the workgroup (256 threads): each
+// wavefront reduces by shuffles, then the four wavefront sums are added in a
+// fixed order.  lds: 4 * NV doubles.  Every thread gets the sums.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* lds) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[wv * NV + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
+    __syncthreads();
+}
+
 // Householder QR of one chunk of rows, one workgroup per chunk, FP64.
 // The chunk is copied into the workgroup's row-major scratch (rows x m,
 // zero-padded), reduced in place, and its m x m triangular factor R is
@@ -266,44 +287,140 @@ __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ te
         }
         __syncthreads();
         const int rows = chunk_rows;
-        for (int j = 0; j < m && j < rows; ++j) {
-            // sigma = sum_{i > j} A[i][j]^2
-            double part = 0.0;
-            for (int i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) {
-                const double a = A[(int64_t)i * m + j];
-                part += a * a;
-            }
-            sh[threadIdx.x] = part;
-            __syncthreads();
-            for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-                if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        // Blocked Householder: panels of QB columns.  Inside a panel each
+        // reflector H_j = I - tau_j v_j v_j^T (v_j(j) = 1, below it the scaled
+        // column, stored in place) is applied to the panel's remaining
+        // columns; the panel's product H_j0 ... H_j0+b-1 = I - Y T Y^T (T upper
+        // triangular) is then applied to the trailing columns at once,
+        // A_k <- A_k - Y (T^T (Y^T A_k)): two passes over the trailing
+        // matrix per panel instead of two per column.
+        double* taus = sh;                      // [QB] reflector scales of the panel
+        double* Tm = taus + QB;                 // [QB][QB] the panel's T
+        double* red = Tm + QB * QB;             // [4][QB*QB] block sums
+        const int NTH = 256;                    // rows are split over the threads: i = tid (mod 256)
+        const int tid = (int)threadIdx.x;
+        for (int j0 = 0; j0 < m && j0 < rows; j0 += QB) {
+            const int jb = min(QB, min(m, rows) - j0);
+            for (int q = 0; q < jb; ++q) {
+                const int j = j0 + q;
+                double sg[1] = {0.0};
+                for (int i = j + 1 + tid; i < rows; i += NTH) {
+                    const double a = A[(int64_t)i * m + j];
+                    sg[0] += a * a;
+                }
+                block_sums<1>(sg, red);
+                const double sigma = sg[0];
+                const double alpha = A[(int64_t)j * m + j];
+                if (sigma == 0.0) {  // column already reduced: H = I
+                    if (tid == 0) taus[q] = 0.0;
+                    __syncthreads();
+                    continue;
+                }
+                const double nrm = sqrt(alpha * alpha + sigma);
+                const double beta = alpha > 0.0 ? -nrm : nrm;
+                const double tau = (beta - alpha) / beta;
+                const double scl = 1.0 / (alpha - beta);
+                for (int i = j + 1 + tid; i < rows; i += NTH) A[(int64_t)i * m + j] *= scl;
+                __syncthreads();
+                // the panel's remaining columns: dots over the rows below j, then the update
+                const int nk = j0 + jb - 1 - j;
+                if (nk > 0) {
+                    double d[QB];
+#pragma unroll
+                    for (int c = 0; c < QB; ++c) d[c] = 0.0;
+                    for (int i = j + 1 + tid; i < rows; i += NTH) {
+                        const double vi = A[(int64_t)i * m + j];
+#pragma unroll
+                        for (int c = 0; c < QB; ++c)
+                            if (c < nk) d[c] += vi * A[(int64_t)i * m + j + 1 + c];
+                    }
+                    block_sums<QB>(d, red);
+                    double wk[QB];
+#pragma unroll
+                    for (int c = 0; c < QB; ++c) wk[c] = c < nk ? tau * (A[(int64_t)j * m + j + 1 + c] + d[c]) : 0.0;
+                    __syncthreads();
+                    if (tid == 0)
+#pragma unroll
+                        for (int c = 0; c < QB; ++c)
+                            if (c < nk) A[(int64_t)j * m + j + 1 + c] -= wk[c];
+                    for (int i = j + 1 + tid; i < rows; i += NTH) {
+                        const double vi = A[(int64_t)i * m + j];
+#pragma unroll
+                        for (int c = 0; c < QB; ++c)
+                            if (c < nk) A[(int64_t)i * m + j + 1 + c] -= wk[c] * vi;
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    taus[q] = tau;
+                    A[(int64_t)j * m + j] = beta;
+                }
                 __syncthreads();
             }
-            const double sigma = sh[0];
-            const double alpha = A[(int64_t)j * m + j];
-            __syncthreads();
-            if (sigma == 0.0) continue;  // column already reduced: H = I
-            const double nrm = sqrt(alpha * alpha + sigma);
-            const double beta = alpha > 0.0 ? -nrm : nrm;
-            const double tau = (beta - alpha) / beta;
-            const double scl = 1.0 / (alpha - beta);
-            for (int i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) A[(int64_t)i * m + j] *= scl;
-            __syncthreads();
-            // apply H = I - tau v v^T (v_j = 1) to the trailing columns, one thread per column
-            for (int k = j + 1 + threadIdx.x; k < m; k += blockDim.x) {
-                double dot0 = A[(int64_t)j * m + k], dot1 = 0.0;
-                int i = j + 1;
-                for (; i + 1 < rows; i += 2) {
-                    dot0 += A[(int64_t)i * m + j] * A[(int64_t)i * m + k];
-                    dot1 += A[(int64_t)(i + 1) * m + j] * A[(int64_t)(i + 1) * m + k];
+            if (j0 + jb >= m) break;  // no trailing columns
+            // T of the panel: T[q][q] = tau_q, T[0:q][q] = -tau_q T[0:q][0:q] g,
+            // g[r] = v_r^T v_q, from the Gram entries of the reflectors (v_p is 0
+            // above row j0+p, 1 at it, the stored column below it)
+            double g[QB * QB];
+#pragma unroll
+            for (int e = 0; e < QB * QB; ++e) g[e] = 0.0;
+            for (int i = j0 + tid; i < rows; i += NTH) {
+                double y[QB];
+#pragma unroll
+                for (int c = 0; c < QB; ++c)
+                    y[c] = c < jb ? (i > j0 + c ? A[(int64_t)i * m + j0 + c] : (i == j0 + c ? 1.0 : 0.0)) : 0.0;
+#pragma unroll
+                for (int pp = 0; pp < QB; ++pp)
+#pragma unroll
+                    for (int qq = pp + 1; qq < QB; ++qq) g[pp * QB + qq] += y[pp] * y[qq];
+            }
+            block_sums<QB * QB>(g, red);
+            if (tid == 0) {
+                for (int qq = 0; qq < jb; ++qq) {
+                    double z[QB];
+                    for (int pp = 0; pp < qq; ++pp) {
+                        double acc = 0.0;
+                        for (int r = pp; r < qq; ++r) acc += Tm[pp * QB + r] * g[r * QB + qq];
+                        z[pp] = acc;
+                    }
+                    for (int pp = 0; pp < qq; ++pp) Tm[pp * QB + qq] = -taus[qq] * z[pp];
+                    Tm[qq * QB + qq] = taus[qq];
                 }
-                if (i < rows) dot0 += A[(int64_t)i * m + j] * A[(int64_t)i * m + k];
-                const double wk = tau * (dot0 + dot1);
-                A[(int64_t)j * m + k] -= wk;
-                for (int ii = j + 1; ii < rows; ++ii) A[(int64_t)ii * m + k] -= wk * A[(int64_t)ii * m + j];
             }
             __syncthreads();
-            if (threadIdx.x == 0) A[(int64_t)j * m + j] = beta;
+            // trailing columns, one thread per column: w = Y^T A_k, u = T^T w,
+            // A_k -= Y u
+            for (int k = j0 + jb + tid; k < m; k += NTH) {
+                double w[QB];
+#pragma unroll
+                for (int c = 0; c < QB; ++c) w[c] = 0.0;
+                for (int i = j0; i < rows; ++i) {
+                    const double a = A[(int64_t)i * m + k];
+                    const double* yr = A + (int64_t)i * m + j0;
+#pragma unroll
+                    for (int c = 0; c < QB; ++c) {
+                        const double y = c < jb ? (i > j0 + c ? yr[c] : (i == j0 + c ? 1.0 : 0.0)) : 0.0;
+                        w[c] += y * a;
+                    }
+                }
+                double u[QB];
+#pragma unroll
+                for (int pp = 0; pp < QB; ++pp) {
+                    double acc = 0.0;
+                    for (int c = 0; c <= pp && c < jb; ++c) acc += Tm[c * QB + pp] * w[c];
+                    u[pp] = pp < jb ? acc : 0.0;
+                }
+                for (int i = j0; i < rows; ++i) {
+                    const double* yr = A + (int64_t)i * m + j0;
+                    double dd = 0.0;
+#pragma unroll
+                    for (int c = 0; c < QB; ++c) {
+                        const double y = c < jb ? (i > j0 + c ? yr[c] : (i == j0 + c ? 1.0 : 0.0)) : 0.0;
+                        dd += y * u[c];
+                    }
+                    A[(int64_t)i * m + k] -= dd;
+                }
+            }
             __syncthreads();
         }
         // write R (upper triangle, zeros below)
@@ -547,8 +664,9 @@ void launch_gather_a_samples(const Ctx& c, double* samples, hipStream_t st) {
 void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
                       const double* samples, const double* in, double* out, double* scratch, int grid, int nchunks,
                       hipStream_t st) {
-    k_qr_chunks<<<grid, 256, 256 * sizeof(double), st>>>(c.tets, jobs, njobs, level0, m, chunk_rows, samples, in, out,
-                                                         scratch, nchunks);
+    k_qr_chunks<<<grid, 256, (QB + QB * QB + 4 * QB * QB) * sizeof(double), st>>>(c.tets, jobs, njobs, level0, m,
+                                                                              chunk_rows, samples, in, out, scratch,
+                                                                              nchunks);
 }
 
 void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st) {
