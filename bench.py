@@ -110,14 +110,19 @@ def start_vector(torch, n):
     return torch.tensor(W.SplitMix64(CONTRACTION_SEED).uniform_array(n, -1.0, 1.0), device="cuda")
 
 
-def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0)):
+def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0), overlap=None, grid=None):
     """Times `steps` sweeps; also measures the smoother's contraction factor.
-    Returns (results, handle): the caller closes the handle."""
+    overlap / grid (None: the setup's choice) pin the residual mode and the
+    persistent grid.  Returns (results, handle): the caller closes the handle."""
     import numpy as np
     t0 = time.perf_counter()
     sm = make_smoother(pkg, wl, variant, tile)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    if grid is not None:
+        sm.set_flow_grid(grid)
+    if overlap is not None:
+        sm.set_overlap(overlap)
     b = torch.tensor(np.concatenate([t.rhs() for t in wl.tets]), device="cuda")
     x = torch.zeros_like(b)
     if warmup:
@@ -383,7 +388,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the level-8 refinement and the 256-tetrahedron batch of the default run")
-    ap.add_argument("--tile", default="auto", help="block shape BVxBW of the sweep schedule, e.g. 16x32")
+    ap.add_argument("--tile", default="auto",
+                    help="block shape BVxBW of the sweep schedule, e.g. 16x32 (one, or one per variant)")
+    ap.add_argument("--overlap", default="auto",
+                    help="residual beside the forward sweep: auto (the setup's choice), off or on (one, or per variant)")
+    ap.add_argument("--grid", default="auto",
+                    help="workgroups of the persistent sweeps: auto (the setup's choice) or a number (one, or per variant)")
     ap.add_argument("--copy-bytes", type=int, default=0, help="also run a streaming copy of this size")
     ap.add_argument("--to-tol", type=float, default=0.0,
                     help="instead of fixed sweeps: time each variant's refinement to this relative residual")
@@ -410,7 +420,17 @@ def main():
         dg = tuple(int(c) for c in a.degree.split(","))
         wl = dataclasses.replace(wl, degree=dg[0] if len(dg) == 1 else dg)
     variants = a.variants.split(",")
-    tile = (0, 0) if a.tile == "auto" else tuple(int(c) for c in a.tile.split("x"))
+    def per_variant(arg, parse):
+        items = arg.split(",")
+        if len(items) == 1:
+            items = items * len(variants)
+        if len(items) != len(variants):
+            sys.exit("bench.py: give one value or one per variant")
+        return [parse(c) for c in items]
+    tiles = per_variant(a.tile, lambda c: (0, 0) if c == "auto" else tuple(int(k) for k in c.split("x")))
+    overlaps = per_variant(a.overlap, lambda c: {"auto": None, "off": 0, "on": 1}[c])
+    grids = per_variant(a.grid, lambda c: None if c == "auto" else int(c))
+    tile = tiles[0]
     if a.to_tol > 0:
         return main_to_tol(a, torch, pkg, wl, variants, tile)
     if a.pcg_tol > 0 or a.pcg_abs_tol > 0:
@@ -419,7 +439,8 @@ def main():
         return main_lfa(a, pkg, wl)
     results, handles = {}, {}
     for v in variants:
-        results[v], handles[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tile)
+        i = variants.index(v)
+        results[v], handles[v] = run_variant(pkg, torch, wl, v, a.steps, a.warmup, tiles[i], overlaps[i], grids[i])
         print("# %s: %.3e DOF-updates/s, %.4f ms/step, relres %.3e, tile %s, grid %s, %s residual, kernels %s, "
               "contraction %.6f" % (
                   v, results[v]["value"], results[v]["ms_per_step"], results[v]["relres_after"],

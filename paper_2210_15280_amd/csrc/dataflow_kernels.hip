@@ -328,17 +328,21 @@ __global__ void __launch_bounds__(BV* BW + (D + 1) * WAVE)
                 int rspin = rspin0;  // polls of a stale residual entry before computing it here
                 // OVL: the residual kernel marks every (64-lane group, hyperplane band)
                 // it has finished; before loading the residuals of a new band the
-                // wave waits for its group's mark (a bounded wait: the per-point tags
-                // stay the guarantee), so it does not poll the entries point by point
+                // wave waits for its group's mark, so it does not poll the entries
+                // point by point.  The wait is short and bounded (the per-point tags
+                // stay the guarantee): if a mark does not come, the residual kernel
+                // is not running beside this one (kernels serialised, e.g. under a
+                // counter profiler), and the wave stops waiting for marks and
+                // computes missing residuals itself.
                 int band_ok = -1;
                 auto wait_band = [&](const int th) {
                     if constexpr (OVL) {
                         const int k = min(th, te) / RES_T;
                         if (k > band_ok) {
                             const uint64_t* fl = rflag + ((int64_t)b * (NT / WAVE) + l / WAVE) * nbands + k;
-                            for (int it = 0; it < (1 << 16) && (uint32_t)ld_dev(fl) != tag; ++it)
-                                __builtin_amdgcn_s_sleep(8);
-                            band_ok = k;
+                            int it = 0;
+                            for (; it < 512 && (uint32_t)ld_dev(fl) != tag; ++it) __builtin_amdgcn_s_sleep(8);
+                            band_ok = it < 512 ? k : (1 << 30);
                         }
                     }
                 };
