@@ -127,7 +127,13 @@ typedef struct ilu_handle_s *ilu_handle_t;
  * variants sample the factors on S_d and solve the FP64 least-squares
  * problems (Sec. 4.1, Alg. 1).  Synchronous on `hip_stream`, so breakdown
  * (ILU_EBREAKDOWN), rank (ILU_ERANK) and geometry (ILU_EGEOM) errors are
- * reported here.  On success *out owns all device memory of the smoother. */
+ * reported here.  On success *out owns all device memory of the smoother.
+ * The stored variants keep full factor arrays.  The surrogate variants factor
+ * on a ring of the last four hyperplanes (the stencil equations of a point
+ * reach back at most three hyperplanes) and take each point's samples (and,
+ * ILU_BOUNDARY_V1, its boundary record) as it is factored, so the
+ * factorisation adds O(h^-2) memory to the assembled stencil: no full factor
+ * array exists at any time (see ilu_setup_memory). */
 int ilu_setup_surrogate(const ilu_tet_desc *tets, int32_t ntets, const ilu_opts *opts, void *hip_stream,
                         ilu_handle_t *out);
 
@@ -270,6 +276,11 @@ int ilu_sample_stride(ilu_handle_t h, int32_t tet, int32_t *stride_out);
  * tolerance is tested after every 8 sweeps, so up to 7 sweeps may follow the
  * first one that met it). */
 int ilu_last_sweeps(ilu_handle_t h, int32_t *sweeps_out);
+
+/* Device memory (bytes) that the library held during the ilu_setup_surrogate
+ * call that made `h`: the peak over the call (the autotuner's timing handles
+ * included) and what `h` holds after it.  Host pointers, may be NULL. */
+int ilu_setup_memory(ilu_handle_t h, int64_t *peak_bytes, int64_t *resident_bytes);
 
 /* Block shape (rows in v, rows in w) of the sweep schedule the handle uses:
  * the one requested in ilu_opts.tile, or the automatic choice. */

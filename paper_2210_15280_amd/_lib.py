@@ -76,6 +76,7 @@ def lib():
         L.ilu_get_surrogate_values.argtypes = [P, I32, P, P, P]
         L.ilu_sample_stride.argtypes = [P, I32, ctypes.POINTER(I32)]
         L.ilu_tile.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.ilu_setup_memory.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.ilu_last_sweeps.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_last_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)]
         L.ilu_set_kernel_timing.argtypes = [P, I32]
@@ -297,6 +298,13 @@ class Smoother:
         bv, bw = ctypes.c_int32(), ctypes.c_int32()
         _check(self.L.ilu_tile(self.h, ctypes.byref(bv), ctypes.byref(bw)), "ilu_tile")
         return bv.value, bw.value
+
+    @property
+    def setup_memory(self):
+        """(peak, resident) device bytes the library held during setup / holds after it."""
+        pk, rs = ctypes.c_int64(), ctypes.c_int64()
+        _check(self.L.ilu_setup_memory(self.h, ctypes.byref(pk), ctypes.byref(rs)), "ilu_setup_memory")
+        return pk.value, rs.value
 
     def timing(self):
         """(sweep loop ms, forward ms, backward ms, residual ms) of the last smooth call."""

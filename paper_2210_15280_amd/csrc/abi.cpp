@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
@@ -26,33 +27,55 @@ using namespace ilu;
 
 namespace {
 
+// Device bytes the library holds during one setup call on this thread: the
+// current sum over its buffers and the largest it reached.  Buffers record
+// the setup (epoch) they were allocated in, so only those count on release.
+struct SetupMem {
+    uint64_t epoch = 0;
+    bool on = false;
+    int64_t cur = 0, peak = 0;
+};
+thread_local SetupMem g_setup_mem;
+
 // Owning device buffer (move-only: a copy would free the same pointer twice).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    uint64_t epoch = 0;  // setup that allocated it (0: none)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
-    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), epoch(o.epoch) {
+        o.p = nullptr;
+        o.bytes = 0;
+        o.epoch = 0;
+    }
     DevBuf& operator=(DevBuf&& o) noexcept {
         if (this != &o) {
             release();
             p = o.p;
             bytes = o.bytes;
+            epoch = o.epoch;
             o.p = nullptr;
             o.bytes = 0;
+            o.epoch = 0;
         }
         return *this;
     }
     void swap(DevBuf& o) noexcept {
         std::swap(p, o.p);
         std::swap(bytes, o.bytes);
+        std::swap(epoch, o.epoch);
     }
     ~DevBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            if (g_setup_mem.on && epoch == g_setup_mem.epoch) g_setup_mem.cur -= (int64_t)bytes;
+        }
         p = nullptr;
         bytes = 0;
+        epoch = 0;
     }
     hipError_t alloc(size_t n, hipStream_t st, bool zero = true) {
         release();
@@ -60,7 +83,13 @@ struct DevBuf {
         hipError_t e = hipMalloc(&p, bytes);
         if (e != hipSuccess) {
             p = nullptr;
+            bytes = 0;
             return e;
+        }
+        if (g_setup_mem.on) {
+            epoch = g_setup_mem.epoch;
+            g_setup_mem.cur += (int64_t)bytes;
+            g_setup_mem.peak = std::max(g_setup_mem.peak, g_setup_mem.cur);
         }
         if (zero) e = hipMemsetAsync(p, 0, bytes, st);
         return e;
@@ -97,6 +126,7 @@ struct ilu_handle_s {
     int64_t npartial = 0;      // partial sums of the residual kernel
     int64_t npartial_tag = 0;  // ... and of the tagged one (overlapped residual)
     int flow_grid = 0;
+    int64_t setup_peak = 0, setup_resident = 0;  // library device bytes: peak during setup, held after it
     int flow_grid_max = 0;               // resident workgroups of the dataflow sweeps (the default grid)
     hipEvent_t ev[8] = {};
     bool have_timing = false;
@@ -272,6 +302,13 @@ int build_layout(ilu_handle_t h) {
         if (kv < 0 || kw < 0 || kv >= nbv[ti] || kw >= nbw[ti]) return -1;
         return bmap[ti][(size_t)kv * nbw[ti] + kw];
     };
+    auto gl_of = [&](int ti, int v, int w) -> int32_t {
+        const int n = h->tets[ti].n;
+        if (v < 2 || v > n - 2 || w < 1 || w > v - 1) return -1;
+        const int b = block_at(ti, (v - 2) / bv, (w - 1) / bw);
+        const BlockDev& B = h->blocks[b];
+        return (int32_t)((int64_t)b * lpb + lane_at(v - B.V0, w - B.W0, bv));
+    };
     auto rp_of = [&](int ti, int v, int w) -> int64_t {
         const int n = h->tets[ti].n;
         if (v < 2 || v > n - 2 || w < 1 || w > v - 1) return 0;  // zero region
@@ -340,7 +377,14 @@ int build_layout(ilu_handle_t h) {
             L.v1f[2] = valid ? base_of(fbase, ti, v, w + 1) : -1;
             L.v1f[3] = valid ? base_of(fbase, ti, v + 1, w + 1) : -1;
             L.v1b = valid ? base_of(bbase, ti, v, w) : -1;
-            L.pad_ = 0;
+            L.gl[R_SELF] = valid ? (int32_t)(bi * lpb + l) : -1;
+            L.gl[R_VM] = gl_of(ti, v - 1, w);
+            L.gl[R_WM] = gl_of(ti, v, w - 1);
+            L.gl[R_VMWM] = gl_of(ti, v - 1, w - 1);
+            L.gl[R_VP] = gl_of(ti, v + 1, w);
+            L.gl[R_WP] = gl_of(ti, v, w + 1);
+            L.gl[R_VPWP] = gl_of(ti, v + 1, w + 1);
+            L.pad_[0] = L.pad_[1] = 0;
             L.gt[0] = 1 << 30;
             L.gt[1] = -1;
             if (valid && (v - w <= 2 || w == 1)) B.edge = 1;
@@ -423,6 +467,12 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coe
     std::vector<int64_t> in_at(np, 0);  // row offset of each problem in the current input
     DevBuf finalR, in, out, scratch, jobs_d;
     if (finalR.alloc((size_t)np * m * m * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    // level 0: pieces of chunk - m samples, streamed in runs of run_pieces so
+    // that there are about as many runs as workgroups (one R each)
+    const int grid_max = 256, piece = chunk - m;
+    int64_t pieces = 0;
+    for (int p = 0; p < np; ++p) pieces += (rows[p] + piece - 1) / piece;
+    const int run_pieces = (int)std::max<int64_t>(1, (pieces + grid_max - 1) / grid_max);
     bool level0 = true;
     for (int level = 0; level < 64; ++level) {
         std::vector<QrJob> jobs;
@@ -436,7 +486,8 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coe
             J.fit = p % NFIT;
             J.in_rows = rows[p];
             J.in_off = level0 ? h->tets[J.tet].samp_off[J.fit] : in_at[p];
-            J.nchunk = (int)((rows[p] + chunk - 1) / chunk);
+            J.nchunk = level0 ? (int)((rows[p] + (int64_t)piece * run_pieces - 1) / ((int64_t)piece * run_pieces))
+                              : (int)((rows[p] + chunk - 1) / chunk);
             J.chunk0 = chunks;
             J.out_off = outrows;
             chunks += J.nchunk;
@@ -446,12 +497,13 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coe
         }
         if (jobs.empty()) break;
         if (out.alloc((size_t)outrows * m * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
-        const int grid = std::min(chunks, 256);
+        const int grid = std::min(chunks, grid_max);
         if (scratch.bytes < (size_t)grid * chunk * m * sizeof(double))
             if (scratch.alloc((size_t)grid * chunk * m * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
         if (upload(jobs_d, jobs, st)) return ILU_ENOMEM;
-        launch_qr_chunks(c, jobs_d.as<QrJob>(), (int)jobs.size(), level0 ? 1 : 0, m, chunk, samples.as<double>(),
-                         in.as<double>(), out.as<double>(), scratch.as<double>(), grid, chunks, st);
+        launch_qr_chunks(c, jobs_d.as<QrJob>(), (int)jobs.size(), level0 ? 1 : 0, m, chunk, run_pieces,
+                         samples.as<double>(), in.as<double>(), out.as<double>(), scratch.as<double>(), grid, chunks,
+                         st);
         HIPCHK(hipGetLastError());
         for (size_t j = 0; j < jobs.size(); ++j) {
             const int p = jp[j];
@@ -576,17 +628,6 @@ void sweep_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st);
 void sweep_bwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* target = nullptr);
 int sweep_res_fwd(ilu_handle_t h, const Ctx& c, hipStream_t st, double* partial, hipEvent_t* mk);
 
-// Variant V1: the exact factors of set F, copied once from the full factor
-// arrays of the setup.
-int gather_v1f(ilu_handle_t h, hipStream_t st) {
-    const bool f32 = h->variant == ILU_SURR_F32;
-    const size_t es = f32 ? sizeof(float) : sizeof(double);
-    if (h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
-    launch_gather_v1f(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->v1f.p, f32, st);
-    HIPCHK(hipGetLastError());
-    return ILU_OK;
-}
-
 // Variant V1: the backward weights of set B from F and the surrogate tables
 // (after every change of the surrogate coefficients).  The buffer is
 // allocated once; its last entries stay 0.
@@ -643,9 +684,10 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
     }
     launch_assemble(h->ctx(), h->A8.as<double>(), nullptr, st);
     HIPCHK(hipGetLastError());
-    // factorisation on the hyperplane schedule
     int32_t fl[4];
-    if (refit || v1) {
+    if (!surr) {
+        // stored variants: factorisation on the hyperplane schedule into full
+        // factor planes, transposed into the backward weights
         if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         const Ctx c = h->ctx();
@@ -657,43 +699,45 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         HIPCHK(hipGetLastError());
         if (int e = read_flags(h, st, fl)) return e;
         if (fl[0]) return ILU_EBREAKDOWN;
-    }
-    if (!refit) {
-        h->coef_h = *coef_in;
-        if (v1) {
-            if (int e = gather_v1f(h, st)) return e;
-            h->Lf.release();
-            h->Df.release();
+        if (h->Lb.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+        launch_transpose(c, h->Lf.as<double>(), h->Df.as<double>(), h->Lb.as<double>(), st);
+        HIPCHK(hipGetLastError());
+    } else {
+        // surrogate variants: Alg. 1 on a ring of four hyperplanes; each point
+        // leaves its samples and (V1) its boundary record as it is factored
+        const bool f32 = h->variant == ILU_SURR_F32;
+        const size_t es = f32 ? sizeof(float) : sizeof(double);
+        DevBuf samples;
+        if (refit && samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+        if (v1 && h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
+        if (refit || v1) {
+            const int64_t nring = (int64_t)h->blocks.size() * h->bv * h->bw + 1;
+            DevBuf ring;
+            if (ring.alloc((size_t)8 * 4 * nring * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+            const Ctx c = h->ctx();
+            for (int t = h->tmin; t <= h->tmax; ++t)
+                launch_factor_ring(c, t, ring.as<double>(), nring, refit ? samples.as<double>() : nullptr,
+                                   v1 ? h->v1f.p : nullptr, f32, h->flags.as<int>(), st);
+            HIPCHK(hipGetLastError());
+            if (int e = read_flags(h, st, fl)) return e;
+            if (fl[0]) return ILU_EBREAKDOWN;
         }
-        if (h->coef_d.alloc(h->coef_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
-        HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double),
-                              hipMemcpyHostToDevice, st));
+        if (refit) {
+            if (int e = solve_lsq(h, samples, st, h->coef_d)) return e;
+            if (int e = read_flags(h, st, fl)) return e;
+            if (fl[1]) return ILU_ERANK;
+            h->coef_h.resize((size_t)ntets * NFIT * h->K);
+            HIPCHK(hipMemcpyAsync(h->coef_h.data(), h->coef_d.p, h->coef_h.size() * sizeof(double),
+                                  hipMemcpyDeviceToHost, st));
+        } else {
+            h->coef_h = *coef_in;
+            if (h->coef_d.alloc(h->coef_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
+            HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, st));
+        }
         if (int e = build_tables(h, st)) return e;
         if (v1)
             if (int e = build_v1b(h, st)) return e;
-    } else if (!surr) {
-        if (h->Lb.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-        launch_transpose(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), h->Lb.as<double>(), st);
-        HIPCHK(hipGetLastError());
-    } else {
-        DevBuf samples;
-        if (samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-        launch_gather_samples(h->ctx(), h->Lf.as<double>(), h->Df.as<double>(), samples.as<double>(), st);
-        HIPCHK(hipGetLastError());
-        if (int e = solve_lsq(h, samples, st, h->coef_d)) return e;
-        if (int e = read_flags(h, st, fl)) return e;
-        if (fl[1]) return ILU_ERANK;
-        h->coef_h.resize((size_t)ntets * NFIT * h->K);
-        HIPCHK(hipMemcpyAsync(h->coef_h.data(), h->coef_d.p, h->coef_h.size() * sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        if (int e = build_tables(h, st)) return e;
-        // the exact factors are only needed during setup for the surrogate variants
-        if (v1) {
-            if (int e = gather_v1f(h, st)) return e;
-            if (int e = build_v1b(h, st)) return e;
-        }
-        h->Lf.release();
-        h->Df.release();
     }
     // surrogate operator: the centre and lower stencil weights sampled on the
     // same sets and fitted like the factors (or injected by the autotuner)
@@ -878,6 +922,34 @@ int64_t check_layout(ilu_handle_t h) {
         }
     }
     for (int64_t i = 0; i < h->nlex; ++i) bad += seen_lex[i] < 0;
+    // global lanes of the neighbour rows (the setup's hyperplane ring): the
+    // lane they name holds the row the row pointer names, or both are outside
+    {
+        static const int dv[7] = {0, -1, 0, -1, 1, 0, 1}, dw[7] = {0, 0, -1, -1, 0, 1, 1};
+        for (size_t b = 0; b < h->blocks.size(); ++b)
+            for (int l = 0; l < LANES; ++l) {
+                const LaneDev& L = h->lanes[b * LANES + l];
+                if (L.v == 0) {
+                    bad += L.gl[R_SELF] != -1;
+                    continue;
+                }
+                for (int sl = 0; sl < 7; ++sl) {
+                    const int32_t g = L.gl[sl];
+                    if (g < 0) {
+                        bad += L.rp[sl] != 0;
+                        continue;
+                    }
+                    if ((size_t)g >= h->lanes.size()) {
+                        ++bad;
+                        continue;
+                    }
+                    const LaneDev& M = h->lanes[g];
+                    if (M.v != L.v + dv[sl] || M.w != L.w + dw[sl] || M.rp[R_SELF] != L.rp[sl] ||
+                        h->blocks[g / LANES].tet != h->blocks[b].tet)
+                        ++bad;
+                }
+            }
+    }
     static const int dx[7] = {-1, 0, 1, -1, 0, 0, 1}, dy[7] = {0, -1, -1, 1, 1, 0, 0}, dz[7] = {0, 0, 0, -1, -1, -1, -1};
     static const int lrow[7] = {R_SELF, R_VM, R_VM, R_WM, R_WM, R_VMWM, R_VMWM};
     static const int urow[7] = {R_SELF, R_VP, R_VP, R_WP, R_WP, R_VPWP, R_VPWP};
@@ -1301,22 +1373,44 @@ const char* ilu_strerror(int code) {
     }
 }
 
+namespace {
+int setup_any(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t* out) {
+    if (opts->tile[0] == 0 && opts->tile[1] == 0 && opts->schedule != ILU_SCHED_PLANE)
+        return setup_autotuned(tets, ntets, opts, st, out);
+    ilu_handle_t h = new (std::nothrow) ilu_handle_s();
+    if (!h) return ILU_ENOMEM;
+    const int rc = setup_impl(tets, ntets, opts, st, h);
+    if (rc != ILU_OK) {
+        (void)hipStreamSynchronize(st);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return ILU_OK;
+}
+}  // namespace
+
 int ilu_setup_surrogate(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, void* hip_stream,
                         ilu_handle_t* out) {
     if (!tets || !opts || !out || ntets <= 0) return ILU_EINVAL;
     *out = nullptr;
     if (int e = validate_args(tets, ntets, opts)) return e;
-    if (opts->tile[0] == 0 && opts->tile[1] == 0 && opts->schedule != ILU_SCHED_PLANE)
-        return setup_autotuned(tets, ntets, opts, (hipStream_t)hip_stream, out);
-    ilu_handle_t h = new (std::nothrow) ilu_handle_s();
-    if (!h) return ILU_ENOMEM;
-    const int rc = setup_impl(tets, ntets, opts, (hipStream_t)hip_stream, h);
-    if (rc != ILU_OK) {
-        (void)hipStreamSynchronize((hipStream_t)hip_stream);
-        delete h;
-        return rc;
+    static std::atomic<uint64_t> epochs{0};
+    SetupMem& m = g_setup_mem;
+    m = SetupMem{++epochs, true, 0, 0};
+    const int rc = setup_any(tets, ntets, opts, (hipStream_t)hip_stream, out);
+    m.on = false;
+    if (rc == ILU_OK) {
+        (*out)->setup_peak = m.peak;
+        (*out)->setup_resident = m.cur;
     }
-    *out = h;
+    return rc;
+}
+
+int ilu_setup_memory(ilu_handle_t h, int64_t* peak_bytes, int64_t* resident_bytes) {
+    if (!h) return ILU_EINVAL;
+    if (peak_bytes) *peak_bytes = h->setup_peak;
+    if (resident_bytes) *resident_bytes = h->setup_resident;
     return ILU_OK;
 }
 

@@ -88,7 +88,10 @@ struct LaneDev {
     int32_t v1b;         // variant V1: first set-B index of the own row (-1: row outside)
     int32_t gt[2];       // hyperplanes [gt[0], gt[1]] with an active point in this lane's 64-lane
                          // group (empty if gt[0] > gt[1]): the point-parallel kernels skip the rest
-    int32_t pad_;
+    int32_t gl[7];       // global lane (block * lanes per block + lane) of the own row and the six
+                         // neighbour rows, RowSlot order; -1 if the row is outside (the setup's
+                         // hyperplane ring is indexed by it)
+    int32_t pad_[2];
 };
 
 // Point sets of variant V1 (Sec. 4.1), per row (y, z) with xmax = n-1-y-z:

@@ -16,17 +16,23 @@ struct QrJob {
 
 void launch_assemble(const Ctx& c, double* A8, double* Afull, hipStream_t st);
 void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags, hipStream_t st);
+// Alg. 1 for hyperplane t into a ring of four hyperplanes (ring: [8][4][nring]
+// FP64, nring = lanes + 1, zeroed once), with the samples (may be null) and,
+// variant V1, the boundary records F (FP32 if f32, may be null) of the points
+// factored
+void launch_factor_ring(const Ctx& c, int t, double* ring, int64_t nring, double* samples, void* F, bool f32,
+                        int* flags, hipStream_t st);
 void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st);
-void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st);
 // samples of the assembled stencil (centre and lower weights) on the same sample sets
 void launch_gather_a_samples(const Ctx& c, double* samples, hipStream_t st);
+// TSQR level: level 0 factors runs of run_pieces pieces of chunk_rows - m
+// sample rows each (one R per run), later levels chunks of chunk_rows stacked
+// R rows; QrJob.nchunk counts runs at level 0
 void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
-                      const double* samples, const double* in, double* out, double* scratch, int grid, int nchunks,
-                      hipStream_t st);
+                      int run_pieces, const double* samples, const double* in, double* out, double* scratch, int grid,
+                      int nchunks, hipStream_t st);
 void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st);
 void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, double* tab, float* tab32, hipStream_t st);
-// variant V1: exact factors of set F (8-value records, FP32 if f32)
-void launch_gather_v1f(const Ctx& c, const double* Lf, const double* Df, void* F, bool f32, hipStream_t st);
 // variant V1: backward weights of set B from F and the FP64 row tables
 void launch_build_v1b(const Ctx& c, const double* tab, const void* F, void* Bw, bool f32, hipStream_t st);
 // mode 0: stream -> lexicographic, mode 1: lexicographic -> stream

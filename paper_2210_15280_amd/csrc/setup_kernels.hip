@@ -74,6 +74,36 @@ __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __re
 // Neighbours that are not interior contribute L = 0, D = 1 (the guard values
 // of Alg. 1).  Factors are written to Lf[7][S] (lower weights) and Df[S].
 // The first point with D <= 0 is reported through flags[0].
+// The stencil equations of one point (Alg. 1): lower weights a[s] = A^p_{d_s}
+// and centre Ac of the point, pivots Dn[s] of the lower neighbours (1 where
+// the neighbour is not interior) and their factors Lq(s, d) = L^{p+d_s}_d (0
+// where not interior).  Equations in the order bc, s, bnw, be, w, bn, se, c.
+template <class LQ>
+__device__ __forceinline__ void stencil_equations(const double (&a)[NLOW], double Ac, const double (&Dn)[NLOW], LQ Lq,
+                                                  double (&Lp)[NLOW], double& Dp) {
+    enum { W_ = 0, S_ = 1, SE = 2, BNW = 3, BN = 4, BC = 5, BE = 6 };
+    const double Lbc = a[BC] / Dn[BC];
+    const double Ls = (a[S_] - Lbc * Dn[BC] * Lq(S_, BN)) / Dn[S_];
+    const double Lbnw = (a[BNW] - Lbc * Dn[BC] * Lq(BNW, SE)) / Dn[BNW];
+    const double Lbe = (a[BE] - Lbc * Dn[BC] * Lq(BE, W_)) / Dn[BE];
+    const double Lw = (a[W_] - Lbc * Dn[BC] * Lq(W_, BE) - Lbnw * Dn[BNW] * Lq(W_, BN) - Ls * Dn[S_] * Lq(W_, SE)) /
+                      Dn[W_];
+    const double Lbn = (a[BN] - Lbc * Dn[BC] * Lq(BN, S_) - Lbe * Dn[BE] * Lq(BN, SE) - Lbnw * Dn[BNW] * Lq(BN, W_)) /
+                       Dn[BN];
+    const double Lse = (a[SE] - Lbc * Dn[BC] * Lq(SE, BNW) - Lbe * Dn[BE] * Lq(SE, BN) - Ls * Dn[S_] * Lq(SE, W_)) /
+                       Dn[SE];
+    Dp = Ac - Lbc * Lbc * Dn[BC] - Lbe * Lbe * Dn[BE] - Lbnw * Lbnw * Dn[BNW] - Lbn * Lbn * Dn[BN] -
+         Lse * Lse * Dn[SE] - Ls * Ls * Dn[S_] - Lw * Lw * Dn[W_];
+    Lp[W_] = Lw;
+    Lp[S_] = Ls;
+    Lp[SE] = Lse;
+    Lp[BNW] = Lbnw;
+    Lp[BN] = Lbn;
+    Lp[BC] = Lbc;
+    Lp[BE] = Lbe;
+}
+
+// Alg. 1 on the hyperplane schedule into full factor planes (stored variant).
 __global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                                const LaneDev* __restrict__ lanes, int lpb, int groups, int t_glob, int64_t S, const double* __restrict__ A8,
                                double* __restrict__ Lf, double* __restrict__ Df, int* __restrict__ flags) {
@@ -88,39 +118,100 @@ __global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* 
     const int x = t - 2 * v - w;
     if (x < 1 || x > n - 1 - v) return;
     const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
-
-    // neighbour positions, interior flags, pivots
     int64_t q[NLOW];
     bool in[NLOW];
-    double Dn[NLOW];
+    double Dn[NLOW], a[NLOW];
 #pragma unroll
     for (int s = 0; s < NLOW; ++s) {
         q[s] = Ln.rp[low_row(s)] + (int64_t)lpb * (t + low_dt(s));
         in[s] = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
         Dn[s] = in[s] ? Df[q[s]] : 1.0;
+        a[s] = A8[(int64_t)(1 + s) * S + idx];
     }
     auto Lq = [&](int s, int d) -> double { return in[s] ? Lf[(int64_t)d * S + q[s]] : 0.0; };
-    enum { W_ = 0, S_ = 1, SE = 2, BNW = 3, BN = 4, BC = 5, BE = 6 };
-    double a[NLOW];
-#pragma unroll
-    for (int s = 0; s < NLOW; ++s) a[s] = A8[(int64_t)(1 + s) * S + idx];
-    const double Lbc = a[BC] / Dn[BC];
-    const double Ls = (a[S_] - Lbc * Dn[BC] * Lq(S_, BN)) / Dn[S_];
-    const double Lbnw = (a[BNW] - Lbc * Dn[BC] * Lq(BNW, SE)) / Dn[BNW];
-    const double Lbe = (a[BE] - Lbc * Dn[BC] * Lq(BE, W_)) / Dn[BE];
-    const double Lw = (a[W_] - Lbc * Dn[BC] * Lq(W_, BE) - Lbnw * Dn[BNW] * Lq(W_, BN) - Ls * Dn[S_] * Lq(W_, SE)) /
-                      Dn[W_];
-    const double Lbn = (a[BN] - Lbc * Dn[BC] * Lq(BN, S_) - Lbe * Dn[BE] * Lq(BN, SE) - Lbnw * Dn[BNW] * Lq(BN, W_)) /
-                       Dn[BN];
-    const double Lse = (a[SE] - Lbc * Dn[BC] * Lq(SE, BNW) - Lbe * Dn[BE] * Lq(SE, BN) - Ls * Dn[S_] * Lq(SE, W_)) /
-                       Dn[SE];
-    const double Dp = A8[idx] - Lbc * Lbc * Dn[BC] - Lbe * Lbe * Dn[BE] - Lbnw * Lbnw * Dn[BNW] -
-                      Lbn * Lbn * Dn[BN] - Lse * Lse * Dn[SE] - Ls * Ls * Dn[S_] - Lw * Lw * Dn[W_];
-    const double Lp[NLOW] = {Lw, Ls, Lse, Lbnw, Lbn, Lbc, Lbe};
+    double Lp[NLOW], Dp;
+    stencil_equations(a, A8[idx], Dn, Lq, Lp, Dp);
 #pragma unroll
     for (int s = 0; s < NLOW; ++s) Lf[(int64_t)s * S + idx] = in[s] ? Lp[s] : 0.0;
     Df[idx] = Dp;
     if (!(Dp > 0.0)) atomicOr(&flags[0], 1);
+}
+
+// Samples of one factored point (Sec. 4.1, reading of the garbled formula):
+// for every fitted direction whose sample set S_d holds p (p = shift_d mod
+// stride componentwise, shift_d = 1 - min(d, 0), and p + d interior), the
+// value L^p_d (lower directions) or 1/D^p (centre) at its lexicographic
+// position k = (p - shift)/stride in the lattice simplex of S_d.
+__device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz);
+__device__ __forceinline__ void put_samples(const TetDev& T, int x, int y, int z, const double (&Lp)[NLOW], double Dp,
+                                            double* __restrict__ samples) {
+    const int n = T.n, st = T.stride;
+    for (int f = 0; f < NFIT; ++f) {
+        const int dx = f < NLOW ? low_dx(f) : 0, dy = f < NLOW ? low_dy(f) : 0, dz = f < NLOW ? low_dz(f) : 0;
+        const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
+        if ((x - sx) % st || (y - sy) % st || (z - sz) % st) continue;
+        if (!interior(n, x + dx, y + dy, z + dz)) continue;
+        const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
+        samples[T.samp_off[f] + simplex_index(T.samp_M[f], kx, ky, kz)] = f < NLOW ? Lp[f] : 1.0 / Dp;
+    }
+}
+
+// Alg. 1 in O(h^-2) memory (surrogate variants): the factors of hyperplane t
+// go to slot t mod 4 of a ring of four hyperplanes, ring[(k * 4 + slot) *
+// nring + global lane], k = 0..6 the lower factors and 7 the pivot, nring =
+// lanes + 1 (the last lane is zero and stands for rows outside the lattice);
+// the stencil equations at t read t-1 .. t-3 only.  Each factored point
+// leaves its samples (and, variant V1, its boundary record [L_0..L_6, 1/D])
+// right away, so no full factor array is ever held.
+template <typename FT>
+__global__ void k_factor_ring(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                              const LaneDev* __restrict__ lanes, int lpb, int groups, int t_glob, int64_t S,
+                              const double* __restrict__ A8, double* __restrict__ ring, int64_t nring,
+                              double* __restrict__ samples, FT* __restrict__ F, int* __restrict__ flags) {
+    int b, lane;
+    decode_group(groups, b, lane);
+    const BlockDev& B = blocks[b];
+    const int t = t_glob;
+    if (t < B.tb || t > B.te) return;
+    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
+    if (Ln.v == 0) return;
+    const TetDev& T = tets[B.tet];
+    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w, xmax = n - 1 - v;
+    const int x = t - 2 * v - w;
+    if (x < 1 || x > xmax) return;
+    const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
+    int64_t q[NLOW];
+    bool in[NLOW];
+    double Dn[NLOW], a[NLOW];
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) {
+        const int32_t g = Ln.gl[low_row(s)];
+        const int slot = (t + low_dt(s)) & 3;
+        q[s] = (int64_t)slot * nring + (g >= 0 ? g : nring - 1);
+        in[s] = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
+        Dn[s] = in[s] ? ring[(int64_t)7 * 4 * nring + q[s]] : 1.0;
+        a[s] = A8[(int64_t)(1 + s) * S + idx];
+    }
+    auto Lq = [&](int s, int d) -> double { return in[s] ? ring[(int64_t)d * 4 * nring + q[s]] : 0.0; };
+    double Lp[NLOW], Dp;
+    stencil_equations(a, A8[idx], Dn, Lq, Lp, Dp);
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) Lp[s] = in[s] ? Lp[s] : 0.0;
+    const int64_t me = (int64_t)(t & 3) * nring + Ln.gl[R_SELF];
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) ring[(int64_t)s * 4 * nring + me] = Lp[s];
+    ring[(int64_t)7 * 4 * nring + me] = Dp;
+    if (!(Dp > 0.0)) atomicOr(&flags[0], 1);
+    if (samples) put_samples(T, x, y, z, Lp, Dp, samples);
+    if (F) {
+        const int k = v1f_pos(x, xmax, y, z);
+        if (k >= 0) {
+            const int64_t j = (int64_t)Ln.v1f[0] + k;
+#pragma unroll
+            for (int s = 0; s < NLOW; ++s) F[j * 8 + s] = (FT)Lp[s];
+            F[j * 8 + NLOW] = (FT)(1.0 / Dp);
+        }
+    }
 }
 
 // Backward-sweep weights per point: Lb[0] = 1/D^p, Lb[1+s] = L^{p-d_s}_{d_s}
@@ -162,10 +253,11 @@ __device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz) 
     return choose3(M + 3) - choose3(M + 3 - kz) + (int64_t)ky * (Mz + 1) - (int64_t)ky * (ky - 1) / 2 + kx;
 }
 
-__global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                 const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S, const double* __restrict__ Lf,
-                                 const double* __restrict__ Df, const double* __restrict__ A8,
-                                 double* __restrict__ samples) {
+// Samples of the assembled stencil (centre and lower weights) on the sample
+// sets of the factors (the factors' own samples leave k_factor_ring).
+__global__ void k_gather_a_samples(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                                   const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S,
+                                   const double* __restrict__ A8, double* __restrict__ samples) {
     int b, lane;
     decode_group(groups, b, lane);
     const BlockDev B = blocks[b];
@@ -184,9 +276,7 @@ __global__ void k_gather_samples(const TetDev* __restrict__ tets, const BlockDev
             if (!interior(n, x + dx, y + dy, z + dz)) continue;
             const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
             const int64_t si = simplex_index(T.samp_M[f], kx, ky, kz);
-            // ILU fit: L^p_d and 1/D^p; operator fit (A8 given): A^p_d and A^p_c
-            samples[T.samp_off[f] + si] = A8 ? (f < NLOW ? A8[(int64_t)(1 + f) * S + idx] : A8[idx])
-                                             : (f < NLOW ? Lf[(int64_t)f * S + idx] : 1.0 / Df[idx]);
+            samples[T.samp_off[f] + si] = f < NLOW ? A8[(int64_t)(1 + f) * S + idx] : A8[idx];
         }
     }
 }
@@ -214,17 +304,18 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* lds) {
     __syncthreads();
 }
 
-// Householder QR of one chunk of rows, one workgroup per chunk, FP64.
-// The chunk is copied into the workgroup's row-major scratch (rows x m,
-// zero-padded), reduced in place, and its m x m triangular factor R is
-// written as m rows of the output.  Level 0 builds its rows from the samples
-// ([basis values | sample value]); later levels read stacked R factors.
-// Stacking the R factors of the chunks and factoring again yields the R of
-// the whole least-squares matrix (TSQR).
-
-
+// Householder QR of chunks of rows, one workgroup per chunk, FP64.  A chunk
+// is copied into the workgroup's row-major scratch (rows x m, zero-padded),
+// reduced in place, and its m x m triangular factor R is written as m rows of
+// the output.  Stacking the R factors of the chunks and factoring again yields
+// the R of the whole least-squares matrix (TSQR).
+// Level 0 streams: chunk c of a problem is a run of `run_pieces` pieces of
+// chunk_rows - m sample rows ([basis values | sample value]); each piece is
+// stacked under the R of the run so far (the first under zeros) and the stack
+// is factored again, so a run leaves one R however many samples it covers.
+// Later levels read stacked R factors, chunk_rows of them per chunk.
 __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ tets, const QrJob* __restrict__ jobs,
-                                                   int njobs, int level0, int m, int chunk_rows,
+                                                   int njobs, int level0, int m, int chunk_rows, int run_pieces,
                                                    const double* __restrict__ samples, const double* __restrict__ in,
                                                    double* __restrict__ out, double* __restrict__ scratch_all,
                                                    int nchunks_total) {
@@ -239,8 +330,11 @@ __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ te
         const QrJob J = jobs[lo];
         const int c = cid - J.chunk0;
         double* A = scratch_all + (int64_t)blockIdx.x * chunk_rows * m;
-        const int64_t r0 = (int64_t)c * chunk_rows;
-        const int nr = (int)min<int64_t>(chunk_rows, J.in_rows - r0);
+        const int pr = level0 ? chunk_rows - m : chunk_rows;  // new rows per piece
+        const int64_t rbeg = level0 ? (int64_t)c * run_pieces * pr : (int64_t)c * chunk_rows;
+        const int64_t rend = level0 ? min<int64_t>(J.in_rows, rbeg + (int64_t)run_pieces * pr)
+                                    : min<int64_t>(J.in_rows, rbeg + chunk_rows);
+        for (int64_t p0 = rbeg; p0 < rend; p0 += pr) {
         // fill
         if (level0) {
             const TetDev& T = tets[J.tet];
@@ -251,14 +345,21 @@ __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ te
                       dz = J.fit < NLOW ? low_dz(J.fit) : 0;
             const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
             const double invn = 1.0 / T.n;
-            for (int r = threadIdx.x; r < chunk_rows; r += blockDim.x) {
+            // the R of the run so far (zeros before the first piece): clear
+            // the reflectors left below its diagonal
+            for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
+                const int r = (int)(e / m), k = (int)(e % m);
+                if (p0 == rbeg || k < r) A[e] = 0.0;
+            }
+            for (int r = m + threadIdx.x; r < chunk_rows; r += blockDim.x) {
                 double* row = A + (int64_t)r * m;
-                if (r >= nr) {
+                int64_t si = p0 + (r - m);
+                if (si >= rend) {
                     for (int k = 0; k < m; ++k) row[k] = 0.0;
                     continue;
                 }
+                const double val = samples[J.in_off + si];
                 // decode the lexicographic simplex index back to k
-                int64_t si = r0 + r;
                 int kz = 0;
                 while (choose3(M + 3) - choose3(M + 3 - (kz + 1)) <= si) ++kz;
                 si -= choose3(M + 3) - choose3(M + 3 - kz);
@@ -277,12 +378,13 @@ __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ te
                 for (int kk = 0; kk <= dgz; ++kk)
                     for (int j = 0; j <= dgy; ++j)
                         for (int i = 0; i <= dgx; ++i) row[col++] = px[i] * py[j] * pz[kk];
-                row[K] = samples[J.in_off + r0 + r];
+                row[K] = val;
             }
         } else {
+            const int nr = (int)(rend - rbeg);
             for (int64_t e = threadIdx.x; e < (int64_t)chunk_rows * m; e += blockDim.x) {
                 const int r = (int)(e / m), k = (int)(e % m);
-                A[e] = r < nr ? in[(J.in_off + r0 + r) * m + k] : 0.0;
+                A[e] = r < nr ? in[(J.in_off + rbeg + r) * m + k] : 0.0;
             }
         }
         __syncthreads();
@@ -423,10 +525,11 @@ __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ te
             }
             __syncthreads();
         }
+        }  // pieces
         // write R (upper triangle, zeros below)
         for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
             const int r = (int)(e / m), k = (int)(e % m);
-            out[(J.out_off + (int64_t)c * m + r) * m + k] = (k >= r && r < rows) ? A[(int64_t)r * m + k] : 0.0;
+            out[(J.out_off + (int64_t)c * m + r) * m + k] = (k >= r && r < chunk_rows) ? A[(int64_t)r * m + k] : 0.0;
         }
         __syncthreads();
     }
@@ -539,31 +642,6 @@ __global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __
 
 // ------------------------------------------------------- boundary variant V1
 
-// Exact factors of the points of set F (the boundary points, Sec. 4.1):
-// record j = [L^p_d for d in D_l, 1/D^p] of the point with compact index j.
-template <typename T>
-__global__ void k_gather_v1f(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                             const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S,
-                             const double* __restrict__ Lf, const double* __restrict__ Df, T* __restrict__ F) {
-    int b, lane;
-    decode_group(groups, b, lane);
-    const BlockDev B = blocks[b];
-    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
-    if (Ln.v == 0) return;
-    const int n = tets[B.tet].n, v = Ln.v, w = Ln.w, y = v - w, z = w, xmax = n - 1 - v;
-    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
-        const int x = t - 2 * v - w;
-        if (x < 1 || x > xmax) continue;
-        const int k = v1f_pos(x, xmax, y, z);
-        if (k < 0) continue;
-        const int64_t j = (int64_t)Ln.v1f[0] + k;
-        const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
-#pragma unroll
-        for (int s = 0; s < NLOW; ++s) F[j * 8 + s] = (T)Lf[(int64_t)s * S + idx];
-        F[j * 8 + NLOW] = (T)(1.0 / Df[idx]);
-    }
-}
-
 __device__ __forceinline__ double horner_d(const double* c, int NC, double eta) {
     double acc = c[NC - 1];
     for (int i = NC - 2; i >= 0; --i) acc = acc * eta + c[i];
@@ -647,26 +725,30 @@ void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags
     k_factor_plane<<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.A8, Lf, Df, flags);
 }
 
+void launch_factor_ring(const Ctx& c, int t, double* ring, int64_t nring, double* samples, void* F, bool f32,
+                        int* flags, hipStream_t st) {
+    if (f32)
+        k_factor_ring<float><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S,
+                                                                  c.A8, ring, nring, samples, (float*)F, flags);
+    else
+        k_factor_ring<double><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S,
+                                                                   c.A8, ring, nring, samples, (double*)F, flags);
+}
+
 void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st) {
     k_transpose_factors<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df, Lb);
 }
 
-void launch_gather_samples(const Ctx& c, const double* Lf, const double* Df, double* samples, hipStream_t st) {
-    k_gather_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df,
-                                                           nullptr, samples);
-}
-
 void launch_gather_a_samples(const Ctx& c, double* samples, hipStream_t st) {
-    k_gather_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, nullptr,
-                                                           nullptr, c.A8, samples);
+    k_gather_a_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8,
+                                                             samples);
 }
 
 void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
-                      const double* samples, const double* in, double* out, double* scratch, int grid, int nchunks,
-                      hipStream_t st) {
-    k_qr_chunks<<<grid, 256, (QB + QB * QB + 4 * QB * QB) * sizeof(double), st>>>(c.tets, jobs, njobs, level0, m,
-                                                                              chunk_rows, samples, in, out, scratch,
-                                                                              nchunks);
+                      int run_pieces, const double* samples, const double* in, double* out, double* scratch, int grid,
+                      int nchunks, hipStream_t st) {
+    k_qr_chunks<<<grid, 256, (QB + QB * QB + 4 * QB * QB) * sizeof(double), st>>>(
+        c.tets, jobs, njobs, level0, m, chunk_rows, run_pieces, samples, in, out, scratch, nchunks);
 }
 
 void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st) {
@@ -675,15 +757,6 @@ void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, doubl
 
 void launch_row_tables(const Ctx& c, int nslots, const double* coef, int NC, double* tab, float* tab32, hipStream_t st) {
     k_row_tables<<<(nslots + 127) / 128, 128, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, nslots, coef, NC, tab, tab32);
-}
-
-void launch_gather_v1f(const Ctx& c, const double* Lf, const double* Df, void* F, bool f32, hipStream_t st) {
-    if (f32)
-        k_gather_v1f<float><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf,
-                                                                  Df, (float*)F);
-    else
-        k_gather_v1f<double><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf,
-                                                                   Df, (double*)F);
 }
 
 void launch_build_v1b(const Ctx& c, const double* tab, const void* F, void* Bw, bool f32, hipStream_t st) {
