@@ -453,72 +453,56 @@ int read_flags(ilu_handle_t h, hipStream_t st, int32_t out[4]) {
     return ILU_OK;
 }
 
-// Least squares for every (tet, fitted direction): TSQR with Householder
-// chunks, then back substitution (all on the device).
+// Least squares for every (tet, fitted direction): TSQR on the device, then
+// back substitution.  Level 0 splits the samples of each problem into runs of
+// equal length, about QR_RUNS of them over all problems, each reduced to one
+// triangular factor; every later level reduces each problem's stacked factors
+// eight at a time, until one R per problem is left.
 int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coef_out) {
     const int K = h->K, m = K + 1;
-    const int chunk = 4 * m;
+    if (m > 512) return ILU_EINVAL;
     const Ctx c = h->ctx();
     const int np = h->ntets * NFIT;
+    constexpr int64_t QR_RUNS = 512, QR_MIN_RUN = 256;
     std::vector<int64_t> rows(np);
+    int64_t total = 0;
     for (int ti = 0; ti < h->ntets; ++ti)
-        for (int f = 0; f < NFIT; ++f) rows[ti * NFIT + f] = h->tets[ti].samp_cnt[f];
-    std::vector<bool> done(np, false);
+        for (int f = 0; f < NFIT; ++f) total += rows[ti * NFIT + f] = h->tets[ti].samp_cnt[f];
+    const int64_t run0 = std::max<int64_t>(QR_MIN_RUN, (total + QR_RUNS - 1) / QR_RUNS);
     std::vector<int64_t> in_at(np, 0);  // row offset of each problem in the current input
-    DevBuf finalR, in, out, scratch, jobs_d;
-    if (finalR.alloc((size_t)np * m * m * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    // level 0: pieces of chunk - m samples, streamed in runs of run_pieces so
-    // that there are about as many runs as workgroups (one R each)
-    const int grid_max = 256, piece = chunk - m;
-    int64_t pieces = 0;
-    for (int p = 0; p < np; ++p) pieces += (rows[p] + piece - 1) / piece;
-    const int run_pieces = (int)std::max<int64_t>(1, (pieces + grid_max - 1) / grid_max);
-    bool level0 = true;
-    for (int level = 0; level < 64; ++level) {
-        std::vector<QrJob> jobs;
+    DevBuf in, out, jobs_d;
+    for (int level = 0;; ++level) {
+        std::vector<QrJob> jobs(np);
         int64_t outrows = 0;
-        int chunks = 0;
-        std::vector<int> jp;
+        int runs = 0;
+        bool more = false;
         for (int p = 0; p < np; ++p) {
-            if (done[p]) continue;
-            QrJob J{};
+            QrJob& J = jobs[p];
             J.tet = p / NFIT;
             J.fit = p % NFIT;
             J.in_rows = rows[p];
-            J.in_off = level0 ? h->tets[J.tet].samp_off[J.fit] : in_at[p];
-            J.nchunk = level0 ? (int)((rows[p] + (int64_t)piece * run_pieces - 1) / ((int64_t)piece * run_pieces))
-                              : (int)((rows[p] + chunk - 1) / chunk);
-            J.chunk0 = chunks;
+            J.in_off = level == 0 ? h->tets[J.tet].samp_off[J.fit] : in_at[p];
+            J.run_rows = level == 0 ? run0 : (int64_t)8 * m;
+            J.nchunk = (int)std::max<int64_t>(1, (rows[p] + J.run_rows - 1) / J.run_rows);
+            J.chunk0 = runs;
             J.out_off = outrows;
-            chunks += J.nchunk;
+            runs += J.nchunk;
             outrows += (int64_t)J.nchunk * m;
-            jobs.push_back(J);
-            jp.push_back(p);
+            more = more || J.nchunk > 1;
         }
-        if (jobs.empty()) break;
         if (out.alloc((size_t)outrows * m * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
-        const int grid = std::min(chunks, grid_max);
-        if (scratch.bytes < (size_t)grid * chunk * m * sizeof(double))
-            if (scratch.alloc((size_t)grid * chunk * m * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
         if (upload(jobs_d, jobs, st)) return ILU_ENOMEM;
-        launch_qr_chunks(c, jobs_d.as<QrJob>(), (int)jobs.size(), level0 ? 1 : 0, m, chunk, run_pieces,
-                         samples.as<double>(), in.as<double>(), out.as<double>(), scratch.as<double>(), grid, chunks,
-                         st);
+        launch_qr_stream(c, jobs_d.as<QrJob>(), np, level == 0 ? 1 : 0, m, samples.as<double>(), in.as<double>(),
+                         out.as<double>(), (int)std::min<int64_t>(runs, QR_RUNS), runs, st);
         HIPCHK(hipGetLastError());
-        for (size_t j = 0; j < jobs.size(); ++j) {
-            const int p = jp[j];
-            rows[p] = (int64_t)jobs[j].nchunk * m;
-            in_at[p] = jobs[j].out_off;
-            if (jobs[j].nchunk == 1) {
-                done[p] = true;
-                HIPCHK(hipMemcpyAsync(finalR.as<double>() + (size_t)p * m * m, out.as<double>() + jobs[j].out_off * m,
-                                      (size_t)m * m * sizeof(double), hipMemcpyDeviceToDevice, st));
-            }
+        for (int p = 0; p < np; ++p) {
+            rows[p] = (int64_t)jobs[p].nchunk * m;
+            in_at[p] = jobs[p].out_off;
         }
         in.swap(out);
-        level0 = false;
+        if (!more) break;
     }
-    // solve
+    // solve: one R per problem, at row p * m of `in`
     std::vector<QrJob> sj(np);
     for (int p = 0; p < np; ++p) {
         sj[p] = QrJob{};
@@ -528,7 +512,7 @@ int solve_lsq(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coe
     }
     if (upload(jobs_d, sj, st)) return ILU_ENOMEM;
     if (coef_out.alloc((size_t)np * K * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    launch_qr_solve(jobs_d.as<QrJob>(), np, m, finalR.as<double>(), coef_out.as<double>(), h->flags.as<int>(), st);
+    launch_qr_solve(jobs_d.as<QrJob>(), np, m, in.as<double>(), coef_out.as<double>(), h->flags.as<int>(), st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return ILU_OK;
@@ -642,22 +626,41 @@ int build_v1b(ilu_handle_t h, hipStream_t st) {
 
 int setup_sweep_buffers(ilu_handle_t h, hipStream_t st);
 
-// Full setup of one handle.  With `coef_in` (surrogate variants only) the
-// least-squares fit is skipped and these coefficients are used: the fit does
-// not depend on the block shape, so the tile autotuner fits once.
+// Fit of one set of 8 polynomials per tetrahedron from its samples (Sec. 4.1):
+// TSQR least squares on the device, coefficients copied to the host too.
+int fit_samples(ilu_handle_t h, const DevBuf& samples, hipStream_t st, DevBuf& coef_d, std::vector<double>& coef_h) {
+    if (int e = solve_lsq(h, samples, st, coef_d)) return e;
+    int32_t fl[4];
+    if (int e = read_flags(h, st, fl)) return e;
+    if (fl[1]) return ILU_ERANK;
+    coef_h.resize((size_t)h->ntets * NFIT * h->K);
+    HIPCHK(hipMemcpyAsync(coef_h.data(), coef_d.p, coef_h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    return ILU_OK;
+}
+
+// Full setup of one handle (timing_only: layout and zeroed buffers only, for
+// the tile autotuner).
+//  * Stored variants: the stencil is assembled (A8), factored on the
+//    hyperplane schedule into full factor planes and transposed into the
+//    backward weights.
+//  * Surrogate variants: Alg. 1 on a ring of four hyperplanes, each point
+//    leaving its samples (and V1 boundary record) as it is factored, then the
+//    least-squares fit and the per-row tables.  With the exact operator the
+//    stencil is assembled first (the residual reads it); with the surrogate
+//    operator no stencil array is ever formed: the ring kernel computes each
+//    row on the fly and samples it for the operator's own fit.
 int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t h,
-               const std::vector<double>* coef_in = nullptr, const std::vector<double>* coefA_in = nullptr,
                bool timing_only = false) {
     int64_t soff = 0;
     if (int e = prepare(tets, ntets, opts, h, &soff)) return e;
     const bool surr = h->variant != ILU_STORED_F64;
-    const bool refit = !(surr && coef_in);
+    const bool v1 = h->boundary == ILU_BOUNDARY_V1;
+    const bool a_surr = h->a_mode == ILU_A_SURROGATE;  // surrogate variants only
     if (upload(h->tets_d, h->tets, st) || upload(h->blocks_d, h->blocks, st) || upload(h->lanes_d, h->lanes, st))
         return ILU_ENOMEM;
     if (h->flags.alloc(4 * sizeof(int32_t), st) != hipSuccess) return ILU_ENOMEM;
     const int64_t S = h->S;
-    if (h->A8.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-    const bool v1 = h->boundary == ILU_BOUNDARY_V1;
+    if (!a_surr && h->A8.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
     if (timing_only) {
         // every buffer the sweeps read, zero: their kernels have no
         // data-dependent control flow, so the time does not depend on values
@@ -671,9 +674,8 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
             if (h->tab64.alloc(nslots * rec * sizeof(double), st) ||
                 (f32 && h->tab32.alloc(nslots * rec * sizeof(float), st)))
                 return ILU_ENOMEM;
-            if (h->a_mode == ILU_A_SURROGATE &&
-                (h->tabA64.alloc(nslots * rec * sizeof(double), st) ||
-                 (f32 && h->tabA32.alloc(nslots * rec * sizeof(float), st))))
+            if (a_surr && (h->tabA64.alloc(nslots * rec * sizeof(double), st) ||
+                           (f32 && h->tabA32.alloc(nslots * rec * sizeof(float), st))))
                 return ILU_ENOMEM;
             const size_t es = f32 ? sizeof(float) : sizeof(double);
             if (v1 && (h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) ||
@@ -682,12 +684,12 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         }
         return setup_sweep_buffers(h, st);
     }
-    launch_assemble(h->ctx(), h->A8.as<double>(), nullptr, st);
-    HIPCHK(hipGetLastError());
+    if (!a_surr) {
+        launch_assemble(h->ctx(), h->A8.as<double>(), nullptr, st);
+        HIPCHK(hipGetLastError());
+    }
     int32_t fl[4];
     if (!surr) {
-        // stored variants: factorisation on the hyperplane schedule into full
-        // factor planes, transposed into the backward weights
         if (h->Lf.alloc((size_t)7 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         if (h->Df.alloc((size_t)S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         const Ctx c = h->ctx();
@@ -702,63 +704,37 @@ int setup_impl(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hi
         if (h->Lb.alloc((size_t)8 * S * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
         launch_transpose(c, h->Lf.as<double>(), h->Df.as<double>(), h->Lb.as<double>(), st);
         HIPCHK(hipGetLastError());
-    } else {
-        // surrogate variants: Alg. 1 on a ring of four hyperplanes; each point
-        // leaves its samples and (V1) its boundary record as it is factored
-        const bool f32 = h->variant == ILU_SURR_F32;
-        const size_t es = f32 ? sizeof(float) : sizeof(double);
-        DevBuf samples;
-        if (refit && samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-        if (v1 && h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
-        if (refit || v1) {
-            const int64_t nring = (int64_t)h->blocks.size() * h->bv * h->bw + 1;
-            DevBuf ring;
-            if (ring.alloc((size_t)8 * 4 * nring * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-            const Ctx c = h->ctx();
-            for (int t = h->tmin; t <= h->tmax; ++t)
-                launch_factor_ring(c, t, ring.as<double>(), nring, refit ? samples.as<double>() : nullptr,
-                                   v1 ? h->v1f.p : nullptr, f32, h->flags.as<int>(), st);
-            HIPCHK(hipGetLastError());
-            if (int e = read_flags(h, st, fl)) return e;
-            if (fl[0]) return ILU_EBREAKDOWN;
-        }
-        if (refit) {
-            if (int e = solve_lsq(h, samples, st, h->coef_d)) return e;
-            if (int e = read_flags(h, st, fl)) return e;
-            if (fl[1]) return ILU_ERANK;
-            h->coef_h.resize((size_t)ntets * NFIT * h->K);
-            HIPCHK(hipMemcpyAsync(h->coef_h.data(), h->coef_d.p, h->coef_h.size() * sizeof(double),
-                                  hipMemcpyDeviceToHost, st));
-        } else {
-            h->coef_h = *coef_in;
-            if (h->coef_d.alloc(h->coef_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
-            HIPCHK(hipMemcpyAsync(h->coef_d.p, h->coef_h.data(), h->coef_h.size() * sizeof(double),
-                                  hipMemcpyHostToDevice, st));
-        }
-        if (int e = build_tables(h, st)) return e;
-        if (v1)
-            if (int e = build_v1b(h, st)) return e;
+        return setup_sweep_buffers(h, st);
     }
-    // surrogate operator: the centre and lower stencil weights sampled on the
-    // same sets and fitted like the factors (or injected by the autotuner)
-    if (h->a_mode == ILU_A_SURROGATE) {
-        if (coefA_in) {
-            h->coefA_h = *coefA_in;
-            if (h->coefA_d.alloc(h->coefA_h.size() * sizeof(double), st, false) != hipSuccess) return ILU_ENOMEM;
-            HIPCHK(hipMemcpyAsync(h->coefA_d.p, h->coefA_h.data(), h->coefA_h.size() * sizeof(double),
-                                  hipMemcpyHostToDevice, st));
-        } else {
-            DevBuf samples;
-            if (samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
-            launch_gather_a_samples(h->ctx(), samples.as<double>(), st);
-            HIPCHK(hipGetLastError());
-            if (int e = solve_lsq(h, samples, st, h->coefA_d)) return e;
-            if (int e = read_flags(h, st, fl)) return e;
-            if (fl[1]) return ILU_ERANK;
-            h->coefA_h.resize((size_t)ntets * NFIT * h->K);
-            HIPCHK(hipMemcpyAsync(h->coefA_h.data(), h->coefA_d.p, h->coefA_h.size() * sizeof(double),
-                                  hipMemcpyDeviceToHost, st));
-        }
+    const bool f32 = h->variant == ILU_SURR_F32;
+    const size_t es = f32 ? sizeof(float) : sizeof(double);
+    DevBuf samples, asamples;
+    if (samples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    if (a_surr && asamples.alloc((size_t)soff * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+    if (v1 && h->v1f.alloc((size_t)8 * (h->v1_nf + 1) * es, st) != hipSuccess) return ILU_ENOMEM;
+    {
+        const int64_t nring = (int64_t)h->blocks.size() * h->bv * h->bw + 1;
+        DevBuf ring;
+        if (ring.alloc((size_t)8 * 4 * nring * sizeof(double), st) != hipSuccess) return ILU_ENOMEM;
+        const Ctx c = h->ctx();
+        for (int t = h->tmin; t <= h->tmax; ++t)
+            launch_factor_ring(c, t, ring.as<double>(), nring, samples.as<double>(),
+                               a_surr ? asamples.as<double>() : nullptr, v1 ? h->v1f.p : nullptr, f32,
+                               h->flags.as<int>(), st);
+        HIPCHK(hipGetLastError());
+        if (int e = read_flags(h, st, fl)) return e;
+        if (fl[0]) return ILU_EBREAKDOWN;
+    }
+    if (int e = fit_samples(h, samples, st, h->coef_d, h->coef_h)) return e;
+    samples.release();
+    if (int e = build_tables(h, st)) return e;
+    if (v1)
+        if (int e = build_v1b(h, st)) return e;
+    // surrogate operator: the centre and lower stencil weights, sampled on the
+    // same sets and fitted like the factors
+    if (a_surr) {
+        if (int e = fit_samples(h, asamples, st, h->coefA_d, h->coefA_h)) return e;
+        asamples.release();
         if (int e = build_tables_from(h, st, h->coefA_d, h->tabA64, h->tabA32)) return e;
     }
     return setup_sweep_buffers(h, st);
@@ -841,7 +817,7 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
         o.tile[1] = sh[1];
         ilu_handle_t h = new (std::nothrow) ilu_handle_s();
         if (!h) return ILU_ENOMEM;
-        int rc = setup_impl(tets, ntets, &o, st, h, nullptr, nullptr, true);
+        int rc = setup_impl(tets, ntets, &o, st, h, true);
         const int gmax = h->flow_grid_max;
         struct Cand { int ovl, grid; };
         Cand cands[5] = {{ILU_OVERLAP_OFF, gmax}, {ILU_OVERLAP_OFF, gmax / 2}, {ILU_OVERLAP_OFF, gmax / 3},

@@ -50,14 +50,6 @@ constexpr long SPIN_LIMIT = 1L << 20;
 // accumulation order over D_l: s, bnw, bc, be (older hyperplanes) then w, se, bn
 constexpr int ORD[7] = {1, 3, 5, 6, 0, 2, 4};
 
-// Workgroup barrier that orders LDS traffic only: a full __syncthreads()
-// would also wait for this wave's outstanding global stores and loads.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 template <int N>
 struct IC {
     static constexpr int value = N;

@@ -63,6 +63,14 @@ __host__ __device__ __forceinline__ int64_t lex_index(int n, int x, int y, int z
     return choose3(n - 1) - choose3(n - z) + (int64_t)(y - 1) * m - (int64_t)(y - 1) * y / 2 + (x - 1);
 }
 
+// Workgroup barrier that orders LDS traffic only: a full __syncthreads()
+// would also wait for this wave's outstanding global stores and loads.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Shifted Legendre values P_0..P_deg at s = 2 xhat - 1.
 __device__ __forceinline__ void legendre(double s, int deg, double* P) {
     P[0] = 1.0;

@@ -72,8 +72,10 @@ __global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __re
 // of Sec. 3 (eq. matrix-equations) in the order of Alg. 1 -- bc, s, bnw, be,
 // w, bn, se, then the pivot c -- from the already factored lower neighbours.
 // Neighbours that are not interior contribute L = 0, D = 1 (the guard values
-// of Alg. 1).  Factors are written to Lf[7][S] (lower weights) and Df[S].
-// The first point with D <= 0 is reported through flags[0].
+// of Alg. 1).  k_factor_plane writes the factors to full planes Lf[7][S]
+// (lower weights) and Df[S], k_factor_ring to a ring of four hyperplanes.
+// A point with D <= 0 is reported through flags[0].
+
 // The stencil equations of one point (Alg. 1): lower weights a[s] = A^p_{d_s}
 // and centre Ac of the point, pivots Dn[s] of the lower neighbours (1 where
 // the neighbour is not interior) and their factors Lq(s, d) = L^{p+d_s}_d (0
@@ -137,83 +139,6 @@ __global__ void k_factor_plane(const TetDev* __restrict__ tets, const BlockDev* 
     if (!(Dp > 0.0)) atomicOr(&flags[0], 1);
 }
 
-// Samples of one factored point (Sec. 4.1, reading of the garbled formula):
-// for every fitted direction whose sample set S_d holds p (p = shift_d mod
-// stride componentwise, shift_d = 1 - min(d, 0), and p + d interior), the
-// value L^p_d (lower directions) or 1/D^p (centre) at its lexicographic
-// position k = (p - shift)/stride in the lattice simplex of S_d.
-__device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz);
-__device__ __forceinline__ void put_samples(const TetDev& T, int x, int y, int z, const double (&Lp)[NLOW], double Dp,
-                                            double* __restrict__ samples) {
-    const int n = T.n, st = T.stride;
-    for (int f = 0; f < NFIT; ++f) {
-        const int dx = f < NLOW ? low_dx(f) : 0, dy = f < NLOW ? low_dy(f) : 0, dz = f < NLOW ? low_dz(f) : 0;
-        const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
-        if ((x - sx) % st || (y - sy) % st || (z - sz) % st) continue;
-        if (!interior(n, x + dx, y + dy, z + dz)) continue;
-        const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
-        samples[T.samp_off[f] + simplex_index(T.samp_M[f], kx, ky, kz)] = f < NLOW ? Lp[f] : 1.0 / Dp;
-    }
-}
-
-// Alg. 1 in O(h^-2) memory (surrogate variants): the factors of hyperplane t
-// go to slot t mod 4 of a ring of four hyperplanes, ring[(k * 4 + slot) *
-// nring + global lane], k = 0..6 the lower factors and 7 the pivot, nring =
-// lanes + 1 (the last lane is zero and stands for rows outside the lattice);
-// the stencil equations at t read t-1 .. t-3 only.  Each factored point
-// leaves its samples (and, variant V1, its boundary record [L_0..L_6, 1/D])
-// right away, so no full factor array is ever held.
-template <typename FT>
-__global__ void k_factor_ring(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                              const LaneDev* __restrict__ lanes, int lpb, int groups, int t_glob, int64_t S,
-                              const double* __restrict__ A8, double* __restrict__ ring, int64_t nring,
-                              double* __restrict__ samples, FT* __restrict__ F, int* __restrict__ flags) {
-    int b, lane;
-    decode_group(groups, b, lane);
-    const BlockDev& B = blocks[b];
-    const int t = t_glob;
-    if (t < B.tb || t > B.te) return;
-    const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
-    if (Ln.v == 0) return;
-    const TetDev& T = tets[B.tet];
-    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w, xmax = n - 1 - v;
-    const int x = t - 2 * v - w;
-    if (x < 1 || x > xmax) return;
-    const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
-    int64_t q[NLOW];
-    bool in[NLOW];
-    double Dn[NLOW], a[NLOW];
-#pragma unroll
-    for (int s = 0; s < NLOW; ++s) {
-        const int32_t g = Ln.gl[low_row(s)];
-        const int slot = (t + low_dt(s)) & 3;
-        q[s] = (int64_t)slot * nring + (g >= 0 ? g : nring - 1);
-        in[s] = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
-        Dn[s] = in[s] ? ring[(int64_t)7 * 4 * nring + q[s]] : 1.0;
-        a[s] = A8[(int64_t)(1 + s) * S + idx];
-    }
-    auto Lq = [&](int s, int d) -> double { return in[s] ? ring[(int64_t)d * 4 * nring + q[s]] : 0.0; };
-    double Lp[NLOW], Dp;
-    stencil_equations(a, A8[idx], Dn, Lq, Lp, Dp);
-#pragma unroll
-    for (int s = 0; s < NLOW; ++s) Lp[s] = in[s] ? Lp[s] : 0.0;
-    const int64_t me = (int64_t)(t & 3) * nring + Ln.gl[R_SELF];
-#pragma unroll
-    for (int s = 0; s < NLOW; ++s) ring[(int64_t)s * 4 * nring + me] = Lp[s];
-    ring[(int64_t)7 * 4 * nring + me] = Dp;
-    if (!(Dp > 0.0)) atomicOr(&flags[0], 1);
-    if (samples) put_samples(T, x, y, z, Lp, Dp, samples);
-    if (F) {
-        const int k = v1f_pos(x, xmax, y, z);
-        if (k >= 0) {
-            const int64_t j = (int64_t)Ln.v1f[0] + k;
-#pragma unroll
-            for (int s = 0; s < NLOW; ++s) F[j * 8 + s] = (FT)Lp[s];
-            F[j * 8 + NLOW] = (FT)(1.0 / Dp);
-        }
-    }
-}
-
 // Backward-sweep weights per point: Lb[0] = 1/D^p, Lb[1+s] = L^{p-d_s}_{d_s}
 // (the transposed factor, read from the upper neighbour; 0 if that neighbour
 // is not interior).
@@ -246,82 +171,155 @@ __global__ void k_transpose_factors(const TetDev* __restrict__ tets, const Block
 // p = shift_d (mod stride) componentwise with shift_d = 1 - min(d, 0), and
 // p + d interior.  With k = (p - shift)/stride the set is the lattice simplex
 // {k >= 0, k_x + k_y + k_z <= M_d}; sample k is stored at its lexicographic
-// position (k_z slowest).  Values: L^p_d for the lower directions, 1/D^p for c.
+// position (k_z slowest).
 __device__ __forceinline__ int64_t simplex_index(int M, int kx, int ky, int kz) {
     // points with k_z' < k_z: C(M+3,3) - C(M+3-kz,3)
     const int64_t Mz = M - kz;  // layer side
     return choose3(M + 3) - choose3(M + 3 - kz) + (int64_t)ky * (Mz + 1) - (int64_t)ky * (ky - 1) / 2 + kx;
 }
 
-// Samples of the assembled stencil (centre and lower weights) on the sample
-// sets of the factors (the factors' own samples leave k_factor_ring).
-__global__ void k_gather_a_samples(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
-                                   const LaneDev* __restrict__ lanes, int lpb, int groups, int64_t S,
-                                   const double* __restrict__ A8, double* __restrict__ samples) {
+// Samples of one point (Sec. 4.1, reading of the garbled formula): for every
+// fitted direction whose sample set S_d holds p (p = shift_d mod stride
+// componentwise, shift_d = 1 - min(d, 0), and p + d interior), val[f] (the
+// lower directions, then the centre) at its lexicographic position
+// k = (p - shift)/stride in the lattice simplex of S_d.
+__device__ __forceinline__ void put_samples(const TetDev& T, int x, int y, int z, const double (&val)[NFIT],
+                                            double* __restrict__ samples) {
+    const int n = T.n, st = T.stride;
+    for (int f = 0; f < NFIT; ++f) {
+        const int dx = f < NLOW ? low_dx(f) : 0, dy = f < NLOW ? low_dy(f) : 0, dz = f < NLOW ? low_dz(f) : 0;
+        const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
+        if ((x - sx) % st || (y - sy) % st || (z - sz) % st) continue;
+        if (!interior(n, x + dx, y + dy, z + dz)) continue;
+        const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
+        samples[T.samp_off[f] + simplex_index(T.samp_M[f], kx, ky, kz)] = val[f];
+    }
+}
+
+// Alg. 1 in O(h^-2) memory (surrogate variants): the factors of hyperplane t
+// go to slot t mod 4 of a ring of four hyperplanes, ring[(k * 4 + slot) *
+// nring + global lane], k = 0..6 the lower factors and 7 the pivot, nring =
+// lanes + 1 (the last lane is zero and stands for rows outside the lattice);
+// the stencil equations at t read t-1 .. t-3 only.  Each factored point
+// leaves its samples (L^p_d, 1/D^p) and, variant V1, its boundary record
+// [L_0..L_6, 1/D] right away, so no full factor array is ever held.  Without
+// an assembled stencil (A8 null: the surrogate operator) the point's stencil
+// row is computed here, as the assembly would, and its samples (A^p_d, A^p_c)
+// go to asamples: then the whole setup holds no O(h^-3) array.
+template <typename FT>
+__global__ void k_factor_ring(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+                              const LaneDev* __restrict__ lanes, int lpb, int groups, int t_glob, int64_t S,
+                              const double* __restrict__ A8, double* __restrict__ ring, int64_t nring,
+                              double* __restrict__ samples, double* __restrict__ asamples, FT* __restrict__ F,
+                              int* __restrict__ flags) {
     int b, lane;
     decode_group(groups, b, lane);
-    const BlockDev B = blocks[b];
+    const BlockDev& B = blocks[b];
+    const int t = t_glob;
+    if (t < B.tb || t > B.te) return;
     const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
     if (Ln.v == 0) return;
     const TetDev& T = tets[B.tet];
-    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w, st = T.stride;
-    for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
-        const int x = t - 2 * v - w;
-        if (x < 1 || x > n - 1 - v) continue;
-        const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
-        for (int f = 0; f < NFIT; ++f) {
-            const int dx = f < NLOW ? low_dx(f) : 0, dy = f < NLOW ? low_dy(f) : 0, dz = f < NLOW ? low_dz(f) : 0;
-            const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
-            if ((x - sx) % st || (y - sy) % st || (z - sz) % st) continue;
-            if (!interior(n, x + dx, y + dy, z + dz)) continue;
-            const int kx = (x - sx) / st, ky = (y - sy) / st, kz = (z - sz) / st;
-            const int64_t si = simplex_index(T.samp_M[f], kx, ky, kz);
-            samples[T.samp_off[f] + si] = f < NLOW ? A8[(int64_t)(1 + f) * S + idx] : A8[idx];
+    const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w, xmax = n - 1 - v;
+    const int x = t - 2 * v - w;
+    if (x < 1 || x > xmax) return;
+    const int64_t idx = Ln.rp[R_SELF] + (int64_t)lpb * t;
+    int64_t q[NLOW];
+    bool in[NLOW];
+    double Dn[NLOW], a[NLOW], Ac;
+    double Ad[15];
+    if (!A8)
+        stencil_row(T.J, T.v0, 1.0 / n, x, y, z, [&](double X, double Y, double Z) { return kappa_at(T, X, Y, Z); },
+                    Ad);
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) {
+        const int32_t g = Ln.gl[low_row(s)];
+        const int slot = (t + low_dt(s)) & 3;
+        q[s] = (int64_t)slot * nring + (g >= 0 ? g : nring - 1);
+        in[s] = interior(n, x + low_dx(s), y + low_dy(s), z + low_dz(s));
+        Dn[s] = in[s] ? ring[(int64_t)7 * 4 * nring + q[s]] : 1.0;
+        a[s] = A8 ? A8[(int64_t)(1 + s) * S + idx] : (in[s] ? Ad[s] : 0.0);
+    }
+    Ac = A8 ? A8[idx] : Ad[7];
+    auto Lq = [&](int s, int d) -> double { return in[s] ? ring[(int64_t)d * 4 * nring + q[s]] : 0.0; };
+    double Lp[NLOW], Dp;
+    stencil_equations(a, Ac, Dn, Lq, Lp, Dp);
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) Lp[s] = in[s] ? Lp[s] : 0.0;
+    const int64_t me = (int64_t)(t & 3) * nring + Ln.gl[R_SELF];
+#pragma unroll
+    for (int s = 0; s < NLOW; ++s) ring[(int64_t)s * 4 * nring + me] = Lp[s];
+    ring[(int64_t)7 * 4 * nring + me] = Dp;
+    if (!(Dp > 0.0)) atomicOr(&flags[0], 1);
+    if (samples) {
+        double val[NFIT];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s) val[s] = Lp[s];
+        val[NLOW] = 1.0 / Dp;
+        put_samples(T, x, y, z, val, samples);
+    }
+    if (asamples) {
+        double val[NFIT];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s) val[s] = a[s];
+        val[NLOW] = Ac;
+        put_samples(T, x, y, z, val, asamples);
+    }
+    if (F) {
+        const int k = v1f_pos(x, xmax, y, z);
+        if (k >= 0) {
+            const int64_t j = (int64_t)Ln.v1f[0] + k;
+#pragma unroll
+            for (int s = 0; s < NLOW; ++s) F[j * 8 + s] = (FT)Lp[s];
+            F[j * 8 + NLOW] = (FT)(1.0 / Dp);
         }
     }
 }
 
 // ------------------------------------------------------------ least squares
 
-constexpr int QB = 8;  // Householder panel width of the chunk QR
-
-// Sums of NV per-thread values over the workgroup (256 threads): each
-// wavefront reduces by shuffles, then the four wavefront sums are added in a
-// fixed order.  lds: 4 * NV doubles.  Every thread gets the sums.
-template <int NV>
-__device__ __forceinline__ void block_sums(double (&v)[NV], double* lds) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int k = 0; k < NV; ++k) lds[wv * NV + k] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
-    __syncthreads();
+// P_a(s) of the shifted Legendre recurrence (the values legendre() tabulates).
+__device__ __forceinline__ double legendre_at(double s, int a) {
+    if (a == 0) return 1.0;
+    double pm = 1.0, p = s;
+    for (int k = 1; k < a; ++k) {
+        const double pn = ((2 * k + 1) * s * p - k * pm) / (k + 1);
+        pm = p;
+        p = pn;
+    }
+    return p;
 }
 
-// Householder QR of chunks of rows, one workgroup per chunk, FP64.  A chunk
-// is copied into the workgroup's row-major scratch (rows x m, zero-padded),
-// reduced in place, and its m x m triangular factor R is written as m rows of
-// the output.  Stacking the R factors of the chunks and factoring again yields
-// the R of the whole least-squares matrix (TSQR).
-// Level 0 streams: chunk c of a problem is a run of `run_pieces` pieces of
-// chunk_rows - m sample rows ([basis values | sample value]); each piece is
-// stacked under the R of the run so far (the first under zeros) and the stack
-// is factored again, so a run leaves one R however many samples it covers.
-// Later levels read stacked R factors, chunk_rows of them per chunk.
-__global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ tets, const QrJob* __restrict__ jobs,
-                                                   int njobs, int level0, int m, int chunk_rows, int run_pieces,
-                                                   const double* __restrict__ samples, const double* __restrict__ in,
-                                                   double* __restrict__ out, double* __restrict__ scratch_all,
-                                                   int nchunks_total) {
-    extern __shared__ double sh[];  // reduction scratch
-    for (int cid = blockIdx.x; cid < nchunks_total; cid += gridDim.x) {
-        // locate job
+// Streaming Householder QR of the rows of one least-squares problem (FP64),
+// as in TSQR with flat trees: a run of rows is taken QR_ROWS at a time as a
+// block B under the triangular factor R of the rows before it, and [R; B] is
+// reduced to the new R by m reflectors that each touch one row of R and all
+// rows of B (R's structure below the diagonal is kept).  Reflector j:
+// x = [R_jj; B_:j], beta = -sign(R_jj) |x|, v = [1; B_:j / (R_jj - beta)],
+// tau = (beta - R_jj) / beta; every column k > j gets s = R_jk + v^T B_:k,
+// R_jk -= tau s, B_:k -= tau s v.
+// Thread k owns column k: its QR_ROWS entries of B in registers and its
+// entries of R in the run's output slot (m x m, row-major, zeros below the
+// diagonal), so R needs no synchronisation; reflector j's v is passed through
+// shared memory by thread j (double-buffered: one barrier per reflector).
+// Level 0 builds the rows from the samples ([basis values | sample value] at
+// the sample points), later levels read the stacked R factors of the level
+// before.  Each run leaves its R; stacking them and reducing again gives the
+// R of the whole problem.
+constexpr int QR_ROWS = 32;  // rows per block
+constexpr int QR_MAXM = 512; // columns (threads per workgroup) at most
+
+__global__ void __launch_bounds__(QR_MAXM) k_qr_stream(const TetDev* __restrict__ tets,
+                                                       const QrJob* __restrict__ jobs, int njobs, int level0, int m,
+                                                       const double* __restrict__ samples,
+                                                       const double* __restrict__ in, double* __restrict__ out,
+                                                       int nruns) {
+    __shared__ double vbuf[2][QR_ROWS];
+    __shared__ double taus[2];
+    __shared__ double pts[QR_ROWS][4];  // level 0: rescaled sample point and value of each block row
+    const int k = (int)threadIdx.x;
+    const bool col = k < m;
+    for (int cid = blockIdx.x; cid < nruns; cid += gridDim.x) {
         int lo = 0, hi = njobs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
@@ -329,209 +327,109 @@ __global__ void __launch_bounds__(256) k_qr_chunks(const TetDev* __restrict__ te
         }
         const QrJob J = jobs[lo];
         const int c = cid - J.chunk0;
-        double* A = scratch_all + (int64_t)blockIdx.x * chunk_rows * m;
-        const int pr = level0 ? chunk_rows - m : chunk_rows;  // new rows per piece
-        const int64_t rbeg = level0 ? (int64_t)c * run_pieces * pr : (int64_t)c * chunk_rows;
-        const int64_t rend = level0 ? min<int64_t>(J.in_rows, rbeg + (int64_t)run_pieces * pr)
-                                    : min<int64_t>(J.in_rows, rbeg + chunk_rows);
-        for (int64_t p0 = rbeg; p0 < rend; p0 += pr) {
-        // fill
-        if (level0) {
-            const TetDev& T = tets[J.tet];
-            const int K = m - 1;
-            const int dgx = T.deg[0], dgy = T.deg[1], dgz = T.deg[2];
-            const int M = T.samp_M[J.fit];
-            const int dx = J.fit < NLOW ? low_dx(J.fit) : 0, dy = J.fit < NLOW ? low_dy(J.fit) : 0,
-                      dz = J.fit < NLOW ? low_dz(J.fit) : 0;
-            const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
-            const double invn = 1.0 / T.n;
-            // the R of the run so far (zeros before the first piece): clear
-            // the reflectors left below its diagonal
-            for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
-                const int r = (int)(e / m), k = (int)(e % m);
-                if (p0 == rbeg || k < r) A[e] = 0.0;
-            }
-            for (int r = m + threadIdx.x; r < chunk_rows; r += blockDim.x) {
-                double* row = A + (int64_t)r * m;
-                int64_t si = p0 + (r - m);
-                if (si >= rend) {
-                    for (int k = 0; k < m; ++k) row[k] = 0.0;
-                    continue;
-                }
-                const double val = samples[J.in_off + si];
-                // decode the lexicographic simplex index back to k
-                int kz = 0;
-                while (choose3(M + 3) - choose3(M + 3 - (kz + 1)) <= si) ++kz;
-                si -= choose3(M + 3) - choose3(M + 3 - kz);
-                const int Mz = M - kz;
-                int ky = 0;
-                while ((int64_t)(ky + 1) * (Mz + 1) - (int64_t)(ky + 1) * ky / 2 <= si) ++ky;
-                si -= (int64_t)ky * (Mz + 1) - (int64_t)ky * (ky - 1) / 2;
-                const int kx = (int)si;
-                const double X = (sx + T.stride * kx) * invn, Y = (sy + T.stride * ky) * invn,
-                             Z = (sz + T.stride * kz) * invn;
-                double px[9], py[9], pz[9];
-                legendre(2 * X - 1, dgx, px);
-                legendre(2 * Y - 1, dgy, py);
-                legendre(2 * Z - 1, dgz, pz);
-                int col = 0;
-                for (int kk = 0; kk <= dgz; ++kk)
-                    for (int j = 0; j <= dgy; ++j)
-                        for (int i = 0; i <= dgx; ++i) row[col++] = px[i] * py[j] * pz[kk];
-                row[K] = val;
-            }
-        } else {
-            const int nr = (int)(rend - rbeg);
-            for (int64_t e = threadIdx.x; e < (int64_t)chunk_rows * m; e += blockDim.x) {
-                const int r = (int)(e / m), k = (int)(e % m);
-                A[e] = r < nr ? in[(J.in_off + rbeg + r) * m + k] : 0.0;
-            }
-        }
-        __syncthreads();
-        const int rows = chunk_rows;
-        // Blocked Householder: panels of QB columns.  Inside a panel each
-        // reflector H_j = I - tau_j v_j v_j^T (v_j(j) = 1, below it the scaled
-        // column, stored in place) is applied to the panel's remaining
-        // columns; the panel's product H_j0 ... H_j0+b-1 = I - Y T Y^T (T upper
-        // triangular) is then applied to the trailing columns at once,
-        // A_k <- A_k - Y (T^T (Y^T A_k)): two passes over the trailing
-        // matrix per panel instead of two per column.
-        double* taus = sh;                      // [QB] reflector scales of the panel
-        double* Tm = taus + QB;                 // [QB][QB] the panel's T
-        double* red = Tm + QB * QB;             // [4][QB*QB] block sums
-        const int NTH = 256;                    // rows are split over the threads: i = tid (mod 256)
-        const int tid = (int)threadIdx.x;
-        for (int j0 = 0; j0 < m && j0 < rows; j0 += QB) {
-            const int jb = min(QB, min(m, rows) - j0);
-            for (int q = 0; q < jb; ++q) {
-                const int j = j0 + q;
-                double sg[1] = {0.0};
-                for (int i = j + 1 + tid; i < rows; i += NTH) {
-                    const double a = A[(int64_t)i * m + j];
-                    sg[0] += a * a;
-                }
-                block_sums<1>(sg, red);
-                const double sigma = sg[0];
-                const double alpha = A[(int64_t)j * m + j];
-                if (sigma == 0.0) {  // column already reduced: H = I
-                    if (tid == 0) taus[q] = 0.0;
-                    __syncthreads();
-                    continue;
-                }
-                const double nrm = sqrt(alpha * alpha + sigma);
-                const double beta = alpha > 0.0 ? -nrm : nrm;
-                const double tau = (beta - alpha) / beta;
-                const double scl = 1.0 / (alpha - beta);
-                for (int i = j + 1 + tid; i < rows; i += NTH) A[(int64_t)i * m + j] *= scl;
-                __syncthreads();
-                // the panel's remaining columns: dots over the rows below j, then the update
-                const int nk = j0 + jb - 1 - j;
-                if (nk > 0) {
-                    double d[QB];
-#pragma unroll
-                    for (int c = 0; c < QB; ++c) d[c] = 0.0;
-                    for (int i = j + 1 + tid; i < rows; i += NTH) {
-                        const double vi = A[(int64_t)i * m + j];
-#pragma unroll
-                        for (int c = 0; c < QB; ++c)
-                            if (c < nk) d[c] += vi * A[(int64_t)i * m + j + 1 + c];
-                    }
-                    block_sums<QB>(d, red);
-                    double wk[QB];
-#pragma unroll
-                    for (int c = 0; c < QB; ++c) wk[c] = c < nk ? tau * (A[(int64_t)j * m + j + 1 + c] + d[c]) : 0.0;
-                    __syncthreads();
-                    if (tid == 0)
-#pragma unroll
-                        for (int c = 0; c < QB; ++c)
-                            if (c < nk) A[(int64_t)j * m + j + 1 + c] -= wk[c];
-                    for (int i = j + 1 + tid; i < rows; i += NTH) {
-                        const double vi = A[(int64_t)i * m + j];
-#pragma unroll
-                        for (int c = 0; c < QB; ++c)
-                            if (c < nk) A[(int64_t)i * m + j + 1 + c] -= wk[c] * vi;
-                    }
+        const int64_t rbeg = (int64_t)c * J.run_rows, rend = min<int64_t>(J.in_rows, rbeg + J.run_rows);
+        double* R = out + (J.out_off + (int64_t)c * m) * m;
+        if (col)
+            for (int r = 0; r < m; ++r) R[(int64_t)r * m + k] = 0.0;
+        // the basis function of column k (level 0): Legendre degrees (i, j, l)
+        // with x fastest, the last column is the sample value
+        const TetDev& T = tets[J.tet];
+        const int nx = T.deg[0] + 1, ny = T.deg[1] + 1;
+        const int bi = k % nx, bj = (k / nx) % ny, bl = k / (nx * ny);
+        for (int64_t p0 = rbeg; p0 < rend; p0 += QR_ROWS) {
+            const int nb = (int)min<int64_t>(QR_ROWS, rend - p0);
+            double Bc[QR_ROWS];
+            if (level0) {
+                if (k < nb) {
+                    const int M = T.samp_M[J.fit];
+                    const int dx = J.fit < NLOW ? low_dx(J.fit) : 0, dy = J.fit < NLOW ? low_dy(J.fit) : 0,
+                              dz = J.fit < NLOW ? low_dz(J.fit) : 0;
+                    const int sx = 1 - (dx < 0 ? dx : 0), sy = 1 - (dy < 0 ? dy : 0), sz = 1 - (dz < 0 ? dz : 0);
+                    // decode the lexicographic simplex index back to the lattice point
+                    int64_t si = p0 + k;
+                    const double val = samples[J.in_off + si];
+                    int kz = 0;
+                    while (choose3(M + 3) - choose3(M + 3 - (kz + 1)) <= si) ++kz;
+                    si -= choose3(M + 3) - choose3(M + 3 - kz);
+                    const int Mz = M - kz;
+                    int ky = 0;
+                    while ((int64_t)(ky + 1) * (Mz + 1) - (int64_t)(ky + 1) * ky / 2 <= si) ++ky;
+                    si -= (int64_t)ky * (Mz + 1) - (int64_t)ky * (ky - 1) / 2;
+                    const int kx = (int)si;
+                    const double invn = 1.0 / T.n;
+                    pts[k][0] = 2 * ((sx + T.stride * kx) * invn) - 1;
+                    pts[k][1] = 2 * ((sy + T.stride * ky) * invn) - 1;
+                    pts[k][2] = 2 * ((sz + T.stride * kz) * invn) - 1;
+                    pts[k][3] = val;
                 }
                 __syncthreads();
-                if (tid == 0) {
-                    taus[q] = tau;
-                    A[(int64_t)j * m + j] = beta;
+#pragma unroll
+                for (int i = 0; i < QR_ROWS; ++i) {
+                    double v = 0.0;
+                    if (col && i < nb)
+                        v = k == m - 1 ? pts[i][3]
+                                       : legendre_at(pts[i][0], bi) * legendre_at(pts[i][1], bj) *
+                                             legendre_at(pts[i][2], bl);
+                    Bc[i] = v;
                 }
                 __syncthreads();
+            } else {
+                const int kc = col ? k : 0;
+#pragma unroll
+                for (int i = 0; i < QR_ROWS; ++i)
+                    Bc[i] = (col && i < nb) ? in[(J.in_off + p0 + i) * m + kc] : 0.0;
             }
-            if (j0 + jb >= m) break;  // no trailing columns
-            // T of the panel: T[q][q] = tau_q, T[0:q][q] = -tau_q T[0:q][0:q] g,
-            // g[r] = v_r^T v_q, from the Gram entries of the reflectors (v_p is 0
-            // above row j0+p, 1 at it, the stored column below it)
-            double g[QB * QB];
+            // R_jk for the next four reflectors, loaded ahead (row j of R
+            // changes only under reflector j, and only thread k touches
+            // column k); unconditional loads at a clamped row, and four
+            // registers in turn, so each wait covers the load of four
+            // reflectors ago only
+            const int kc = col ? k : 0;
+            auto rload = [&](int r) { return R[(int64_t)min(r, m - 1) * m + kc]; };
+            auto reflect = [&](int j, double rjk) {
+                const int buf = j & 1;
+                if (k == j) {
+                    double sg = 0.0;
 #pragma unroll
-            for (int e = 0; e < QB * QB; ++e) g[e] = 0.0;
-            for (int i = j0 + tid; i < rows; i += NTH) {
-                double y[QB];
+                    for (int i = 0; i < QR_ROWS; ++i) sg += Bc[i] * Bc[i];
+                    double tau = 0.0;
+                    if (sg != 0.0) {  // else the column is already reduced: H = I
+                        const double alpha = rjk;
+                        const double nrm = sqrt(alpha * alpha + sg);
+                        const double beta = alpha > 0.0 ? -nrm : nrm;
+                        tau = (beta - alpha) / beta;
+                        const double scl = 1.0 / (alpha - beta);
 #pragma unroll
-                for (int c = 0; c < QB; ++c)
-                    y[c] = c < jb ? (i > j0 + c ? A[(int64_t)i * m + j0 + c] : (i == j0 + c ? 1.0 : 0.0)) : 0.0;
-#pragma unroll
-                for (int pp = 0; pp < QB; ++pp)
-#pragma unroll
-                    for (int qq = pp + 1; qq < QB; ++qq) g[pp * QB + qq] += y[pp] * y[qq];
-            }
-            block_sums<QB * QB>(g, red);
-            if (tid == 0) {
-                for (int qq = 0; qq < jb; ++qq) {
-                    double z[QB];
-                    for (int pp = 0; pp < qq; ++pp) {
-                        double acc = 0.0;
-                        for (int r = pp; r < qq; ++r) acc += Tm[pp * QB + r] * g[r * QB + qq];
-                        z[pp] = acc;
+                        for (int i = 0; i < QR_ROWS; ++i) vbuf[buf][i] = Bc[i] * scl;
+                        R[(int64_t)j * m + j] = beta;
                     }
-                    for (int pp = 0; pp < qq; ++pp) Tm[pp * QB + qq] = -taus[qq] * z[pp];
-                    Tm[qq * QB + qq] = taus[qq];
+                    taus[buf] = tau;
                 }
-            }
-            __syncthreads();
-            // trailing columns, one thread per column: w = Y^T A_k, u = T^T w,
-            // A_k -= Y u
-            for (int k = j0 + jb + tid; k < m; k += NTH) {
-                double w[QB];
+                lds_barrier();  // v and tau of reflector j; R and B stay private to their threads
+                const double tau = taus[buf];
+                if (col && k > j && tau != 0.0) {
+                    double sv = rjk;
 #pragma unroll
-                for (int c = 0; c < QB; ++c) w[c] = 0.0;
-                for (int i = j0; i < rows; ++i) {
-                    const double a = A[(int64_t)i * m + k];
-                    const double* yr = A + (int64_t)i * m + j0;
+                    for (int i = 0; i < QR_ROWS; ++i) sv += vbuf[buf][i] * Bc[i];
+                    sv *= tau;
+                    R[(int64_t)j * m + k] = rjk - sv;
 #pragma unroll
-                    for (int c = 0; c < QB; ++c) {
-                        const double y = c < jb ? (i > j0 + c ? yr[c] : (i == j0 + c ? 1.0 : 0.0)) : 0.0;
-                        w[c] += y * a;
-                    }
+                    for (int i = 0; i < QR_ROWS; ++i) Bc[i] -= sv * vbuf[buf][i];
                 }
-                double u[QB];
-#pragma unroll
-                for (int pp = 0; pp < QB; ++pp) {
-                    double acc = 0.0;
-                    for (int c = 0; c <= pp && c < jb; ++c) acc += Tm[c * QB + pp] * w[c];
-                    u[pp] = pp < jb ? acc : 0.0;
-                }
-                for (int i = j0; i < rows; ++i) {
-                    const double* yr = A + (int64_t)i * m + j0;
-                    double dd = 0.0;
-#pragma unroll
-                    for (int c = 0; c < QB; ++c) {
-                        const double y = c < jb ? (i > j0 + c ? yr[c] : (i == j0 + c ? 1.0 : 0.0)) : 0.0;
-                        dd += y * u[c];
-                    }
-                    A[(int64_t)i * m + k] -= dd;
-                }
+            };
+            double ra = rload(0), rb = rload(1), rc = rload(2), rd = rload(3);
+            for (int j = 0; j < m; j += 4) {
+                reflect(j, ra);
+                ra = rload(j + 4);
+                if (j + 1 < m) reflect(j + 1, rb);
+                rb = rload(j + 5);
+                if (j + 2 < m) reflect(j + 2, rc);
+                rc = rload(j + 6);
+                if (j + 3 < m) reflect(j + 3, rd);
+                rd = rload(j + 7);
             }
             __syncthreads();
         }
-        }  // pieces
-        // write R (upper triangle, zeros below)
-        for (int64_t e = threadIdx.x; e < (int64_t)m * m; e += blockDim.x) {
-            const int r = (int)(e / m), k = (int)(e % m);
-            out[(J.out_off + (int64_t)c * m + r) * m + k] = (k >= r && r < chunk_rows) ? A[(int64_t)r * m + k] : 0.0;
-        }
-        __syncthreads();
     }
 }
 
@@ -725,30 +623,26 @@ void launch_factor_plane(const Ctx& c, int t, double* Lf, double* Df, int* flags
     k_factor_plane<<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S, c.A8, Lf, Df, flags);
 }
 
-void launch_factor_ring(const Ctx& c, int t, double* ring, int64_t nring, double* samples, void* F, bool f32,
-                        int* flags, hipStream_t st) {
+void launch_factor_ring(const Ctx& c, int t, double* ring, int64_t nring, double* samples, double* asamples,
+                        void* F, bool f32, int* flags, hipStream_t st) {
     if (f32)
         k_factor_ring<float><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S,
-                                                                  c.A8, ring, nring, samples, (float*)F, flags);
+                                                                  c.A8, ring, nring, samples, asamples, (float*)F,
+                                                                  flags);
     else
         k_factor_ring<double><<<c.nblocks * c.groups, 64, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, t, c.S,
-                                                                   c.A8, ring, nring, samples, (double*)F, flags);
+                                                                   c.A8, ring, nring, samples, asamples, (double*)F,
+                                                                   flags);
 }
 
 void launch_transpose(const Ctx& c, const double* Lf, const double* Df, double* Lb, hipStream_t st) {
     k_transpose_factors<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, Lf, Df, Lb);
 }
 
-void launch_gather_a_samples(const Ctx& c, double* samples, hipStream_t st) {
-    k_gather_a_samples<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.S, c.A8,
-                                                             samples);
-}
-
-void launch_qr_chunks(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, int chunk_rows,
-                      int run_pieces, const double* samples, const double* in, double* out, double* scratch, int grid,
-                      int nchunks, hipStream_t st) {
-    k_qr_chunks<<<grid, 256, (QB + QB * QB + 4 * QB * QB) * sizeof(double), st>>>(
-        c.tets, jobs, njobs, level0, m, chunk_rows, run_pieces, samples, in, out, scratch, nchunks);
+void launch_qr_stream(const Ctx& c, const QrJob* jobs, int njobs, int level0, int m, const double* samples,
+                      const double* in, double* out, int grid, int nruns, hipStream_t st) {
+    const int threads = (m + 63) / 64 * 64;
+    k_qr_stream<<<grid, threads, 0, st>>>(c.tets, jobs, njobs, level0, m, samples, in, out, nruns);
 }
 
 void launch_qr_solve(const QrJob* jobs, int njobs, int m, const double* R, double* coef, int* flags, hipStream_t st) {

@@ -73,3 +73,26 @@ def test_surrogate_setup_holds_no_factor_array(torch, pkg, variant, boundary):
     # what the stored variant holds beyond the surrogate handle is at least its
     # factor and weight arrays
     assert sres - resident >= 64 * n_unknowns
+
+
+def test_surrogate_operator_setup_forms_no_stencil_array(torch, pkg):
+    # with the surrogate operator the residual evaluates A from its own fitted
+    # polynomials, so no stencil array is assembled at any point of the setup
+    # (the ring kernel computes each row on the fly and samples it), and the
+    # handle keeps only vectors and per-row tables
+    t = W.make_tet(29, 8, *W.KAPPA_SIN, jitter=0.15)
+    out = {}
+    for a_mode in (pkg.A_EXACT, pkg.A_SURROGATE):
+        sm = pkg.Smoother([t], pkg.SURR_F32, degree=4, stride=4, tile=(16, 32), a_mode=a_mode)
+        out[a_mode] = sm.setup_memory + (sm.n_total,)
+        sm.close()
+    st = pkg.Smoother([t], pkg.STORED_F64, tile=(16, 32))
+    speak, sres = st.setup_memory
+    (ep, er, N), (mp, mr, _) = out[pkg.A_EXACT], out[pkg.A_SURROGATE]
+    print("[memory] level 8 bytes per unknown: stored resident %.1f peak %.1f; FP32 surrogate, exact operator "
+          "resident %.1f peak %.1f; surrogate operator resident %.1f peak %.1f (stored / matrix-free %.1fx)"
+          % (sres / N, speak / N, er / N, ep / N, mr / N, mp / N, sres / mr))
+    # the assembled stencil alone is 64 bytes per stream slot (at least 64 per unknown)
+    assert er - mr >= 64 * N
+    assert mp - mr < 16 * N
+    assert sres > 4 * mr
