@@ -531,6 +531,12 @@ def test_maximum_level_10(torch, pkg):
     assert O.num_interior(10) == 177_910_271
     sm = pkg.Smoother([t], pkg.SURR_F32, degree=4, stride=4, tile=(16, 16))
     assert sm.n_total == O.num_interior(10)
+    # the setup's factorisation (a ring of four hyperplanes), samples and fit
+    # add at most a few bytes per unknown to what the handle keeps
+    peak, resident = sm.setup_memory
+    print("[memory] level 10 FP32 surrogate: resident %.1f B/unknown, setup peak %.1f B/unknown"
+          % (resident / sm.n_total, peak / sm.n_total))
+    assert peak - resident < 8 * sm.n_total
     b = torch.tensor(t.rhs(), device="cuda")
     x = torch.zeros_like(b)
     rel1, _ = sm.smooth(x, b, 1, want_relres=True)
