@@ -336,12 +336,14 @@ def _cpu_worker(k):
 
 
 def host_cores():
-    """Cores this process may run on (the machine's CPU share), at most 16."""
+    """Cores this process may run on, at most 8: forked workers inherit the
+    parent's open GPU device handles, and processes holding a GPU are a
+    limited resource on shared hosts."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(16, n))
+    return max(1, min(8, n))
 
 
 def cpu_baseline(wl, variant, budget_s=12.0, sample_level=7):
