@@ -31,7 +31,7 @@ __device__ double kappa_at(const TetDev& T, double X, double Y, double Z) {
 // seven lower weights (entries whose
 // neighbour is on the macro boundary are stored as 0: the restricted matrix
 // drops them), slot order [c, w, s, se, bnw, bn, bc, be].
-__global__ void k_assemble(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+__global__ void __launch_bounds__(256) k_assemble(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                            const LaneDev* __restrict__ lanes, int lpb, int groups, int nblocks, int64_t S, double* __restrict__ A8,
                            double* __restrict__ Afull /* optional [15][S] */) {
     int b, lane;
@@ -207,7 +207,7 @@ __device__ __forceinline__ void put_samples(const TetDev& T, int x, int y, int z
 // row is computed here, as the assembly would, and its samples (A^p_d, A^p_c)
 // go to asamples: then the whole setup holds no O(h^-3) array.
 template <typename FT>
-__global__ void k_factor_ring(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+__global__ void __launch_bounds__(64) k_factor_ring(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                               const LaneDev* __restrict__ lanes, int lpb, int groups, int t_glob, int64_t S,
                               const double* __restrict__ A8, double* __restrict__ ring, int64_t nring,
                               double* __restrict__ samples, double* __restrict__ asamples, FT* __restrict__ F,
@@ -389,9 +389,11 @@ __global__ void __launch_bounds__(QR_MAXM) k_qr_stream(const TetDev* __restrict_
             auto reflect = [&](int j, double rjk) {
                 const int buf = j & 1;
                 if (k == j) {
-                    double sg = 0.0;
+                    // four partial sums: the chain is on the critical path of every reflector
+                    double sp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int i = 0; i < QR_ROWS; ++i) sg += Bc[i] * Bc[i];
+                    for (int i = 0; i < QR_ROWS; ++i) sp[i & 3] += Bc[i] * Bc[i];
+                    const double sg = (sp[0] + sp[1]) + (sp[2] + sp[3]);
                     double tau = 0.0;
                     if (sg != 0.0) {  // else the column is already reduced: H = I
                         const double alpha = rjk;
@@ -408,10 +410,10 @@ __global__ void __launch_bounds__(QR_MAXM) k_qr_stream(const TetDev* __restrict_
                 lds_barrier();  // v and tau of reflector j; R and B stay private to their threads
                 const double tau = taus[buf];
                 if (col && k > j && tau != 0.0) {
-                    double sv = rjk;
+                    double sp[4] = {rjk, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int i = 0; i < QR_ROWS; ++i) sv += vbuf[buf][i] * Bc[i];
-                    sv *= tau;
+                    for (int i = 0; i < QR_ROWS; ++i) sp[i & 3] += vbuf[buf][i] * Bc[i];
+                    const double sv = ((sp[0] + sp[1]) + (sp[2] + sp[3])) * tau;
                     R[(int64_t)j * m + k] = rjk - sv;
 #pragma unroll
                     for (int i = 0; i < QR_ROWS; ++i) Bc[i] -= sv * vbuf[buf][i];
