@@ -48,7 +48,7 @@ __device__ inline void perm_of(int k, int seq[4]) {
 // The stencil equations are swept in the order bc, s, bnw, be, w, bn, se,
 // then c, from L_c = D_c = 1 and L_d = 0, until no value moves by more than
 // 1e-15 (relative for D).
-__global__ void k_lfa_stencils(const double* __restrict__ verts, int64_t vstride, int ntets,
+__global__ void __launch_bounds__(64) k_lfa_stencils(const double* __restrict__ verts, int64_t vstride, int ntets,
                                double* __restrict__ rec) {
     const int id = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (id >= ntets * LFA_PERMS) return;

@@ -471,7 +471,7 @@ __global__ void k_qr_solve(const QrJob* __restrict__ jobs, int njobs, int m, con
 //   forward table  [7][NC]: L_d at (x, y, z)                 (d in D_l)
 //   backward table [8][NC]: 1/D at (x, y, z), then L_d at p - d
 // Row record layout: [xm, 1/hw, fwd 7*NC, bwd 8*NC].
-__global__ void k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
+__global__ void __launch_bounds__(128) k_row_tables(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                              const LaneDev* __restrict__ lanes, int lpb, int groups, int nslots, const double* __restrict__ coef,
                              int NC, double* __restrict__ tab, float* __restrict__ tab32) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
