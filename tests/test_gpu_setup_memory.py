@@ -96,3 +96,15 @@ def test_surrogate_operator_setup_forms_no_stencil_array(torch, pkg):
     assert er - mr >= 64 * N
     assert mp - mr < 16 * N
     assert sres > 4 * mr
+
+
+def test_setup_memory_of_an_autotuned_handle(torch, pkg):
+    # the autotuner's timing handles are set up and freed inside the same
+    # call: they count towards the peak, never towards what the handle keeps
+    t = W.make_tet(31, 7, *W.KAPPA_SIN, jitter=0.15)
+    auto = pkg.Smoother([t], pkg.SURR_F32, degree=4, stride=4)
+    fixed = pkg.Smoother([t], pkg.SURR_F32, degree=4, stride=4, tile=auto.tile)
+    (pa, ra), (pf, rf) = auto.setup_memory, fixed.setup_memory
+    print("[memory] level 7 autotuned %s: peak %d resident %d; fixed tile: peak %d resident %d" % (auto.tile, pa, ra, pf, rf))
+    assert ra == rf > 0
+    assert pa >= pf >= rf
