@@ -233,7 +233,7 @@ int hip_fail(hipError_t e, const char* what, int line) {
         if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__); \
     } while (0)
 
-// Sample sets S_d as lattice simplices of side M (see the sampling kernel).
+// Sample sets S_d as lattice simplices of side M (see put_samples in the setup kernels).
 int sample_side(int n, int fit, int stride) {
     static const int d[8][3] = {{-1, 0, 0}, {0, -1, 0}, {1, -1, 0}, {-1, 1, -1},
                                 {0, 1, -1}, {0, 0, -1}, {1, 0, -1}, {0, 0, 0}};
