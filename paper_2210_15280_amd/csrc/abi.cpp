@@ -22,6 +22,7 @@
 #include "sweep_kernels.h"
 #include "krylov_kernels.h"
 #include "lfa_kernels.h"
+#include "residual_stage.h"
 
 using namespace ilu;
 
@@ -859,6 +860,105 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
 }
 
 
+// The LDS-staged residual of BV x BW blocks: every load address of every
+// slice (own rows, halo rows, b; the zero slot at 0 for points outside the
+// lattice) lies in the streams, and every value an active point reads from an
+// LDS cell was staged from the address k_residual reads it from, or both
+// addresses are zero slots.
+template <int BV, int BW>
+int64_t check_residual_lds(ilu_handle_t h, const std::vector<int32_t>& owner) {
+    using G = RlGeo<BV, BW>;
+    constexpr int NT = G::NT;
+    const int64_t S = h->S;
+    int64_t bad = 0;
+    auto zero_slot = [&](int64_t q) { return q >= 0 && q < S && owner[q] == -1; };
+    struct Src {
+        int64_t rp = 0;
+        RlRow row{0, 0};
+        int arr = -1;
+    };
+    std::vector<Src> xs(G::XC), as(G::AC);
+    for (size_t b = 0; b < h->blocks.size(); ++b) {
+        const BlockDev& B = h->blocks[b];
+        const LaneDev* Lb = &h->lanes[b * NT];
+        const int n = h->tets[B.tet].n;
+        for (int l = 0; l < NT; ++l) {
+            const Src own{Lb[l].rp[R_SELF], rl_row(n, Lb[l].v, Lb[l].w), -1};
+            xs[l] = own;
+            for (int a = 2; a < 8; ++a) {
+                as[(a - 2) * NT + l] = own;
+                as[(a - 2) * NT + l].arr = a;
+            }
+        }
+        for (int j = 0; j < G::NH; ++j) {
+            const RlHalo o = rl_halo<BV, BW>(j);
+            int sv = 0, sw = 0;
+            lane_rc(o.src, BV, &sv, &sw);
+            const Src sr{Lb[o.src].rp[o.slot],
+                         rl_row(n, B.V0 + sv + rl_slot_dv(o.slot), B.W0 + sw + rl_slot_dw(o.slot)), o.arr};
+            if (o.arr < 0) xs[o.dst] = sr;
+            else as[o.dst] = sr;
+        }
+        auto addr = [&](const Src& sr, int T) { return rl_active(sr.row, T) ? sr.rp + (int64_t)NT * T : 0; };
+        for (int t0 = B.tb; t0 <= B.te; t0 += RES_T) {
+            const int t1 = std::min(B.te + 1, t0 + RES_T), ucap = t1 + 2;
+            // loads: slices t0 - 3 .. ucap of x and the arrays, b of t0 - 6 .. ucap
+            for (int T = t0 - 3; T <= ucap; ++T) {
+                for (int c = 0; c < G::XC; ++c) {
+                    const int64_t q = addr(xs[c], T);
+                    bad += q < 0 || q >= S;
+                }
+                for (int c = 0; c < G::AC; ++c) {
+                    const int64_t q = addr(as[c], T);
+                    bad += q < 0 || q >= S;
+                }
+            }
+            for (int l = 0; l < NT; ++l)
+                for (int u = t0 - 6; u <= ucap; ++u) {
+                    const int64_t q = addr(xs[l], u);
+                    bad += q < 0 || q >= S;
+                }
+            // the values of every active point
+            for (int l = 0; l < NT; ++l) {
+                const LaneDev& L = Lb[l];
+                if (L.v == 0) continue;
+                int vl = 0, wl = 0;
+                lane_rc(l, BV, &vl, &wl);
+                for (int t = t0; t < t1; ++t) {
+                    const int xx = t - 2 * L.v - L.w;
+                    if (xx < 1 || xx > n - 1 - L.v) continue;
+                    bad += !rl_active(xs[l].row, t);
+                    for (int s = 0; s < NLOW; ++s) {
+                        int xl = 0, xu = 0, au = 0;
+                        rl_cells<BV, BW>(vl, wl, s, &xl, &xu, &au);
+                        const int64_t ql = L.rp[low_row(s)] + (int64_t)NT * (t + low_dt(s));
+                        const int64_t qu = L.rp[up_row(s)] + (int64_t)NT * (t + up_dt(s));
+                        const int64_t sl = addr(xs[xl], t + low_dt(s)), su = addr(xs[xu], t + up_dt(s));
+                        bad += xs[xl].arr != -1 || xs[xu].arr != -1;
+                        bad += sl != ql && !(zero_slot(sl) && zero_slot(ql));
+                        bad += su != qu && !(zero_slot(su) && zero_slot(qu));
+                        // upper weight: array 1 of the own row from registers (s = 0),
+                        // else the LDS cell of the upper neighbour; lower weight of
+                        // s >= 1: the own row's cell of array 1 + s
+                        int64_t sa = 0;
+                        if (s == 0) {
+                            sa = addr(xs[l], t + up_dt(s));
+                            bad += au != -1;
+                        } else {
+                            sa = addr(as[au], t + up_dt(s));
+                            const Src& lo = as[(s - 1) * NT + l];
+                            bad += as[au].arr != 1 + s || lo.arr != 1 + s;
+                            bad += addr(lo, t) != L.rp[R_SELF] + (int64_t)NT * t;
+                        }
+                        bad += sa != qu && !(zero_slot(sa) && zero_slot(qu));
+                    }
+                }
+            }
+        }
+    }
+    return bad;
+}
+
 // Replays, on the host, every global index the kernels form and checks that
 // it stays inside the streams and addresses the intended point (or a slot that
 // is never written, which holds zero).  Returns the number of violations.
@@ -973,6 +1073,8 @@ int64_t check_layout(ilu_handle_t h) {
             }
         }
     }
+    if (bv == 8 && bw == 8) bad += check_residual_lds<8, 8>(h, owner);
+    if (bv == 16 && bw == 16) bad += check_residual_lds<16, 16>(h, owner);
     // dataflow exchange: replay the outgoing-entry stores of every block and
     // hyperplane with the kernels' own index functions, then check that every
     // halo read lands on a word written by the producer lane that owns the

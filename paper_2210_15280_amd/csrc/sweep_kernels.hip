@@ -5,6 +5,7 @@
 
 #include "kernels_common.h"
 #include "sweep_kernels.h"
+#include "residual_stage.h"
 #include "tagged_device.h"
 
 namespace ilu {
@@ -87,6 +88,201 @@ __global__ void __launch_bounds__(256) k_residual(const TetDev* __restrict__ tet
         __syncthreads();
     }
     if (threadIdx.x == 0 && partial) partial[it.id] = red[0];
+}
+
+// ------------------------------------------------------ LDS-staged residual
+
+// Raw buffer stores (gfx9 buffer resource: no swizzle, byte range rbytes): a
+// lane whose offset is RL_DROP, beyond every range, writes nothing.
+constexpr uint32_t RL_DROP = 0xFFFFFFF0u;
+constexpr int RL_RSRC_WORD3 = 0x00020000;
+typedef unsigned int rl_u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_dropped(float v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), rs, (int)off, 0, 2);  // aux 2: nontemporal
+}
+__device__ __forceinline__ void store_dropped(double v, __amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(rl_u32x2, v), rs, (int)off, 0, 2);
+}
+
+//
+// The same r = b - A x as k_residual (the values and the order of the
+// products of residual_point), reading every value from memory once: the
+// workgroup owns one block of BV x BW rows (one thread per row) and walks
+// RES_T of its hyperplanes.  A point at t reads x at t - 3 .. t + 3 (LDS ring
+// of hyperplane slices: the block's rows and the one-row halo on all four
+// sides) and arrays 2..7 of the stencil at t .. t + 3 (LDS ring: the block's
+// rows and, at the upper halo rows, the upper weights the block's edge rows
+// read there); arrays 0 and 1, which only the own row reads, and b come from
+// registers, loaded for the step itself.  Step t stages the slices of t + 3,
+// loaded during step t - RL_P, so RL_P slice loads are in flight while the
+// workgroup computes.  A second barrier after the arithmetic lets the rings
+// hold exactly the slices in use (7 of x, 4 of the stencil), so that two
+// 256-row workgroups fit in the LDS of a CU.  Halo rows are reached through
+// the row pointers of the block's edge lanes.  Every value a point uses comes
+// from the address k_residual forms for it, or from the zero slot at 0 where
+// that address holds a point outside the lattice (the host layout check
+// replays these indices).
+template <typename RT, bool SUB, int BV, int BW>
+__global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __restrict__ tets,
+                                                         const BlockDev* __restrict__ blocks,
+                                                         const LaneDev* __restrict__ lanes, int nblocks, int groups,
+                                                         int64_t S, const double* __restrict__ A8,
+                                                         const double* __restrict__ x, const double* __restrict__ b,
+                                                         RT* __restrict__ r, uint32_t rbytes,
+                                                         double* __restrict__ partial) {
+    using G = RlGeo<BV, BW>;
+    constexpr int NT = G::NT, XC = G::XC, AC = G::AC, RX = G::RX, RA = G::RA, HJ = G::HJ;
+    static_assert(RL_P == 4, "four register slice groups");
+    // r through a buffer resource of rbytes bytes: stores at RL_DROP are dropped
+    const __amdgpu_buffer_rsrc_t rbuf = __builtin_amdgcn_make_buffer_rsrc(r, 0, (int)rbytes, RL_RSRC_WORD3);
+    __shared__ double lds[G::LDS];
+    double* const LX = lds;
+    double* const LA = lds + RX * XC;
+    const int blk = (int)blockIdx.x, chunk = (int)blockIdx.y, l = (int)threadIdx.x;
+    double acc2 = 0.0;
+    const BlockDev& B = blocks[blk];
+    const int t0 = B.tb + chunk * RES_T;
+    if (t0 <= B.te) {
+        const int t1 = min(B.te + 1, t0 + RES_T);
+        const int64_t lpb = NT;
+        const LaneDev& Ln = lanes[(int64_t)blk * NT + l];
+        const int n = tets[B.tet].n;
+        int vl = 0, wl = 0;
+        lane_rc(l, BV, &vl, &wl);
+        const int64_t rs = Ln.rp[R_SELF];
+        const RlRow own = rl_row(n, Ln.v, Ln.w);  // v = 0 (no row) is outside the lattice
+        // this thread's halo loads of a slice: job j = l + k NT.  Branch-free,
+        // so that the compiler's wait counts stay exact: a job without a cell
+        // loads the zero slot at 0 and writes it to this thread's own x cell,
+        // which the thread writes again right after.
+        const double* hsrc[HJ];  // x or the halo row's stencil array
+        int64_t hp[HJ];          // row pointer of the halo row
+        RlRow hrow[HJ];          // activity of the halo row
+        int hcell[HJ];           // LDS cell inside the slice
+        int hkind[HJ];           // 0: x, 1: stencil, 2: none
+#pragma unroll
+        for (int k = 0; k < HJ; ++k) {
+            const RlHalo o = rl_halo<BV, BW>(l + k * NT);
+            hsrc[k] = o.arr < 0 ? x : A8 + (int64_t)o.arr * S;
+            hcell[k] = o.dst < 0 ? l : o.dst;
+            hkind[k] = o.dst < 0 ? 2 : o.arr < 0 ? 0 : 1;
+            hp[k] = 0;
+            hrow[k] = RlRow{0, 0};
+            if (o.dst >= 0) {
+                int sv = 0, sw = 0;
+                lane_rc(o.src, BV, &sv, &sw);
+                hp[k] = lanes[(int64_t)blk * NT + o.src].rp[o.slot];
+                hrow[k] = rl_row(n, B.V0 + sv + rl_slot_dv(o.slot), B.W0 + sw + rl_slot_dw(o.slot));
+            }
+        }
+        // LDS cells of the point's neighbours
+        int xl[NLOW], xu[NLOW], au[NLOW];
+#pragma unroll
+        for (int s = 0; s < NLOW; ++s) rl_cells<BV, BW>(vl, wl, s, &xl[s], &xu[s], &au[s]);
+        // the loads of step u: x and arrays 2..7 of slice u + 3 (staged in LDS),
+        // arrays 0, 1 and b of slice u (used by step u itself), the halo of u + 3
+        struct Regs {
+            double xo, an[6], a01[2], bo, h[HJ];
+        };
+        const int ucap = t1 + 2;  // the last slice the chunk reads
+        // A slot of a point outside the lattice holds zero: its load reads the
+        // zero region at 0 instead (cache resident), so only interior points
+        // cost memory traffic.
+        auto load = [&](int u, Regs& R) {
+            const int ux = min(u + 3, ucap), uo = min(u, ucap);
+            const int64_t ix = rl_active(own, ux) ? rs + lpb * ux : 0;
+            const int64_t io = rl_active(own, uo) ? rs + lpb * uo : 0;
+            R.xo = x[ix];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) R.an[a] = A8[(int64_t)(2 + a) * S + ix];
+            R.a01[0] = A8[io];
+            R.a01[1] = A8[S + io];
+            R.bo = SUB ? b[io] : 0.0;
+#pragma unroll
+            for (int k = 0; k < HJ; ++k) R.h[k] = hsrc[k][rl_active(hrow[k], ux) ? hp[k] + lpb * ux : 0];
+        };
+        // stage slice u + 3: the halo first, so that a job without a cell is
+        // overwritten by the thread's own x
+        auto put = [&](int u, const Regs& R) {
+            double* lx = LX + ((u + 3) % RX) * XC;
+            double* la = LA + ((u + 3) % RA) * AC;
+#pragma unroll
+            for (int k = 0; k < HJ; ++k) (hkind[k] == 1 ? la : lx)[hcell[k]] = R.h[k];
+            lx[l] = R.xo;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) la[a * NT + l] = R.an[a];
+        };
+        // x of t0-3 .. t0+2 and arrays 2..7 of t0 .. t0+2 (the three earlier
+        // stencil slices are overwritten before they are read)
+        for (int u = t0 - 6; u < t0; ++u) {
+            Regs R;
+            load(u, R);
+            put(u, R);
+        }
+        Regs R[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) load(t0 + k, R[k]);
+        // every step runs (loads, stores to LDS and the barrier), points beyond
+        // the chunk are not computed: a loop without conditional steps keeps
+        // RL_P slice loads in flight across its back edge
+        auto step = [&](int t, int k) {
+            Regs& Rk = R[k];
+            put(t, Rk);
+            const double a0 = Rk.a01[0], a1 = Rk.a01[1], a1u = R[(k + 1) & 3].a01[1], bt = Rk.bo;
+            lds_barrier();
+            // branch-free (a point outside the chunk or the lattice computes on
+            // defined LDS values and its store is dropped as out of range), so
+            // that the wait counts do not depend on the path
+            {
+                const bool act = t < t1 && rl_active(own, t);
+                double a[15], xv[15];
+                a[0] = a0;
+                const double* at = LA + (t % RA) * AC;
+                xv[0] = LX[(t % RX) * XC + l];
+                a[1] = a1;
+                a[2] = a1u;
+                xv[1] = LX[((t + low_dt(0)) % RX) * XC + xl[0]];
+                xv[2] = LX[((t + up_dt(0)) % RX) * XC + xu[0]];
+#pragma unroll
+                for (int s = 1; s < NLOW; ++s) {
+                    a[1 + 2 * s] = at[(s - 1) * NT + l];
+                    xv[1 + 2 * s] = LX[((t + low_dt(s)) % RX) * XC + xl[s]];
+                    a[2 + 2 * s] = LA[((t + up_dt(s)) % RA) * AC + au[s]];
+                    xv[2 + 2 * s] = LX[((t + up_dt(s)) % RX) * XC + xu[s]];
+                }
+                // the order and the fused multiply-adds of residual_point
+                double acc = a[0] * xv[0];
+#pragma unroll
+                for (int q = 1; q < 15; ++q) acc = fma(a[q], xv[q], acc);
+                const double rv = SUB ? bt - acc : acc;
+                store_dropped((RT)rv, rbuf, act ? (uint32_t)((rs + lpb * t) * (int64_t)sizeof(RT)) : RL_DROP);
+                acc2 += act ? rv * rv : 0.0;
+            }
+            // the next step overwrites the slices of t - 3 (x) and t (stencil)
+            lds_barrier();
+            // the loads of step t + RL_P, issued once this step's own registers
+            // are consumed (so that no loaded register is copied)
+            load(t + RL_P, Rk);
+        };
+        for (int t = t0; t < t1; t += RL_P) {
+            step(t, 0);
+            step(t + 1, 1);
+            step(t + 2, 2);
+            step(t + 3, 3);
+        }
+    }
+    // the partial sums (the LDS rings are free once every wave is here)
+    double* const red = lds;
+    __syncthreads();
+    red[l] = acc2;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if (l < o) red[l] += red[l + o];
+        __syncthreads();
+    }
+    // the partial-sum layout of k_residual: the block's first lane group holds
+    // the sum, its other groups 0
+    if (partial && l < groups) partial[((int64_t)chunk * nblocks + blk) * groups + l] = l == 0 ? red[0] : 0.0;
 }
 
 // Residual for a forward sweep running at the same time: tagged entries
@@ -470,10 +666,29 @@ void launch_residual_sa_nc(const Ctx& c, const TT* tab, const double* x, const d
 }
 }  // namespace
 
+namespace {
+template <int BV, int BW>
+void launch_residual_lds(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract,
+                         double* partial, hipStream_t st) {
+    const dim3 grid((unsigned)c.nblocks, (unsigned)c.res_chunks);
+    const uint32_t rb = (uint32_t)(c.S * (f32 ? 4 : 8));
+#define ILU_RL_ARGS c.tets, c.blocks, c.lanes, c.nblocks, c.groups, c.S, c.A8, x, b
+    if (f32 && subtract) k_residual_lds<float, true, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, partial);
+    else if (f32) k_residual_lds<float, false, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, partial);
+    else if (subtract) k_residual_lds<double, true, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (double*)r, rb, partial);
+    else k_residual_lds<double, false, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (double*)r, rb, partial);
+#undef ILU_RL_ARGS
+}
+}  // namespace
+
 void launch_residual(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract, double* partial,
                      hipStream_t st) {
     if (c.tabA32) return launch_residual_sa_nc<float>(c, c.tabA32, x, b, r, f32, subtract, partial, st);
     if (c.tabA64) return launch_residual_sa_nc<double>(c, c.tabA64, x, b, r, f32, subtract, partial, st);
+    // the LDS-staged kernel addresses r by 32-bit byte offsets below RL_DROP
+    const bool lds_ok = c.res_lds && c.S * 8 < (int64_t)RL_DROP;
+    if (lds_ok && c.bv == 8 && c.bw == 8) return launch_residual_lds<8, 8>(c, x, b, r, f32, subtract, partial, st);
+    if (lds_ok && c.bv == 16 && c.bw == 16) return launch_residual_lds<16, 16>(c, x, b, r, f32, subtract, partial, st);
     const dim3 grid((unsigned)(c.nblocks * c.groups), (unsigned)c.res_chunks);
 #define ILU_RES_ARGS c.tets, c.blocks, c.lanes, c.lpb, c.groups, c.nblocks, c.S, c.A8, x, b
     if (f32 && subtract) k_residual<float, true><<<grid, 256, 0, st>>>(ILU_RES_ARGS, (float*)r, partial);
