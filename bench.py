@@ -225,6 +225,15 @@ def surrogate_quality(torch, stored, surr, tet_level):
     return out
 
 
+def residual_kernel(res, variant):
+    """The sequential residual: with the surrogate operator k_residual_sa;
+    with the stencil arrays LDS-staged on 8x8 and 16x16 blocks, point-parallel
+    on the other block shapes."""
+    if variant.endswith("_sa"):
+        return "k_residual_sa"
+    return "k_residual_lds" if tuple(res["tile"]) in ((8, 8), (16, 16)) else "k_residual"
+
+
 def roofline(res, variant, dg, workload):
     """The dominant kernel against the HBM roofline.  Sequential residual:
     the slowest of the three kernels.  Overlapped residual: the residual
@@ -236,7 +245,7 @@ def roofline(res, variant, dg, workload):
     km = res["kernel_ms"]
     ovl = res.get("overlap") == "overlapped"
     dom = "residual" if ovl else max(km, key=km.get)
-    name = "k_residual_tag" if ovl else KERNEL_NAMES[dom]
+    name = "k_residual_tag" if ovl else residual_kernel(res, variant) if dom == "residual" else KERNEL_NAMES[dom]
     n = res["n_dof"]
     t = km[dom] * 1e-3
     gbs = bpd[dom] * n / t / 1e9

@@ -37,7 +37,7 @@ def test_byte_model_per_dof(variant, res, fwd, bwd):
 
 def test_roofline_reports_the_slowest_kernel_with_algorithmic_bytes():
     n = 22_108_415
-    res = {"kernel_ms": {"forward": 0.49, "backward": 0.535, "residual": 0.70}, "n_dof": n}
+    res = {"kernel_ms": {"forward": 0.49, "backward": 0.535, "residual": 0.70}, "n_dof": n, "tile": [16, 32]}
     r = bench.roofline(res, "surr_f32", 6, "no_such_workload")
     assert r["kernel"] == "k_residual" and r["bound"] == "hbm" and r["unit"] == "GB/s"
     assert r["bytes_per_dof"] == 84 and r["algorithmic_bytes_per_launch"] == 84 * n
@@ -45,6 +45,12 @@ def test_roofline_reports_the_slowest_kernel_with_algorithmic_bytes():
     assert math.isclose(r["achieved"], gbs, rel_tol=1e-3)
     assert r["peak"] == 8000.0 and math.isclose(r["frac"], gbs / 8000.0, rel_tol=1e-3)
     assert r["traffic"] is None  # no counters for this workload
+    # the residual kernel that runs: LDS-staged on 8x8 and 16x16 blocks, with
+    # the surrogate operator the surrogate residual
+    for tile in ([8, 8], [16, 16]):
+        res["tile"] = tile
+        assert bench.roofline(res, "surr_f32", 6, "no_such_workload")["kernel"] == "k_residual_lds"
+    assert bench.roofline(res, "surr_f32_sa", 6, "no_such_workload")["kernel"] == "k_residual_sa"
     res["kernel_ms"]["backward"] = 0.9
     assert bench.roofline(res, "surr_f32", 6, "no_such_workload")["kernel"] == "k_bwd_flow"
 
