@@ -860,11 +860,11 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
 }
 
 
-// The LDS-staged residual of BV x BW blocks: every load address of every
-// slice (own rows, halo rows, b; the zero slot at 0 for points outside the
-// lattice) lies in the streams, and every value an active point reads from an
-// LDS cell was staged from the address k_residual reads it from, or both
-// addresses are zero slots.
+// The LDS-staged residual of BV x BW blocks (both of its work splits): every
+// load address of every slice (own rows, halo rows, b; the zero slot at 0 for
+// points outside the lattice) lies in the streams, and every value an active
+// point reads from an LDS cell was staged from the address k_residual reads it
+// from, or both addresses are zero slots.
 template <int BV, int BW>
 int64_t check_residual_lds(ilu_handle_t h, const std::vector<int32_t>& owner) {
     using G = RlGeo<BV, BW>;
@@ -900,8 +900,14 @@ int64_t check_residual_lds(ilu_handle_t h, const std::vector<int32_t>& owner) {
             else as[o.dst] = sr;
         }
         auto addr = [&](const Src& sr, int T) { return rl_active(sr.row, T) ? sr.rp + (int64_t)NT * T : 0; };
-        for (int t0 = B.tb; t0 <= B.te; t0 += RES_T) {
-            const int t1 = std::min(B.te + 1, t0 + RES_T), ucap = t1 + 2;
+        // the workgroups' hyperplane ranges: chunks of RES_T from the block's
+        // first hyperplane, and the absolute bands of the tagged mode
+        std::vector<std::pair<int, int>> ranges;
+        for (int t0 = B.tb; t0 <= B.te; t0 += RES_T) ranges.push_back({t0, std::min(B.te + 1, t0 + RES_T)});
+        for (int band = B.tb / RES_T; band * RES_T <= B.te; ++band)
+            ranges.push_back({std::max(B.tb, band * RES_T), std::min(B.te + 1, (band + 1) * RES_T)});
+        for (const auto& rg : ranges) {
+            const int t0 = rg.first, t1 = rg.second, ucap = t1 + 2;
             // loads: slices t0 - 3 .. ucap of x and the arrays, b of t0 - 6 .. ucap
             for (int T = t0 - 3; T <= ucap; ++T) {
                 for (int c = 0; c < G::XC; ++c) {

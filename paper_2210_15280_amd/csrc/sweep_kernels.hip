@@ -122,14 +122,21 @@ __device__ __forceinline__ void store_dropped(double v, __amdgpu_buffer_rsrc_t r
 // from the address k_residual forms for it, or from the zero slot at 0 where
 // that address holds a point outside the lattice (the host layout check
 // replays these indices).
-template <typename RT, bool SUB, int BV, int BW>
+//
+// TAG: the residual for a forward sweep running at the same time (as
+// k_residual_tag): workgroup (blk, y) covers the absolute hyperplanes
+// [y RES_T, (y+1) RES_T) of its block, so the grid runs band by band in the
+// order the sweep consumes; r goes out as tagged entries (tag *tagp) and each
+// of the block's lane groups gets its band mark once the workgroup is done.
+template <typename RT, bool SUB, int BV, int BW, bool TAG>
 __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __restrict__ tets,
                                                          const BlockDev* __restrict__ blocks,
                                                          const LaneDev* __restrict__ lanes, int nblocks, int groups,
                                                          int64_t S, const double* __restrict__ A8,
                                                          const double* __restrict__ x, const double* __restrict__ b,
                                                          RT* __restrict__ r, uint32_t rbytes,
-                                                         double* __restrict__ partial) {
+                                                         uint64_t* __restrict__ rt, const int32_t* __restrict__ tagp,
+                                                         uint64_t* __restrict__ rflag, double* __restrict__ partial) {
     using G = RlGeo<BV, BW>;
     constexpr int NT = G::NT, XC = G::XC, AC = G::AC, RX = G::RX, RA = G::RA, HJ = G::HJ;
     static_assert(RL_P == 4, "four register slice groups");
@@ -141,9 +148,10 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
     const int blk = (int)blockIdx.x, chunk = (int)blockIdx.y, l = (int)threadIdx.x;
     double acc2 = 0.0;
     const BlockDev& B = blocks[blk];
-    const int t0 = B.tb + chunk * RES_T;
-    if (t0 <= B.te) {
-        const int t1 = min(B.te + 1, t0 + RES_T);
+    const uint32_t tag = TAG ? (uint32_t)tagp[0] : 0u;
+    const int t0 = TAG ? max(B.tb, chunk * RES_T) : B.tb + chunk * RES_T;
+    const int t1 = min(B.te + 1, TAG ? (chunk + 1) * RES_T : t0 + RES_T);
+    if (t0 < t1) {
         const int64_t lpb = NT;
         const LaneDev& Ln = lanes[(int64_t)blk * NT + l];
         const int n = tets[B.tet].n;
@@ -255,7 +263,11 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
 #pragma unroll
                 for (int q = 1; q < 15; ++q) acc = fma(a[q], xv[q], acc);
                 const double rv = SUB ? bt - acc : acc;
-                store_dropped((RT)rv, rbuf, act ? (uint32_t)((rs + lpb * t) * (int64_t)sizeof(RT)) : RL_DROP);
+                if (TAG) {
+                    if (act) x_put(rt + (rs + lpb * t) * XEnt<RT>::W, (RT)rv, tag);
+                } else {
+                    store_dropped((RT)rv, rbuf, act ? (uint32_t)((rs + lpb * t) * (int64_t)sizeof(RT)) : RL_DROP);
+                }
                 acc2 += act ? rv * rv : 0.0;
             }
             // the next step overwrites the slices of t - 3 (x) and t (stencil)
@@ -274,6 +286,9 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
     // the partial sums (the LDS rings are free once every wave is here)
     double* const red = lds;
     __syncthreads();
+    // the band marks: a pacing hint for the sweep, which relies on the
+    // entries' own tags; no fence (an agent-scope release writes back the L2)
+    if (TAG && l < groups) st_dev(rflag + ((int64_t)blk * groups + l) * gridDim.y + chunk, (uint64_t)tag);
     red[l] = acc2;
     __syncthreads();
     for (int o = NT / 2; o > 0; o >>= 1) {
@@ -673,10 +688,28 @@ void launch_residual_lds(const Ctx& c, const double* x, const double* b, void* r
     const dim3 grid((unsigned)c.nblocks, (unsigned)c.res_chunks);
     const uint32_t rb = (uint32_t)(c.S * (f32 ? 4 : 8));
 #define ILU_RL_ARGS c.tets, c.blocks, c.lanes, c.nblocks, c.groups, c.S, c.A8, x, b
-    if (f32 && subtract) k_residual_lds<float, true, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, partial);
-    else if (f32) k_residual_lds<float, false, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, partial);
-    else if (subtract) k_residual_lds<double, true, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (double*)r, rb, partial);
-    else k_residual_lds<double, false, BV, BW><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (double*)r, rb, partial);
+#define ILU_RL_NOTAG nullptr, nullptr, nullptr, partial
+    if (f32 && subtract)
+        k_residual_lds<float, true, BV, BW, false><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, ILU_RL_NOTAG);
+    else if (f32)
+        k_residual_lds<float, false, BV, BW, false><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, ILU_RL_NOTAG);
+    else if (subtract)
+        k_residual_lds<double, true, BV, BW, false><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (double*)r, rb, ILU_RL_NOTAG);
+    else
+        k_residual_lds<double, false, BV, BW, false><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (double*)r, rb, ILU_RL_NOTAG);
+#undef ILU_RL_NOTAG
+}
+
+template <int BV, int BW>
+void launch_residual_lds_tagged(const Ctx& c, const double* x, const double* b, uint64_t* rt, bool f32,
+                                const int32_t* tagp, uint64_t* rflag, double* partial, hipStream_t st) {
+    const dim3 grid((unsigned)c.nblocks, (unsigned)c.res_bands);
+    if (f32)
+        k_residual_lds<float, true, BV, BW, true><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, nullptr, 0, rt, tagp, rflag,
+                                                                           partial);
+    else
+        k_residual_lds<double, true, BV, BW, true><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, nullptr, 0, rt, tagp, rflag,
+                                                                            partial);
 #undef ILU_RL_ARGS
 }
 }  // namespace
@@ -701,6 +734,10 @@ int64_t res_tag_partials(const Ctx& c) { return (int64_t)c.nblocks * c.groups * 
 
 void launch_residual_tagged(const Ctx& c, const double* x, const double* b, uint64_t* rt, bool f32,
                             const int32_t* tagp, uint64_t* rflag, double* partial, hipStream_t st) {
+    if (c.res_lds && c.bv == 8 && c.bw == 8)
+        return launch_residual_lds_tagged<8, 8>(c, x, b, rt, f32, tagp, rflag, partial, st);
+    if (c.res_lds && c.bv == 16 && c.bw == 16)
+        return launch_residual_lds_tagged<16, 16>(c, x, b, rt, f32, tagp, rflag, partial, st);
     const dim3 grid((unsigned)(c.nblocks * c.groups), (unsigned)c.res_bands);
     if (f32) k_residual_tag<float><<<grid, 256, 0, st>>>(ILU_RES_ARGS, rt, tagp, rflag, partial);
     else k_residual_tag<double><<<grid, 256, 0, st>>>(ILU_RES_ARGS, rt, tagp, rflag, partial);
