@@ -226,18 +226,21 @@ def surrogate_quality(torch, stored, surr, tet_level):
 
 
 def residual_kernel(res, variant):
-    """The sequential residual: with the surrogate operator k_residual_sa;
-    with the stencil arrays LDS-staged on 8x8 and 16x16 blocks, point-parallel
-    on the other block shapes."""
+    """The residual kernel that runs: with the surrogate operator
+    k_residual_sa; with the stencil arrays LDS-staged on 8x8 and 16x16 blocks
+    (sequential or beside the forward sweep), else point-parallel
+    (k_residual, or k_residual_tag beside the sweep)."""
     if variant.endswith("_sa"):
         return "k_residual_sa"
-    return "k_residual_lds" if tuple(res["tile"]) in ((8, 8), (16, 16)) else "k_residual"
+    if tuple(res["tile"]) in ((8, 8), (16, 16)):
+        return "k_residual_lds"
+    return "k_residual_tag" if res.get("overlap") == "overlapped" else "k_residual"
 
 
 def roofline(res, variant, dg, workload):
     """The dominant kernel against the HBM roofline.  Sequential residual:
     the slowest of the three kernels.  Overlapped residual: the residual
-    kernel (k_residual_tag, timed on its own stream): the forward
+    kernel (timed on its own stream): the forward
     substitution beside it waits for its bands, so its time is mostly the
     residual's."""
     bpd = kernel_bytes(variant)
@@ -245,7 +248,7 @@ def roofline(res, variant, dg, workload):
     km = res["kernel_ms"]
     ovl = res.get("overlap") == "overlapped"
     dom = "residual" if ovl else max(km, key=km.get)
-    name = "k_residual_tag" if ovl else residual_kernel(res, variant) if dom == "residual" else KERNEL_NAMES[dom]
+    name = residual_kernel(res, variant) if dom == "residual" else KERNEL_NAMES[dom]
     n = res["n_dof"]
     t = km[dom] * 1e-3
     gbs = bpd[dom] * n / t / 1e9

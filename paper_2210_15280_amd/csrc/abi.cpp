@@ -780,20 +780,35 @@ int setup_sweep_buffers(ilu_handle_t h, hipStream_t st) {
 // Device time (ms) of one sweep (residual, forward and backward substitution)
 // on zero vectors: the sweep kernels have no data-dependent control flow, so
 // the values do not matter.  One warm-up sweep, then the mean of `reps`.
-int time_sweep(ilu_handle_t h, hipStream_t st, int reps, double* ms) {
+int time_sweep(ilu_handle_t h, hipStream_t st, int reps, double* ms, double cutoff_ms) {
     const Ctx c = h->ctx();
     HIPCHK(hipMemsetAsync(h->xs.p, 0, h->xs.bytes, st));
     HIPCHK(hipMemsetAsync(h->bs.p, 0, h->bs.bytes, st));
+    float a = 0;
     for (int k = 0; k <= reps; ++k) {
-        if (k == 1) HIPCHK(hipEventRecord(h->ev[0], st));
+        if (k <= 1) HIPCHK(hipEventRecord(h->ev[0], st));
         if (int e = sweep_res_fwd(h, c, st, nullptr, nullptr)) return e;
         sweep_bwd(h, c, st);
+        if (k == 0 && cutoff_ms > 0.0) {
+            // the untimed first sweep already far slower than the best
+            // configuration so far (a residual kernel that finds no room beside
+            // the sweep): report it without the timed ones
+            HIPCHK(hipEventRecord(h->ev[1], st));
+            HIPCHK(hipEventSynchronize(h->ev[1]));
+            HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+            if (a > cutoff_ms) {
+                reps = 0;
+                break;
+            }
+        }
     }
-    HIPCHK(hipEventRecord(h->ev[1], st));
-    HIPCHK(hipEventSynchronize(h->ev[1]));
-    float a = 0;
-    HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
-    *ms = a / reps;
+    if (reps > 0) {
+        HIPCHK(hipEventRecord(h->ev[1], st));
+        HIPCHK(hipEventSynchronize(h->ev[1]));
+        HIPCHK(hipEventElapsedTime(&a, h->ev[0], h->ev[1]));
+        a /= reps;
+    }
+    *ms = a;
     int32_t fl[4];
     if (int e = read_flags(h, st, fl)) return e;
     return fl[2] ? ILU_EHIP : ILU_OK;
@@ -821,15 +836,15 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
         int rc = setup_impl(tets, ntets, &o, st, h, true);
         const int gmax = h->flow_grid_max;
         struct Cand { int ovl, grid; };
-        Cand cands[5] = {{ILU_OVERLAP_OFF, gmax}, {ILU_OVERLAP_OFF, gmax / 2}, {ILU_OVERLAP_OFF, gmax / 3},
-                         {ILU_OVERLAP_ON, gmax / 2}, {ILU_OVERLAP_ON, gmax / 4}};
+        Cand cands[6] = {{ILU_OVERLAP_OFF, gmax}, {ILU_OVERLAP_OFF, gmax / 2}, {ILU_OVERLAP_OFF, gmax / 3},
+                         {ILU_OVERLAP_ON, gmax}, {ILU_OVERLAP_ON, gmax / 2}, {ILU_OVERLAP_ON, gmax / 4}};
         for (const Cand& cd : cands) {
             if (rc != ILU_OK) break;
             if (cd.grid < 1 || (cd.ovl != ILU_OVERLAP_OFF && !h->ovl_ok)) continue;
             h->flow_grid = cd.grid;
             h->ovl = cd.ovl;
             double ms = 0.0;
-            rc = time_sweep(h, st, 3, &ms);
+            rc = time_sweep(h, st, 3, &ms, best_sh < 0 ? 0.0 : 4.0 * best_ms);
             if (rc == ILU_OK && (best_sh < 0 || ms < best_ms)) {
                 best_sh = si;
                 best_grid = cd.grid;

@@ -103,10 +103,12 @@ def test_overlapped_residual_reporting():
     n = 22_108_415
     wl = W.workload("jit_L9_exp")
     res = {"kernel_ms": {"forward": 1.03, "backward": 0.535, "residual": 0.925}, "n_dof": n, "ms_per_step": 1.6,
-           "overlap": "overlapped"}
+           "overlap": "overlapped", "tile": [16, 32]}
     r = bench.roofline(res, "surr_f32", 6, "no_such_workload")
     # the bandwidth-bound residual, timed on its own stream, not the waiting forward sweep
     assert r["kernel"] == "k_residual_tag" and r["kernel_ms_per_launch"] == 0.925
+    res["tile"] = [16, 16]
+    assert bench.roofline(res, "surr_f32", 6, "no_such_workload")["kernel"] == "k_residual_lds"
     assert math.isclose(r["achieved"], 84 * n / 0.925e-3 / 1e9, rel_tol=1e-3)
     f = bench.latency_floor(res, "surr_f32", wl)
     assert f["t_h_from"] == "backward substitution"
