@@ -41,7 +41,7 @@ def _cases():
     ]
 
 
-@pytest.mark.parametrize("tile", [(8, 8), (16, 32)])
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32)])
 @pytest.mark.parametrize("ti", range(5))
 def test_stencil_assembly_parity(torch, pkg, ti, tile):
     t = _cases()[ti]
@@ -53,6 +53,28 @@ def test_stencil_assembly_parity(torch, pkg, ti, tile):
     x = np.random.default_rng(ti).uniform(-1, 1, P.N)
     y = sm.apply(torch.tensor(x, device="cuda")).cpu().numpy()
     assert _rel(y, P.apply(x)) < 1e-13
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32)])
+def test_stencil_apply_parity_over_many_chunks(torch, pkg, tile):
+    # A x through the residual kernel of each block shape (LDS-staged on 8x8
+    # and 16x16 blocks: several 64-hyperplane chunks per block, ragged last
+    # chunks, halo rows on all four sides, rows outside the lattice) against
+    # the oracle's stencil product, on a batch of three tetrahedra of levels
+    # 5 to 7 that share one stream
+    tets = [W.make_tet(11, 7, *W.KAPPA_EXP, jitter=0.15), W.make_tet(12, 5, *W.KAPPA_SIN, jitter=0.15),
+            W.make_tet(13, 6, *W.KAPPA_EXP, jitter=0.1)]
+    Ps = [O.Problem.from_tet(t) for t in tets]
+    sm = pkg.Smoother(tets, pkg.STORED_F64, tile=tile)
+    assert tuple(sm.tile) == tile
+    rng = np.random.default_rng(7)
+    xs = [rng.uniform(-1, 1, P.N) for P in Ps]
+    y = sm.apply(torch.tensor(np.concatenate(xs), device="cuda")).cpu().numpy()
+    off = 0
+    for P, x in zip(Ps, xs):
+        assert _rel(y[off:off + P.N], P.apply(x)) < 1e-13
+        off += P.N
+    assert off == len(y)
 
 
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32)])
