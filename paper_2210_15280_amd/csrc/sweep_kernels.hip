@@ -220,11 +220,21 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
 #pragma unroll
             for (int a = 0; a < 6; ++a) la[a * NT + l] = R.an[a];
         };
-        // x of t0-3 .. t0+2 and arrays 2..7 of t0 .. t0+2 (the three earlier
-        // stencil slices are overwritten before they are read)
+        // x of t0-3 .. t0+2 and arrays 2..7 of t0 .. t0+2.  Only what the
+        // first steps read is loaded: x alone for the three earlier slices (the
+        // stencil cells of those slots are written but overwritten before they
+        // are read), no weights of arrays 0 and 1 and no b (steps load their own).
         for (int u = t0 - 6; u < t0; ++u) {
             Regs R;
-            load(u, R);
+            const int ux = u + 3;
+            const bool stencil = ux >= t0;
+            const int64_t ix = rl_active(own, ux) ? rs + lpb * ux : 0;
+            R.xo = x[ix];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) R.an[a] = stencil ? A8[(int64_t)(2 + a) * S + ix] : 0.0;
+#pragma unroll
+            for (int k = 0; k < HJ; ++k)
+                R.h[k] = (stencil || hkind[k] != 1) ? hsrc[k][rl_active(hrow[k], ux) ? hp[k] + lpb * ux : 0] : 0.0;
             put(u, R);
         }
         Regs R[4];
