@@ -462,7 +462,7 @@ def main():
                     help="instead of sweeps: time the LFA orientation choice for every tetrahedron of the workload")
     a = ap.parse_args()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(independent tetrahedra would shard across GPUs with no exchange).", file=sys.stderr)
         sys.exit(2)
     import torch
