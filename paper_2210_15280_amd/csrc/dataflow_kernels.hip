@@ -698,8 +698,12 @@ constexpr int U_S64 = 4, D_S64 = 2;              // FP64 surrogate
 constexpr int U_F32 = 8, D_F32 = 2;              // FP32 surrogate
 // With the overlapped residual the forward sweep advances at the rate the
 // residual kernel produces its input, and every register it holds is one the
-// residual kernel beside it cannot use: shallower operand batches.
+// residual kernel beside it cannot use: shallower operand batches.  The
+// residual's traffic also lengthens the exchange round trip, which a third
+// incoming wave hides for the FP32 sweep (level 9, 16 x 16: 1.414 vs 1.442 ms
+// per step; four waves leave the residual no room beside a full grid).
 constexpr int UO_F64 = 2, UO_S64 = 2, UO_F32 = 4;
+constexpr int DO_F32 = 3;
 
 template <int BV, int BW>
 struct Shape {
@@ -714,7 +718,7 @@ struct Shape {
     template <int NC, bool V1, bool OVL>
     static const void* fwd_ptr(int variant) {
         if (variant == 1) return (const void*)k_fwd_flow<double, false, V1, OVL, (OVL ? UO_S64 : U_S64), D_S64, NC, BV, BW>;
-        return (const void*)k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), D_F32, NC, BV, BW>;
+        return (const void*)k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), (OVL ? DO_F32 : D_F32), NC, BV, BW>;
     }
     template <int NC, bool V1>
     static const void* bwd_ptr(int variant) {
@@ -739,7 +743,8 @@ struct Shape {
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.v1f, c.v1f_stride,
                 (const double*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, f.rflag, f.nbands, (double*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
         else
-            k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
+            k_fwd_flow<float, false, V1, OVL, (OVL ? UO_F32 : U_F32), (OVL ? DO_F32 : D_F32), NC, BV, BW>
+                <<<f.grid, NT + ((OVL ? DO_F32 : D_F32) + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.v1f, c.v1f_stride,
                 (const float*)c.r, f.rt, c.A8, f.xo, f.bo, f.rspin, f.rflag, f.nbands, (float*)c.w, f.order_fwd, f.xch, f.ticket, f.flags);
     }
@@ -794,9 +799,11 @@ int resident(int variant, int NC, bool v1) {
 #undef ILU_PTRS
     }
     const int nthreads = BV * BW + (1 + (variant == 0 ? D_F64 : variant == 1 ? D_S64 : D_F32)) * WAVE;
+    // the overlapped FP32 forward sweep has one more incoming wave (not with V1, whose kernel is kf)
+    const int nthreads_o = variant == 2 && !v1 ? BV * BW + (1 + DO_F32) * WAVE : nthreads;
     int a = 0, b = 0, o = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, kf, nthreads, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, ko, nthreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, ko, nthreads_o, 0) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kb, nthreads, 0) != hipSuccess)
         return 1;
     return std::min(a, std::min(o, b));
