@@ -90,9 +90,12 @@ def test_refinement_with_overlap(torch, pkg):
     assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][1], out[2][1])
 
 
-def test_batch_modes_agree(torch, pkg):
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_batch_modes_agree(torch, pkg, tile):
+    # both block shapes of the LDS-staged residual: its tagged form walks the
+    # absolute bands of every tetrahedron of the batch
     tets = W.batch_tets(54, 12, (4, 5, 6))
-    sm = pkg.Smoother(tets, pkg.SURR_F32, degree=2, stride=4, tile=(8, 8))
+    sm = pkg.Smoother(tets, pkg.SURR_F32, degree=2, stride=4, tile=tile)
     b = torch.tensor(np.concatenate([t.rhs() for t in tets]), device="cuda")
     ref = _run(torch, sm, b, 4, pkg.OVERLAP_OFF, False)
     assert np.array_equal(_run(torch, sm, b, 4, pkg.OVERLAP_ON, True), ref)
