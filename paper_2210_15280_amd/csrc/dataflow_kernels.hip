@@ -696,6 +696,7 @@ namespace {
 constexpr int U_F64 = 3, U_F64B = 2, D_F64 = 2;  // stored factors
 constexpr int U_S64 = 4, D_S64 = 2;              // FP64 surrogate
 constexpr int U_F32 = 8, D_F32 = 2;              // FP32 surrogate
+constexpr int UB_F32 = 6;                        // FP32 backward (level 9, 16 x 16: 0.529 vs 0.537 ms with 8)
 // With the overlapped residual the forward sweep advances at the rate the
 // residual kernel produces its input, and every register it holds is one the
 // residual kernel beside it cannot use: shallower operand batches.  The
@@ -723,7 +724,7 @@ struct Shape {
     template <int NC, bool V1>
     static const void* bwd_ptr(int variant) {
         if (variant == 1) return (const void*)k_bwd_flow<double, false, V1, U_S64, D_S64, NC, BV, BW>;
-        return (const void*)k_bwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW>;
+        return (const void*)k_bwd_flow<float, false, V1, UB_F32, D_F32, NC, BV, BW>;
     }
     template <bool OVL>
     static void fwd_stored(const Ctx& c, const Flow& f, hipStream_t st) {
@@ -755,7 +756,7 @@ struct Shape {
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab64, (const double*)c.v1b, c.v1b_stride,
                 (const double*)c.w, x, f.order_bwd, f.xch, f.ticket, f.flags);
         else
-            k_bwd_flow<float, false, V1, U_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
+            k_bwd_flow<float, false, V1, UB_F32, D_F32, NC, BV, BW><<<f.grid, NT + (D_F32 + 1) * WAVE, 0, st>>>(
                 c.tets, c.blocks, c.lanes, c.nblocks, c.S, nullptr, c.tab32, (const float*)c.v1b, c.v1b_stride,
                 (const float*)c.w, x, f.order_bwd, f.xch, f.ticket, f.flags);
     }
