@@ -601,6 +601,36 @@ __global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __res
     const TetDev& T = tets[B.tet];
     const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
     const int64_t lexbase = only_tet >= 0 ? 0 : T.lex_off;
+    if (count == 1 && lmul == 1) {
+        // One vector: each wave takes PU consecutive hyperplanes at a time,
+        // all lanes the same ones (the stream side stays one contiguous line
+        // per hyperplane), and issues the PU loads before the PU stores, so a
+        // wave waits for one memory latency per PU points instead of per
+        // point.  Lane (v, w) holds the points x = t - 2v - w in [1, n-1-v];
+        // its lexicographic index is lrow + t.
+        constexpr int PU = 8;
+        const int lo = max(B.tb, 2 * v + w + 1), hi = min(B.te, n - 1 + v + w);
+        const int64_t lrow = lexbase + lex_index(n, 1, y, z) - 1 - (2 * v + w);
+        const int64_t srow = Ln.rp[R_SELF];
+        const int nw = (int)(blockDim.x >> 6);
+        for (int t0 = B.tb + (int)(threadIdx.x >> 6) * PU; t0 <= B.te; t0 += nw * PU) {
+            double val[PU];
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int t = t0 + u;
+                if (t >= lo && t <= hi) val[u] = mode == 0 ? src[srow + (int64_t)lpb * t] : src[lrow + t];
+            }
+#pragma unroll
+            for (int u = 0; u < PU; ++u) {
+                const int t = t0 + u;
+                if (t >= lo && t <= hi) {
+                    if (mode == 0) dst[lrow + t] = val[u];
+                    else dst[srow + (int64_t)lpb * t] = val[u];
+                }
+            }
+        }
+        return;
+    }
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;
         if (x < 1 || x > n - 1 - v) continue;
