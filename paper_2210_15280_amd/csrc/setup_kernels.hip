@@ -587,8 +587,98 @@ __global__ void k_build_v1b(const TetDev* __restrict__ tets, const BlockDev* __r
 
 // ------------------------------------------------------------ lex <-> stream
 
+// One vector, lexicographic <-> stream, through an LDS tile of PT_T
+// hyperplanes x the 64 rows of a workgroup (256 threads).  On the stream side
+// a wave moves one hyperplane of all 64 rows per access (one 512-byte run); on
+// the lexicographic side half a wave moves PT_T consecutive points of one row
+// (x = t - 2v - w, so row (v, w) is contiguous in t).  MODE 0: stream -> lex,
+// MODE 1: lex -> stream.
+constexpr int PT_T = 32;
+template <int MODE>
+__global__ __launch_bounds__(256) void k_permute_tile(const TetDev* __restrict__ tets,
+                                                      const BlockDev* __restrict__ blocks,
+                                                      const LaneDev* __restrict__ lanes, int lpb, int groups,
+                                                      const double* __restrict__ src, double* __restrict__ dst,
+                                                      int only_tet) {
+    __shared__ double tile[PT_T][WAVE + 1];
+    __shared__ int64_t s_lrow[WAVE], s_srow[WAVE];
+    __shared__ int s_lo[WAVE], s_hi[WAVE];
+    int b, lane;
+    decode_group(groups, b, lane);
+    const BlockDev B = blocks[b];
+    if (only_tet >= 0 && B.tet != only_tet) return;  // the whole workgroup
+    const int l = (int)(threadIdx.x & (WAVE - 1)), wv = (int)(threadIdx.x >> 6);
+    if (wv == 0) {
+        // row (v, w) holds x = t - 2v - w in [1, n-1-v]: t in [lo, hi], at
+        // lexicographic index lrow + t and stream index srow + lpb t
+        const LaneDev& Ln = lanes[(int64_t)b * lpb + lane];
+        int lo = 1, hi = 0;
+        int64_t lrow = 0, srow = 0;
+        if (Ln.v != 0) {
+            const TetDev& T = tets[B.tet];
+            const int n = T.n, v = Ln.v, w = Ln.w;
+            lo = max(B.tb, 2 * v + w + 1);
+            hi = min(B.te, n - 1 + v + w);
+            lrow = (only_tet >= 0 ? 0 : T.lex_off) + lex_index(n, 1, v - w, w) - 1 - (2 * v + w);
+            srow = Ln.rp[R_SELF];
+        }
+        s_lo[l] = lo;
+        s_hi[l] = hi;
+        s_lrow[l] = lrow;
+        s_srow[l] = srow;
+    }
+    __syncthreads();
+    // stream side: row l, hyperplanes wv + 4k of the tile
+    const int slo = s_lo[l], shi = s_hi[l];
+    const int64_t srow = s_srow[l];
+    // lexicographic side: rows r0 + 8k, hyperplane tx of the tile
+    constexpr int RK = WAVE / 8;
+    const int tx = (int)(threadIdx.x & (PT_T - 1)), r0 = (int)(threadIdx.x >> 5);
+    int llo[RK], lhi[RK];
+    int64_t lrow[RK];
+#pragma unroll
+    for (int k = 0; k < RK; ++k) {
+        llo[k] = s_lo[r0 + 8 * k];
+        lhi[k] = s_hi[r0 + 8 * k];
+        lrow[k] = s_lrow[r0 + 8 * k];
+    }
+    constexpr int SK = PT_T / 4;
+    for (int t0 = B.tb; t0 <= B.te; t0 += PT_T) {
+        static_assert(RK == 8 && SK == 8, "one register per access of either side");
+        double val[8];
+        if (MODE == 1) {
+            const int t = t0 + tx;
+#pragma unroll
+            for (int k = 0; k < RK; ++k) val[k] = t >= llo[k] && t <= lhi[k] ? src[lrow[k] + t] : 0.0;
+#pragma unroll
+            for (int k = 0; k < RK; ++k) tile[tx][r0 + 8 * k] = val[k];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < SK; ++k) {
+                const int t = t0 + wv + 4 * k;
+                if (t >= slo && t <= shi) dst[srow + (int64_t)lpb * t] = tile[wv + 4 * k][l];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < SK; ++k) {
+                const int t = t0 + wv + 4 * k;
+                val[k] = t >= slo && t <= shi ? src[srow + (int64_t)lpb * t] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < SK; ++k) tile[wv + 4 * k][l] = val[k];
+            __syncthreads();
+            const int t = t0 + tx;
+#pragma unroll
+            for (int k = 0; k < RK; ++k)
+                if (t >= llo[k] && t <= lhi[k]) dst[lrow[k] + t] = tile[tx][r0 + 8 * k];
+        }
+        __syncthreads();
+    }
+}
+
 // mode 0: stream -> lex (dst[lex] = src[stream]); mode 1: lex -> stream.
-// Stencil/factor exports use `count` arrays spaced `sstride` / `lstride` apart.
+// Stencil/factor exports use `count` arrays spaced `sstride` / `lstride` apart
+// (one vector goes through k_permute_tile).
 __global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __restrict__ blocks,
                           const LaneDev* __restrict__ lanes, int lpb, int groups, int mode, int count, const double* __restrict__ src,
                           double* __restrict__ dst, int64_t sstride, int lmul, int only_tet) {
@@ -601,36 +691,6 @@ __global__ void k_permute(const TetDev* __restrict__ tets, const BlockDev* __res
     const TetDev& T = tets[B.tet];
     const int n = T.n, v = Ln.v, w = Ln.w, y = v - w, z = w;
     const int64_t lexbase = only_tet >= 0 ? 0 : T.lex_off;
-    if (count == 1 && lmul == 1) {
-        // One vector: each wave takes PU consecutive hyperplanes at a time,
-        // all lanes the same ones (the stream side stays one contiguous line
-        // per hyperplane), and issues the PU loads before the PU stores, so a
-        // wave waits for one memory latency per PU points instead of per
-        // point.  Lane (v, w) holds the points x = t - 2v - w in [1, n-1-v];
-        // its lexicographic index is lrow + t.
-        constexpr int PU = 8;
-        const int lo = max(B.tb, 2 * v + w + 1), hi = min(B.te, n - 1 + v + w);
-        const int64_t lrow = lexbase + lex_index(n, 1, y, z) - 1 - (2 * v + w);
-        const int64_t srow = Ln.rp[R_SELF];
-        const int nw = (int)(blockDim.x >> 6);
-        for (int t0 = B.tb + (int)(threadIdx.x >> 6) * PU; t0 <= B.te; t0 += nw * PU) {
-            double val[PU];
-#pragma unroll
-            for (int u = 0; u < PU; ++u) {
-                const int t = t0 + u;
-                if (t >= lo && t <= hi) val[u] = mode == 0 ? src[srow + (int64_t)lpb * t] : src[lrow + t];
-            }
-#pragma unroll
-            for (int u = 0; u < PU; ++u) {
-                const int t = t0 + u;
-                if (t >= lo && t <= hi) {
-                    if (mode == 0) dst[lrow + t] = val[u];
-                    else dst[srow + (int64_t)lpb * t] = val[u];
-                }
-            }
-        }
-        return;
-    }
     for (int t = B.tb + (int)(threadIdx.x >> 6); t <= B.te; t += (int)(blockDim.x >> 6)) {
         const int x = t - 2 * v - w;
         if (x < 1 || x > n - 1 - v) continue;
@@ -696,6 +756,13 @@ void launch_build_v1b(const Ctx& c, const double* tab, const void* F, void* Bw, 
 
 void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,
                     int only_tet, hipStream_t st) {
+    if (count == 1 && lmul == 1) {
+        if (mode == 0)
+            k_permute_tile<0><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, src, dst, only_tet);
+        else
+            k_permute_tile<1><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, src, dst, only_tet);
+        return;
+    }
     k_permute<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, mode, count, src, dst, sstride, lmul, only_tet);
 }
 
