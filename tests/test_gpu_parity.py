@@ -572,6 +572,38 @@ def test_maximum_level_10(torch, pkg):
     assert 0.0 < rel5 < rel1 < 1.0
 
 
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32)])
+def test_layout_round_trip_is_exact(torch, pkg, tile):
+    # zero sweeps: x goes from the interface order into the stream layout and
+    # back, bit for bit, on a batch of lattices of levels 2, 5, 6 and 7 that
+    # share one stream (empty and partly filled rows, hyperplane ranges shorter
+    # and longer than one conversion tile); b goes in through the same
+    # conversion, and the residual of the start it gives matches the oracle
+    tets = [W.make_tet(71, 2, *W.KAPPA_SIN, jitter=0.1), W.make_tet(72, 5, *W.KAPPA_EXP, jitter=0.1),
+            W.make_tet(73, 6, *W.KAPPA_SIN, jitter=0.1), W.make_tet(74, 7, *W.KAPPA_EXP, jitter=0.1)]
+    sm = pkg.Smoother(tets, pkg.STORED_F64, tile=tile)
+    assert tuple(sm.tile) == tile
+    rng = np.random.default_rng(8)
+    x0 = rng.standard_normal(sum(sm.counts))
+    b = rng.uniform(-1, 1, len(x0))
+    x = torch.tensor(x0, device="cuda")
+    rel, ok = sm.smooth(x, torch.tensor(b, device="cuda"), 0, want_relres=True)
+    assert ok and np.array_equal(x.cpu().numpy(), x0)
+    r = np.concatenate([O.Problem.from_tet(t).apply(x0[o:o + n]) for t, o, n in zip(tets, sm.offsets, sm.counts)])
+    assert rel == pytest.approx(np.linalg.norm(b - r) / np.linalg.norm(b), rel=1e-12)
+
+
+def test_full_size_level9_layout_round_trip(torch, pkg):
+    # the benchmark workload at full size (22,108,415 points) on the block
+    # shape the benchmark runs: zero sweeps return x bit for bit
+    wl, t, _ = _l9_setup()
+    sm = pkg.Smoother([t], pkg.STORED_F64, tile=(16, 16))
+    x0 = torch.randn(sm.counts[0], dtype=torch.float64, generator=torch.Generator().manual_seed(9))
+    x = x0.to("cuda")
+    sm.smooth(x, torch.ones_like(x), 0)
+    assert torch.equal(x.cpu(), x0)
+
+
 def test_zero_sweeps_and_tiny_batch(torch, pkg):
     # nsweeps = 0 leaves x as it is and reports the residual of the start;
     # a batch of the smallest lattices (levels 2 and 3: 1 and 35 points) next
