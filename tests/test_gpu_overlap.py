@@ -138,3 +138,29 @@ def test_overlap_on_capped_grids(torch, pkg, variant, grid):
     sm.set_overlap(pkg.OVERLAP_OFF)
     rel0, ok0 = sm.smooth(torch.zeros_like(b), b, 16, rel_tol=1e-3)
     assert rel == rel0 and ok == ok0
+
+
+def test_full_size_level9_modes_agree_bitwise(torch, pkg):
+    # the benchmark's headline variant and workload at full size (level 9,
+    # 22,108,415 points, FP32 surrogate dg 6, 16x16 blocks, the full
+    # persistent grid): from a random start (so that the residual beside the
+    # forward sweep is not just b), three sweeps give bitwise the same iterate
+    # with the residual before, beside and inside the forward substitution,
+    # eagerly and as one captured graph
+    wl = W.workload("jit_L9_exp")
+    t = wl.tets[0]
+    sm = pkg.Smoother([t], pkg.SURR_F32, tile=(16, 16), degree=wl.degree, stride=wl.stride)
+    b = torch.tensor(t.rhs(), device="cuda")
+    x0 = torch.rand(b.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(10)).to("cuda") - 0.5
+
+    def run(mode, graph):
+        sm.set_overlap(mode)
+        sm.set_graph(graph)
+        x = x0.clone()
+        sm.smooth(x, b, 3)
+        return x
+
+    ref = run(pkg.OVERLAP_OFF, False)
+    assert not torch.equal(ref, x0)
+    for mode, graph in ((pkg.OVERLAP_ON, False), (pkg.OVERLAP_ON, True), (pkg.OVERLAP_FUSED, False)):
+        assert torch.equal(run(mode, graph), ref), (mode, graph)
