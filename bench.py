@@ -155,6 +155,7 @@ def run_variant(pkg, torch, wl, variant, steps, warmup, tile=(0, 0), overlap=Non
                loop_ms_per_step=loop_ms / steps, value=n * steps / (ms * 1e-3), relres_after=rel,
                kernel_ms=dict(forward=f_ms, backward=b_ms, residual=r_ms), tile=list(sm.tile),
                overlap=OVERLAP_NAMES[sm.overlap()], flow_grid=[grid, grid_max],
+               residual_chunk=sm.residual_chunk,
                contraction=dict(rho=rho, rho_res=rho_res, steps=CONTRACTION_STEPS))
     return out, sm
 
@@ -328,7 +329,7 @@ def extra_configs(pkg, torch, steps):
         h.close()
         torch.cuda.empty_cache()
         c4[v] = {k: r[k] for k in ("value", "ms_per_step", "setup_s", "kernel_ms", "tile", "relres_after", "n_dof",
-                                   "overlap", "flow_grid")}
+                                   "overlap", "flow_grid", "residual_chunk")}
         c4[v]["roofline"] = step_roofline(r, v, wlb)
         print("# %s %s: %.3e DOF-updates/s, %.4f ms/step" % (wlb.name, v, r["value"], r["ms_per_step"]),
               file=sys.stderr, flush=True)
@@ -535,7 +536,8 @@ def main():
                    "surrogate_degree": wl.degree, "sample_stride": wl.stride, "tile": hr["tile"],
                    "parallelism": "single GPU"},
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "loop_ms_per_step", "relres_after", "setup_s",
-                                            "kernel_ms", "tile", "overlap", "flow_grid")} for v, r in results.items()},
+                                            "kernel_ms", "tile", "overlap", "flow_grid", "residual_chunk")}
+                     for v, r in results.items()},
         "roofline": roofline(hr, head, wl.degree, wl.name),
         "step_roofline": step_roofline(hr, head, wl),
         "latency_floor": latency_floor(hr, head, wl),

@@ -112,8 +112,9 @@ typedef struct ilu_opts {
                                or (16,32).  (0,0) = autotuned: setup times a few sweeps
                                of every shape on the device (on zeroed buffers: the sweep
                                kernels' time does not depend on the values), each with
-                               several persistent-grid sizes (ilu_set_flow_grid) and both
-                               residual modes (ilu_set_overlap), keeps the fastest
+                               several persistent-grid sizes (ilu_set_flow_grid), both
+                               residual modes (ilu_set_overlap) and both chunk lengths of
+                               the residual run on its own (ilu_set_residual_chunk), keeps the fastest
                                combination and builds only that one (hyperplane schedule:
                                the shape is chosen from the levels) */
     int32_t a_mode;         /* ILU_A_EXACT or ILU_A_SURROGATE */
@@ -348,6 +349,16 @@ int ilu_get_overlap(ilu_handle_t h, int32_t *mode);
 int ilu_set_flow_grid(ilu_handle_t h, int32_t grid, int32_t *grid_out);
 /* The grid in use (*grid_out) and the default one (*grid_max_out, may be NULL). */
 int ilu_get_flow_grid(ilu_handle_t h, int32_t *grid_out, int32_t *grid_max_out);
+
+/* Hyperplanes per workgroup of the LDS-staged residual kernel when it runs on
+ * its own (8x8 and 16x16 blocks, ILU_OVERLAP_OFF; diagnostics, tests and the
+ * autotuner, which keeps the faster): 64 (default) or 128.  Longer chunks
+ * stage fewer ring prologues but give fewer workgroups.  r, the iterates and
+ * the layout of the norm's partial sums do not depend on it; the norm's
+ * summation order does (within rounding).  Any other value returns
+ * ILU_EINVAL.  Drops the captured graphs. */
+int ilu_set_residual_chunk(ilu_handle_t h, int32_t hyperplanes);
+int ilu_get_residual_chunk(ilu_handle_t h, int32_t *hyperplanes);
 
 /* Host-only self check (no device needed): builds the stream layout for the
  * given tetrahedra and replays every index the kernels form, counting

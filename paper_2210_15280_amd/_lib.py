@@ -83,6 +83,8 @@ def lib():
         L.ilu_set_graph.argtypes = [P, I32]
         L.ilu_set_overlap.argtypes = [P, I32]
         L.ilu_set_flow_grid.argtypes = [P, I32, ctypes.POINTER(I32)]
+        L.ilu_set_residual_chunk.argtypes = [P, I32]
+        L.ilu_get_residual_chunk.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_get_flow_grid.argtypes = [P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.ilu_get_overlap.argtypes = [P, ctypes.POINTER(I32)]
         L.ilu_check_layout.argtypes = [ctypes.POINTER(ilu_tet_desc), I32, ctypes.POINTER(ilu_opts),
@@ -331,6 +333,17 @@ class Smoother:
         g = ctypes.c_int32()
         _check(self.L.ilu_set_flow_grid(self.h, int(grid), ctypes.byref(g)), "ilu_set_flow_grid")
         return g.value
+
+    def set_residual_chunk(self, hyperplanes: int):
+        """Hyperplanes per workgroup of the residual run on its own: 64 or 128
+        (see ilu_set_residual_chunk)."""
+        _check(self.L.ilu_set_residual_chunk(self.h, int(hyperplanes)), "ilu_set_residual_chunk")
+
+    @property
+    def residual_chunk(self) -> int:
+        v = ctypes.c_int32()
+        _check(self.L.ilu_get_residual_chunk(self.h, ctypes.byref(v)), "ilu_get_residual_chunk")
+        return v.value
 
     @property
     def flow_grid(self):

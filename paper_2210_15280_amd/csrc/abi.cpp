@@ -126,6 +126,7 @@ struct ilu_handle_s {
     DevBuf order_fwd, order_bwd, xch, ticket;
     int64_t npartial = 0;      // partial sums of the residual kernel
     int64_t npartial_tag = 0;  // ... and of the tagged one (overlapped residual)
+    int res_lds_t = RES_T;     // hyperplanes per workgroup of the sequential LDS-staged residual
     int flow_grid = 0;
     int64_t setup_peak = 0, setup_resident = 0;  // library device bytes: peak during setup, held after it
     int flow_grid_max = 0;               // resident workgroups of the dataflow sweeps (the default grid)
@@ -174,6 +175,7 @@ struct ilu_handle_s {
         }
         c.res_chunks = (maxlen + RES_T - 1) / RES_T;
         c.res_bands = (tlast + 1 + RES_T - 1) / RES_T;
+        c.res_lds_t = res_lds_t;
         c.A8 = A8.as<double>();
         c.Lf = Lf.as<double>();
         c.Lb = Lb.as<double>();
@@ -818,12 +820,14 @@ int time_sweep(ilu_handle_t h, hipStream_t st, int reps, double* ms, double cuto
 // handle (layout and zeroed buffers: no assembly, factorisation or fit) times
 // a few sweeps with several persistent-grid sizes, in both residual modes
 // where the overlapped one is available (a latency-bound sweep on a capped
-// grid leaves room for the bandwidth-bound residual beside it); the fastest
+// grid leaves room for the bandwidth-bound residual beside it), and the
+// sequential LDS-staged residual with chunks of RES_T and 2 RES_T hyperplanes
+// (the longer ones pay on batches of small lattices); the fastest
 // combination is then set up in full, once.  Shapes whose sweep kernels would
 // spill registers are skipped.
 int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opts, hipStream_t st, ilu_handle_t* out) {
     static const int shapes[3][2] = {{8, 8}, {16, 16}, {16, 32}};
-    int best_sh = -1, best_grid = 0, best_ovl = ILU_OVERLAP_OFF;
+    int best_sh = -1, best_grid = 0, best_ovl = ILU_OVERLAP_OFF, best_rt = RES_T;
     double best_ms = 0.0;
     for (int si = 0; si < 3; ++si) {
         const int* sh = shapes[si];
@@ -835,20 +839,28 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
         if (!h) return ILU_ENOMEM;
         int rc = setup_impl(tets, ntets, &o, st, h, true);
         const int gmax = h->flow_grid_max;
-        struct Cand { int ovl, grid; };
-        Cand cands[6] = {{ILU_OVERLAP_OFF, gmax}, {ILU_OVERLAP_OFF, gmax / 2}, {ILU_OVERLAP_OFF, gmax / 3},
-                         {ILU_OVERLAP_ON, gmax}, {ILU_OVERLAP_ON, gmax / 2}, {ILU_OVERLAP_ON, gmax / 4}};
+        // rt: hyperplanes per workgroup of the sequential LDS-staged residual
+        // (longer chunks: fewer ring prologues, fewer workgroups)
+        struct Cand { int ovl, grid, rt; };
+        const Cand cands[8] = {{ILU_OVERLAP_OFF, gmax, RES_T},     {ILU_OVERLAP_OFF, gmax / 2, RES_T},
+                               {ILU_OVERLAP_OFF, gmax / 3, RES_T}, {ILU_OVERLAP_OFF, gmax, 2 * RES_T},
+                               {ILU_OVERLAP_OFF, gmax / 2, 2 * RES_T}, {ILU_OVERLAP_ON, gmax, RES_T},
+                               {ILU_OVERLAP_ON, gmax / 2, RES_T},  {ILU_OVERLAP_ON, gmax / 4, RES_T}};
+        const bool lds_shape = sh[0] == sh[1] && (sh[0] == 8 || sh[0] == 16);
         for (const Cand& cd : cands) {
             if (rc != ILU_OK) break;
             if (cd.grid < 1 || (cd.ovl != ILU_OVERLAP_OFF && !h->ovl_ok)) continue;
+            if (cd.rt != RES_T && !lds_shape) continue;
             h->flow_grid = cd.grid;
             h->ovl = cd.ovl;
+            h->res_lds_t = cd.rt;
             double ms = 0.0;
             rc = time_sweep(h, st, 3, &ms, best_sh < 0 ? 0.0 : 4.0 * best_ms);
             if (rc == ILU_OK && (best_sh < 0 || ms < best_ms)) {
                 best_sh = si;
                 best_grid = cd.grid;
                 best_ovl = cd.ovl;
+                best_rt = cd.rt;
                 best_ms = ms;
             }
         }
@@ -869,6 +881,7 @@ int setup_autotuned(const ilu_tet_desc* tets, int32_t ntets, const ilu_opts* opt
     }
     h->flow_grid = std::min(best_grid, h->flow_grid_max);
     h->ovl = h->ovl_ok ? best_ovl : ILU_OVERLAP_OFF;
+    h->res_lds_t = best_rt;
     h->tuned_ms = best_ms;
     *out = h;
     return ILU_OK;
@@ -915,10 +928,11 @@ int64_t check_residual_lds(ilu_handle_t h, const std::vector<int32_t>& owner) {
             else as[o.dst] = sr;
         }
         auto addr = [&](const Src& sr, int T) { return rl_active(sr.row, T) ? sr.rp + (int64_t)NT * T : 0; };
-        // the workgroups' hyperplane ranges: chunks of RES_T from the block's
-        // first hyperplane, and the absolute bands of the tagged mode
+        // the workgroups' hyperplane ranges: chunks of RES_T and of 2 RES_T from
+        // the block's first hyperplane, and the absolute bands of the tagged mode
         std::vector<std::pair<int, int>> ranges;
-        for (int t0 = B.tb; t0 <= B.te; t0 += RES_T) ranges.push_back({t0, std::min(B.te + 1, t0 + RES_T)});
+        for (int len = RES_T; len <= 2 * RES_T; len += RES_T)
+            for (int t0 = B.tb; t0 <= B.te; t0 += len) ranges.push_back({t0, std::min(B.te + 1, t0 + len)});
         for (int band = B.tb / RES_T; band * RES_T <= B.te; ++band)
             ranges.push_back({std::max(B.tb, band * RES_T), std::min(B.te + 1, (band + 1) * RES_T)});
         for (const auto& rg : ranges) {
@@ -2000,6 +2014,20 @@ int ilu_get_flow_grid(ilu_handle_t h, int32_t* grid_out, int32_t* grid_max_out) 
     if (!h || !grid_out) return ILU_EINVAL;
     *grid_out = h->flow_grid;
     if (grid_max_out) *grid_max_out = h->flow_grid_max;
+    return ILU_OK;
+}
+
+int ilu_set_residual_chunk(ilu_handle_t h, int32_t hyperplanes) {
+    if (!h || (hyperplanes != RES_T && hyperplanes != 2 * RES_T)) return ILU_EINVAL;
+    if (h->res_lds_t != hyperplanes)
+        if (int e = drop_graphs(h, nullptr)) return e;  // the captured residual launches have the old grid
+    h->res_lds_t = hyperplanes;
+    return ILU_OK;
+}
+
+int ilu_get_residual_chunk(ilu_handle_t h, int32_t* hyperplanes) {
+    if (!h || !hyperplanes) return ILU_EINVAL;
+    *hyperplanes = h->res_lds_t;
     return ILU_OK;
 }
 

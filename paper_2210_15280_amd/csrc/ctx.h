@@ -22,6 +22,7 @@ struct Ctx {
     int res_bands = 0;       // ceil((last hyperplane + 1) / RES_T): absolute hyperplane bands
     int64_t S = 0;           // stream length (elements)
     bool res_lds = true;     // exact-operator residual with LDS staging (8x8 and 16x16 blocks)
+    int res_lds_t = RES_T;   // hyperplanes per workgroup of that residual run on its own (RES_T or 2 RES_T)
     const double* A8 = nullptr;   // [8][S]: centre, then lower weights w..be
     const double* Lf = nullptr;   // [7][S] stored forward weights
     const double* Lb = nullptr;   // [8][S] stored backward weights (1/D, L^{p-d}_d)

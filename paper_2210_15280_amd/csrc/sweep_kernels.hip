@@ -108,7 +108,7 @@ __device__ __forceinline__ void store_dropped(double v, __amdgpu_buffer_rsrc_t r
 // The same r = b - A x as k_residual (the values and the order of the
 // products of residual_point), reading every value from memory once: the
 // workgroup owns one block of BV x BW rows (one thread per row) and walks
-// RES_T of its hyperplanes.  A point at t reads x at t - 3 .. t + 3 (LDS ring
+// tlen of its hyperplanes (RES_T or 2 RES_T, the handle's choice).  A point at t reads x at t - 3 .. t + 3 (LDS ring
 // of hyperplane slices: the block's rows and the one-row halo on all four
 // sides) and arrays 2..7 of the stencil at t .. t + 3 (LDS ring: the block's
 // rows and, at the upper halo rows, the upper weights the block's edge rows
@@ -136,7 +136,8 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
                                                          const double* __restrict__ x, const double* __restrict__ b,
                                                          RT* __restrict__ r, uint32_t rbytes,
                                                          uint64_t* __restrict__ rt, const int32_t* __restrict__ tagp,
-                                                         uint64_t* __restrict__ rflag, double* __restrict__ partial) {
+                                                         uint64_t* __restrict__ rflag, double* __restrict__ partial,
+                                                         int tlen, int pchunks) {
     using G = RlGeo<BV, BW>;
     constexpr int NT = G::NT, XC = G::XC, AC = G::AC, RX = G::RX, RA = G::RA, HJ = G::HJ;
     static_assert(RL_P == 4, "four register slice groups");
@@ -149,8 +150,8 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
     double acc2 = 0.0;
     const BlockDev& B = blocks[blk];
     const uint32_t tag = TAG ? (uint32_t)tagp[0] : 0u;
-    const int t0 = TAG ? max(B.tb, chunk * RES_T) : B.tb + chunk * RES_T;
-    const int t1 = min(B.te + 1, TAG ? (chunk + 1) * RES_T : t0 + RES_T);
+    const int t0 = TAG ? max(B.tb, chunk * RES_T) : B.tb + chunk * tlen;
+    const int t1 = min(B.te + 1, TAG ? (chunk + 1) * RES_T : t0 + tlen);
     if (t0 < t1) {
         const int64_t lpb = NT;
         const LaneDev& Ln = lanes[(int64_t)blk * NT + l];
@@ -305,9 +306,16 @@ __global__ void __launch_bounds__(BV* BW, 2) k_residual_lds(const TetDev* __rest
         if (l < o) red[l] += red[l + o];
         __syncthreads();
     }
-    // the partial-sum layout of k_residual: the block's first lane group holds
-    // the sum, its other groups 0
-    if (partial && l < groups) partial[((int64_t)chunk * nblocks + blk) * groups + l] = l == 0 ? red[0] : 0.0;
+    // the partial-sum layout of k_residual (pchunks chunks of RES_T
+    // hyperplanes): the block's first lane group holds the sum, its other
+    // groups 0; a chunk of tlen = k RES_T hyperplanes fills the slots of the k
+    // chunks it covers, its sum in the first
+    if (partial && l < groups) {
+        const int k = TAG ? 1 : tlen / RES_T, pc = chunk * k;
+        for (int j = 0; j < k; ++j)
+            if (TAG || pc + j < pchunks)
+                partial[((int64_t)(pc + j) * nblocks + blk) * groups + l] = l == 0 && j == 0 ? red[0] : 0.0;
+    }
 }
 
 // Residual for a forward sweep running at the same time: tagged entries
@@ -695,10 +703,12 @@ namespace {
 template <int BV, int BW>
 void launch_residual_lds(const Ctx& c, const double* x, const double* b, void* r, bool f32, int subtract,
                          double* partial, hipStream_t st) {
-    const dim3 grid((unsigned)c.nblocks, (unsigned)c.res_chunks);
+    // chunks of res_lds_t hyperplanes, k of the RES_T chunks of the partial sums
+    const int k = c.res_lds_t / RES_T;
+    const dim3 grid((unsigned)c.nblocks, (unsigned)((c.res_chunks + k - 1) / k));
     const uint32_t rb = (uint32_t)(c.S * (f32 ? 4 : 8));
 #define ILU_RL_ARGS c.tets, c.blocks, c.lanes, c.nblocks, c.groups, c.S, c.A8, x, b
-#define ILU_RL_NOTAG nullptr, nullptr, nullptr, partial
+#define ILU_RL_NOTAG nullptr, nullptr, nullptr, partial, c.res_lds_t, c.res_chunks
     if (f32 && subtract)
         k_residual_lds<float, true, BV, BW, false><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, (float*)r, rb, ILU_RL_NOTAG);
     else if (f32)
@@ -716,10 +726,10 @@ void launch_residual_lds_tagged(const Ctx& c, const double* x, const double* b, 
     const dim3 grid((unsigned)c.nblocks, (unsigned)c.res_bands);
     if (f32)
         k_residual_lds<float, true, BV, BW, true><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, nullptr, 0, rt, tagp, rflag,
-                                                                           partial);
+                                                                           partial, RES_T, c.res_bands);
     else
         k_residual_lds<double, true, BV, BW, true><<<grid, BV * BW, 0, st>>>(ILU_RL_ARGS, nullptr, 0, rt, tagp, rflag,
-                                                                            partial);
+                                                                            partial, RES_T, c.res_bands);
 #undef ILU_RL_ARGS
 }
 }  // namespace

@@ -77,6 +77,50 @@ def test_stencil_apply_parity_over_many_chunks(torch, pkg, tile):
     assert off == len(y)
 
 
+@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16)])
+def test_residual_chunk_lengths_agree(torch, pkg, tile, variant):
+    # the LDS-staged residual run on its own with chunks of 64 and of 128
+    # hyperplanes (one, two or three chunks per block on these lattices): A x
+    # against the oracle, three sweeps from a random start bitwise equal,
+    # eagerly and from the captured graph, and the norm of the start residual
+    # equal to rounding (its partial sums are added in another order)
+    tets = [W.make_tet(81, 7, *W.KAPPA_EXP, jitter=0.1), W.make_tet(82, 5, *W.KAPPA_SIN, jitter=0.1),
+            W.make_tet(83, 6, *W.KAPPA_EXP, jitter=0.1)]
+    Ps = [O.Problem.from_tet(t) for t in tets]
+    kw = {} if variant == 0 else dict(degree=3, stride=4)
+    sm = pkg.Smoother(tets, variant, tile=tile, **kw)
+    assert sm.residual_chunk == 64
+    with pytest.raises(pkg.ILUError):
+        sm.set_residual_chunk(96)
+    rng = np.random.default_rng(11)
+    xs = [rng.uniform(-1, 1, P.N) for P in Ps]
+    x0 = np.concatenate(xs)
+    b = torch.tensor(np.concatenate([t.rhs() for t in tets]), device="cuda")
+    out = {}
+    for chunk in (64, 128):
+        sm.set_residual_chunk(chunk)
+        assert sm.residual_chunk == chunk
+        y = sm.apply(torch.tensor(x0, device="cuda")).cpu().numpy()
+        off = 0
+        for P, x in zip(Ps, xs):
+            assert _rel(y[off:off + P.N], P.apply(x)) < 1e-13, chunk
+            off += P.N
+        its = []
+        for graph in (False, True):
+            sm.set_graph(graph)
+            x = torch.tensor(x0, device="cuda")
+            sm.smooth(x, b, 3)
+            its.append(x.cpu().numpy())
+        x = torch.tensor(x0, device="cuda")
+        rel, _ = sm.smooth(x, b, 0, want_relres=True)
+        out[chunk] = (y, its, rel)
+    assert np.array_equal(out[64][0], out[128][0])
+    for a in out[64][1] + out[128][1]:
+        assert np.array_equal(a, out[64][1][0])
+    assert out[128][2] == pytest.approx(out[64][2], rel=1e-13)
+
+
 @pytest.mark.parametrize("tile", [(8, 8), (16, 16), (16, 32)])
 @pytest.mark.parametrize("ti", range(5))
 def test_stored_factor_parity(torch, pkg, ti, tile):
