@@ -1559,8 +1559,7 @@ int ilu_smooth(ilu_handle_t h, double* x, const double* b, int32_t nsweeps, doub
     hipStream_t st = (hipStream_t)hip_stream;
     const Ctx c = h->ctx();
     const bool f32 = h->variant == ILU_SURR_F32;
-    launch_permute(c, 1, 1, x, h->xs.as<double>(), h->S, 1, -1, st);
-    launch_permute(c, 1, 1, b, h->bs.as<double>(), h->S, 1, -1, st);
+    launch_permute_in2(c, x, h->xs.as<double>(), b, h->bs.as<double>(), st);
     HIPCHK(hipGetLastError());
     const bool want_norm = rel_tol > 0.0 || relres_out;
     double bn = 1.0;
@@ -1699,8 +1698,7 @@ int ilu_pcg(ilu_handle_t h, double* x, const double* b, int32_t maxit, double re
     double* sc = h->cg_sc.as<double>();
     double* part = h->partial.as<double>();
     double *r = h->cg_r.as<double>(), *z = h->cg_z.as<double>(), *p = h->cg_p.as<double>();
-    launch_permute(c, 1, 1, x, h->xs.as<double>(), h->S, 1, -1, st);
-    launch_permute(c, 1, 1, b, h->bs.as<double>(), h->S, 1, -1, st);
+    launch_permute_in2(c, x, h->xs.as<double>(), b, h->bs.as<double>(), st);
     HIPCHK(hipMemsetAsync(p, 0, vb, st));
     HIPCHK(hipMemsetAsync(h->cg_q.p, 0, vb, st));
     launch_sumsq(c, h->bs.as<double>(), part, st);

@@ -38,6 +38,8 @@ void launch_build_v1b(const Ctx& c, const double* tab, const void* F, void* Bw, 
 // mode 0: stream -> lexicographic, mode 1: lexicographic -> stream
 void launch_permute(const Ctx& c, int mode, int count, const double* src, double* dst, int64_t sstride, int lmul,
                     int only_tet, hipStream_t st);
+// x and b (interface order, all tetrahedra) into the stream layout xs and bs, one launch
+void launch_permute_in2(const Ctx& c, const double* x, double* xs, const double* b, double* bs, hipStream_t st);
 
 
 }  // namespace ilu

@@ -587,20 +587,23 @@ __global__ void k_build_v1b(const TetDev* __restrict__ tets, const BlockDev* __r
 
 // ------------------------------------------------------------ lex <-> stream
 
-// One vector, lexicographic <-> stream, through an LDS tile of PT_T
-// hyperplanes x the 64 rows of a workgroup (256 threads).  On the stream side
-// a wave moves one hyperplane of all 64 rows per access (one 512-byte run); on
-// the lexicographic side half a wave moves PT_T consecutive points of one row
-// (x = t - 2v - w, so row (v, w) is contiguous in t).  MODE 0: stream -> lex,
-// MODE 1: lex -> stream.
+// NV vectors (1 or 2: x and b at once), lexicographic <-> stream, through an
+// LDS tile of PT_T hyperplanes x the 64 rows of a workgroup (256 threads) per
+// vector.  On the stream side a wave moves one hyperplane of all 64 rows per
+// access (one 512-byte run); on the lexicographic side half a wave moves PT_T
+// consecutive points of one row (x = t - 2v - w, so row (v, w) is contiguous
+// in t).  MODE 0: stream -> lex, MODE 1: lex -> stream.
 constexpr int PT_T = 32;
-template <int MODE>
+template <int MODE, int NV>
 __global__ __launch_bounds__(256) void k_permute_tile(const TetDev* __restrict__ tets,
                                                       const BlockDev* __restrict__ blocks,
                                                       const LaneDev* __restrict__ lanes, int lpb, int groups,
-                                                      const double* __restrict__ src, double* __restrict__ dst,
+                                                      const double* __restrict__ src0, double* __restrict__ dst0,
+                                                      const double* __restrict__ src1, double* __restrict__ dst1,
                                                       int only_tet) {
-    __shared__ double tile[PT_T][WAVE + 1];
+    __shared__ double tile[NV][PT_T][WAVE + 1];
+    const double* const src[2] = {src0, src1};
+    double* const dst[2] = {dst0, dst1};
     __shared__ int64_t s_lrow[WAVE], s_srow[WAVE];
     __shared__ int s_lo[WAVE], s_hi[WAVE];
     int b, lane;
@@ -645,32 +648,44 @@ __global__ __launch_bounds__(256) void k_permute_tile(const TetDev* __restrict__
     constexpr int SK = PT_T / 4;
     for (int t0 = B.tb; t0 <= B.te; t0 += PT_T) {
         static_assert(RK == 8 && SK == 8, "one register per access of either side");
-        double val[8];
+        double val[NV][8];
         if (MODE == 1) {
             const int t = t0 + tx;
 #pragma unroll
-            for (int k = 0; k < RK; ++k) val[k] = t >= llo[k] && t <= lhi[k] ? src[lrow[k] + t] : 0.0;
+            for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int k = 0; k < RK; ++k) tile[tx][r0 + 8 * k] = val[k];
+                for (int k = 0; k < RK; ++k) val[q][k] = t >= llo[k] && t <= lhi[k] ? src[q][lrow[k] + t] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int k = 0; k < RK; ++k) tile[q][tx][r0 + 8 * k] = val[q][k];
             __syncthreads();
 #pragma unroll
-            for (int k = 0; k < SK; ++k) {
-                const int t = t0 + wv + 4 * k;
-                if (t >= slo && t <= shi) dst[srow + (int64_t)lpb * t] = tile[wv + 4 * k][l];
-            }
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int k = 0; k < SK; ++k) {
+                    const int t = t0 + wv + 4 * k;
+                    if (t >= slo && t <= shi) dst[q][srow + (int64_t)lpb * t] = tile[q][wv + 4 * k][l];
+                }
         } else {
 #pragma unroll
-            for (int k = 0; k < SK; ++k) {
-                const int t = t0 + wv + 4 * k;
-                val[k] = t >= slo && t <= shi ? src[srow + (int64_t)lpb * t] : 0.0;
-            }
+            for (int q = 0; q < NV; ++q)
 #pragma unroll
-            for (int k = 0; k < SK; ++k) tile[wv + 4 * k][l] = val[k];
+                for (int k = 0; k < SK; ++k) {
+                    const int t = t0 + wv + 4 * k;
+                    val[q][k] = t >= slo && t <= shi ? src[q][srow + (int64_t)lpb * t] : 0.0;
+                }
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int k = 0; k < SK; ++k) tile[q][wv + 4 * k][l] = val[q][k];
             __syncthreads();
             const int t = t0 + tx;
 #pragma unroll
-            for (int k = 0; k < RK; ++k)
-                if (t >= llo[k] && t <= lhi[k]) dst[lrow[k] + t] = tile[tx][r0 + 8 * k];
+            for (int q = 0; q < NV; ++q)
+#pragma unroll
+                for (int k = 0; k < RK; ++k)
+                    if (t >= llo[k] && t <= lhi[k]) dst[q][lrow[k] + t] = tile[q][tx][r0 + 8 * k];
         }
         __syncthreads();
     }
@@ -758,12 +773,19 @@ void launch_permute(const Ctx& c, int mode, int count, const double* src, double
                     int only_tet, hipStream_t st) {
     if (count == 1 && lmul == 1) {
         if (mode == 0)
-            k_permute_tile<0><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, src, dst, only_tet);
+            k_permute_tile<0, 1><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, src,
+                                                                       dst, nullptr, nullptr, only_tet);
         else
-            k_permute_tile<1><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, src, dst, only_tet);
+            k_permute_tile<1, 1><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, src,
+                                                                       dst, nullptr, nullptr, only_tet);
         return;
     }
     k_permute<<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, mode, count, src, dst, sstride, lmul, only_tet);
+}
+
+void launch_permute_in2(const Ctx& c, const double* x, double* xs, const double* b, double* bs, hipStream_t st) {
+    k_permute_tile<1, 2><<<c.nblocks * c.groups, 256, 0, st>>>(c.tets, c.blocks, c.lanes, c.lpb, c.groups, x, xs, b, bs,
+                                                               -1);
 }
 
 
